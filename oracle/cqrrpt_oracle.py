@@ -1,0 +1,432 @@
+"""CQRRPT oracle: a plain, slow, FP64 CPU implementation of the method.
+
+THIS MODULE IS TEST INFRASTRUCTURE. Only the test suite, the package's smoke
+check and the benchmark's CPU-baseline leg may import or call it. The product
+path (the HIP library behind ``include/cqrrpt.h`` and its Python binding) never
+imports, links or executes anything here, and nothing here imports the product.
+
+Paper: Melnichenko, Balabanov, Murray, Demmel, Mahoney, Luszczek,
+"CholeskyQR with Randomization and Pivoting for Tall Matrices (CQRRPT)",
+arXiv:2311.08316.
+
+What is computed, step by step, in the paper's order (Algorithm 2,
+``cqrrpt_core``, with the sketching operator drawn as in Algorithm 1):
+
+  S1  sample a SASO S (d x m): every column has exactly ``nnz`` nonzeros at
+      distinct rows chosen uniformly, with values +-1/sqrt(nnz)   (Sec. 2.3.1)
+  S2  sketch  Ahat = S A                                          (Alg. 2, sketch)
+  S3  Householder QR with max-norm column pivoting of Ahat -> J, R_sk
+                                                                  (Alg. 2, qrcp;
+      Sec. 1 and 5 name LAPACK GEQP3, i.e. Businger-Golub pivoting)
+  S4  first-stage rank bound k_o                                  (Sec. 3.3, first stage)
+  S5  M_pre = A[:, J[:k_o]] R_sk[:k_o, :k_o]^{-1}                  (Alg. 2, precondition)
+  S6  G = M_pre^T M_pre                                           (Alg. 2, Gram)
+  S7  R_pre = chol(G), truncating at the first failing pivot      (Alg. 2; Remark in
+                                                                   Sec. 3.3 on Cholesky
+                                                                   failure)
+  S8  second-stage rank k from cond(diag(R_pre[:l, :l])) <= sqrt(eps_tol/u),
+      eps_tol = 100 u, so the threshold is 10                     (Sec. 3.3, second stage)
+  S9  Q = M_pre[:, :k] R_pre[:k, :k]^{-1}                          (Alg. 2, Q-factor)
+  S10 R = R_pre[:k, :k] R_sk[:k, :]                                (Alg. 2, undo preconditioning)
+
+Readings where the paper is silent (each is listed in the design doc as well):
+  * random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the seed,
+    one counter stream per column of S; Floyd's subset sampler (Bentley and
+    Floyd, CACM 1987) for the distinct rows; Lemire's multiply-shift with
+    rejection (ACM TOMACS 2019) for exact uniform integers.
+  * the 1/sqrt(nnz) scale is applied once to the accumulated signed sum.
+  * pivot ties go to the smallest original column index; column norms are
+    recomputed from scratch at every step (no downdating).
+  * Householder reflector in the LAPACK convention beta = -sign(alpha)||x||
+    (sign(0) = +1); rows of R_sk with a negative diagonal are negated at the
+    end, so diag(R_sk) >= 0 and Q, R are unique.
+  * stage 1 uses ``tol`` in place of the unit roundoff u, compares squared
+    Frobenius norms, and s is the largest |entry| of R_sk.
+  * a Cholesky pivot that is <= 0 or not finite at 0-based column j sets k = j.
+  * outputs are full-size: Q is m x n and R is n x n, zero past the rank.
+
+Dense steps use library primitives (matrix product, triangular solve) as the
+paper's own implementation does (BLAS TRSM/SYRK, Sec. 1.2 and App. A.1).
+"""
+
+import math
+
+import numpy as np
+import scipy.linalg
+import scipy.sparse
+
+# ---------------------------------------------------------------------------
+# S1. Random numbers and the SASO sampler
+# ---------------------------------------------------------------------------
+
+_MASK32 = np.uint64(0xFFFFFFFF)
+# Philox4x32 multipliers and Weyl key increments, from the published
+# definition (Salmon, Moraes, Dror, Shaw, SC'11, Sec. 4 "Philox").
+PHILOX_M0 = 0xD2511F53
+PHILOX_M1 = 0xCD9E8D57
+PHILOX_W0 = 0x9E3779B9
+PHILOX_W1 = 0xBB67AE85
+# Fourth counter word of every SASO draw: ASCII "SAS0". Separates these
+# streams from any other use of the same key.
+SASO_DOMAIN = 0x53415330
+
+
+def philox4x32_10(c0, c1, c2, c3, k0, k1):
+    """Philox4x32 with 10 rounds, vectorised over numpy arrays of uint32 words.
+
+    One round maps (c0, c1, c2, c3) with key (k0, k1) to
+      (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1, lo(M0*c0));
+    the key is bumped by the Weyl constants (W0, W1) between rounds.
+    """
+    c0, c1, c2, c3, k0, k1 = (np.asarray(x, dtype=np.uint64) & _MASK32
+                              for x in (c0, c1, c2, c3, k0, k1))
+    c0, c1, c2, c3, k0, k1 = np.broadcast_arrays(c0, c1, c2, c3, k0, k1)
+    for rnd in range(10):
+        if rnd > 0:
+            k0 = (k0 + np.uint64(PHILOX_W0)) & _MASK32
+            k1 = (k1 + np.uint64(PHILOX_W1)) & _MASK32
+        p0 = np.uint64(PHILOX_M0) * c0
+        p1 = np.uint64(PHILOX_M1) * c2
+        hi0, lo0 = p0 >> np.uint64(32), p0 & _MASK32
+        hi1, lo1 = p1 >> np.uint64(32), p1 & _MASK32
+        c0, c1, c2, c3 = hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0
+    return (c0.astype(np.uint32), c1.astype(np.uint32),
+            c2.astype(np.uint32), c3.astype(np.uint32))
+
+
+class _ColumnWordStream:
+    """The stream of 32-bit words that column j of S consumes, for many j at once.
+
+    Word w of column j is word (w mod 4) of Philox4x32-10 applied to the
+    counter (lo32(j), hi32(j), w div 4, SASO_DOMAIN) under the key
+    (lo32(seed), hi32(seed)).
+    """
+
+    def __init__(self, seed, cols):
+        self.cols = np.asarray(cols, dtype=np.uint64)
+        self.k0 = seed & 0xFFFFFFFF
+        self.k1 = (seed >> 32) & 0xFFFFFFFF
+        self._cache = {}
+
+    def block(self, b):
+        if b not in self._cache:
+            lo = self.cols & _MASK32
+            hi = self.cols >> np.uint64(32)
+            self._cache[b] = philox4x32_10(lo, hi, b, SASO_DOMAIN, self.k0, self.k1)
+        return self._cache[b]
+
+    def word(self, w):
+        """Word index ``w`` (array, one entry per column) of every column."""
+        w = np.asarray(w, dtype=np.int64)
+        w = np.broadcast_to(w, self.cols.shape)
+        out = np.empty(self.cols.shape, dtype=np.uint32)
+        for b in np.unique(w // 4):
+            sel = (w // 4) == b
+            words = self.block(int(b))
+            for lane in range(4):
+                s2 = sel & ((w % 4) == lane)
+                out[s2] = words[lane][s2]
+        return out
+
+
+def lemire_uniform(stream, pos, s):
+    """Exact uniform integers in [0, s) by Lemire's multiply-shift with rejection.
+
+    ``pos`` is the per-column index of the next unused word; it is advanced in
+    place. Draw x, form the 64-bit product x*s, and accept the high word unless
+    the low word falls below (2^32 - s) mod s, in which case draw again.
+    """
+    s = np.asarray(s, dtype=np.uint64)
+    x = stream.word(pos).astype(np.uint64)
+    pos += 1
+    prod = x * s
+    low = prod & _MASK32
+    thresh = (np.uint64(1 << 32) - s) % s
+    reject = low < thresh
+    while np.any(reject):
+        idx = np.flatnonzero(reject)
+        x2 = stream.word(pos)[idx].astype(np.uint64)
+        pos[idx] += 1
+        prod[idx] = x2 * s[idx] if s.ndim else x2 * s
+        low[idx] = prod[idx] & _MASK32
+        reject = low < thresh
+    return (prod >> np.uint64(32)).astype(np.int64)
+
+
+def floyd_sample(d, nnz, uniform):
+    """Floyd's algorithm: ``nnz`` distinct integers from [0, d), in draw order.
+
+    ``uniform(t)`` must return an exact uniform integer in [0, t]
+    (vectorised: one value per independent instance). For t = d-nnz, ..., d-1
+    a draw r in [0, t] is kept unless it was already taken, in which case t
+    itself is taken instead.
+    """
+    picks = []
+    for step in range(nnz):
+        t = d - nnz + step
+        r = uniform(t)
+        taken = np.zeros(r.shape, dtype=bool)
+        for prev in picks:
+            taken |= prev == r
+        picks.append(np.where(taken, t, r))
+    return np.stack(picks, axis=-1) if picks else np.zeros((0,), dtype=np.int64)
+
+
+def saso_sample(m, d, nnz, seed):
+    """The SASO of Sec. 2.3.1 as (rows, signs): column j of S holds +-1/sqrt(nnz)
+    at rows[j, t] with sign signs[j, t], t < nnz; the rows of a column are
+    distinct. Word 0 of column j's stream gives the signs (bit t set means the
+    t-th entry is negative); words 1, 2, ... feed Floyd's sampler.
+    """
+    if not (1 <= nnz <= 32 and nnz <= d):
+        raise ValueError("need 1 <= nnz <= min(32, d)")
+    cols = np.arange(m, dtype=np.uint64)
+    stream = _ColumnWordStream(seed, cols)
+    sign_word = stream.word(np.zeros(m, dtype=np.int64)).astype(np.int64)
+    signs = np.empty((m, nnz), dtype=np.int8)
+    for t in range(nnz):
+        signs[:, t] = np.where((sign_word >> t) & 1, -1, 1)
+    pos = np.ones(m, dtype=np.int64)
+    rows = floyd_sample(d, nnz, lambda t: lemire_uniform(stream, pos, t + 1))
+    return rows.astype(np.int64).reshape(m, nnz), signs
+
+
+def saso_matrix(m, d, nnz, seed):
+    """S as a scipy sparse d x m matrix with entries +-1/sqrt(nnz)."""
+    rows, signs = saso_sample(m, d, nnz, seed)
+    cols = np.repeat(np.arange(m), nnz)
+    vals = signs.reshape(-1).astype(np.float64) * (1.0 / math.sqrt(nnz))
+    return scipy.sparse.csr_matrix((vals, (rows.reshape(-1), cols)), shape=(d, m))
+
+
+# ---------------------------------------------------------------------------
+# S2. The sketch
+# ---------------------------------------------------------------------------
+
+def sketch(A, rows, signs, d):
+    """Ahat = S A for the SASO given by (rows, signs), in FP64 (Alg. 2, sketch).
+
+    The signed sum sum_j sign * A[j, :] is accumulated first and scaled by
+    1/sqrt(nnz) once at the end.
+    """
+    m, nnz = rows.shape
+    cols = np.repeat(np.arange(m), nnz)
+    S_pm1 = scipy.sparse.csr_matrix(
+        (signs.reshape(-1).astype(np.float64), (rows.reshape(-1), cols)), shape=(d, m))
+    return np.asarray(S_pm1 @ np.asarray(A, dtype=np.float64)) * (1.0 / math.sqrt(nnz))
+
+
+# ---------------------------------------------------------------------------
+# S3. QR with column pivoting of the sketch
+# ---------------------------------------------------------------------------
+
+def qrcp(X, return_reflectors=False):
+    """Householder QR with max-norm (Businger-Golub) column pivoting.
+
+    Returns (J, R): J is the 0-based pivot order (Alg. 2 returns it in full)
+    and R is n x n upper triangular with a non-negative diagonal, so that
+    X[:, J] = Q R with Q orthonormal (d x n). At step i every remaining
+    column's norm ||X[i:, c]|| is recomputed; the largest wins, ties going to
+    the smallest original column index.
+    """
+    X = np.array(X, dtype=np.float64, copy=True)
+    d, n = X.shape
+    if d < n:
+        raise ValueError("qrcp expects at least as many rows as columns")
+    J = np.arange(n)
+    betas = np.zeros(n)
+    refl = []
+    for i in range(n):
+        nu = np.sqrt(np.sum(X[i:, i:] ** 2, axis=0))
+        top = nu.max()
+        cand = np.flatnonzero(nu == top)
+        p = i + cand[np.argmin(J[i + cand])]
+        if p != i:
+            X[:, [i, p]] = X[:, [p, i]]
+            J[[i, p]] = J[[p, i]]
+        x = X[i:, i].copy()
+        alpha, normx = x[0], nu[p - i]
+        if normx == 0.0:
+            tau, beta, v = 0.0, 0.0, np.zeros_like(x)
+        else:
+            beta = -normx if alpha >= 0.0 else normx
+            v = x / (alpha - beta)
+            v[0] = 1.0
+            tau = (beta - alpha) / beta
+            w = v @ X[i:, i + 1:]
+            X[i:, i + 1:] -= tau * np.outer(v, w)
+        betas[i] = beta
+        X[i, i] = beta
+        X[i + 1:, i] = 0.0
+        refl.append((v, tau))
+    R = np.triu(X[:n, :n])
+    flip = np.diag(R) < 0.0
+    R[flip, :] = -R[flip, :]
+    if return_reflectors:
+        return J, R, refl, flip
+    return J, R
+
+
+def qrcp_q_factor(refl, flip, d):
+    """Explicit d x n Q of ``qrcp`` from its reflectors (for invariant checks)."""
+    n = len(refl)
+    Q = np.eye(d, n)
+    for i in range(n - 1, -1, -1):
+        v, tau = refl[i]
+        if tau != 0.0:
+            Q[i:, :] -= tau * np.outer(v, v @ Q[i:, :])
+    Q[:, flip] = -Q[:, flip]
+    return Q
+
+
+# ---------------------------------------------------------------------------
+# S4 / S8. Numerical rank (Sec. 3.3)
+# ---------------------------------------------------------------------------
+
+def rank_stage1(R, tol):
+    """k_o = min{ l : ||R[l:, l:]||_F <= tol * s }, s = max |R| (first stage).
+
+    Compared in squared form; the trailing block norms are accumulated as
+    suffix sums of squared row norms from the last row upward.
+    """
+    n = R.shape[1]
+    Rt = np.triu(R[:n, :n])
+    s = np.max(np.abs(Rt)) if Rt.size else 0.0
+    if s == 0.0:
+        return 0
+    rn2 = np.sum(Rt ** 2, axis=1)
+    thr = (tol * s) ** 2
+    suf = 0.0
+    k_o = n
+    for l in range(n - 1, -1, -1):
+        suf = suf + rn2[l]
+        if suf <= thr:
+            k_o = l
+        else:
+            break
+    return k_o
+
+
+def rank_stage2(Rpre, cond_max=10.0):
+    """k = max{ l : max|diag R_pre[:l,:l]| / min|diag R_pre[:l,:l]| <= cond_max }.
+
+    cond(diag(.)) is the paper's preferred estimator; it is non-decreasing in
+    l, so the scan stops at the first violation.
+    """
+    dg = np.abs(np.diag(Rpre))
+    k = 0
+    dmax, dmin = 0.0, math.inf
+    for l in range(1, len(dg) + 1):
+        dmax = max(dmax, dg[l - 1])
+        dmin = min(dmin, dg[l - 1])
+        if dmax / dmin <= cond_max:
+            k = l
+        else:
+            break
+    return k
+
+
+# ---------------------------------------------------------------------------
+# S7. Cholesky with the failure index
+# ---------------------------------------------------------------------------
+
+def cholesky_upper(G):
+    """Upper Cholesky R^T R = G, row by row. Returns (R, k): if the pivot of
+    0-based row j is <= 0 or not finite, the factor stops there and k = j
+    (the leading j x j block is exact: Remark on Cholesky failure, Sec. 3.3).
+    """
+    n = G.shape[0]
+    R = np.zeros((n, n))
+    for j in range(n):
+        piv = G[j, j] - R[:j, j] @ R[:j, j]
+        if not (piv > 0.0) or not math.isfinite(piv):
+            return R[:j, :j].copy(), j
+        r = math.sqrt(piv)
+        R[j, j] = r
+        R[j, j + 1:] = (G[j, j + 1:] - R[:j, j] @ R[:j, j + 1:]) / r
+    return R, n
+
+
+# ---------------------------------------------------------------------------
+# The whole path
+# ---------------------------------------------------------------------------
+
+STATUS_OK = 0
+STATUS_NONFINITE = 1
+
+
+def cqrrpt_core(A, S, tol, cond_max=10.0):
+    """Algorithm 2 with an explicit sketching operator S (dense or sparse d x m).
+
+    Returns dict(Q, R, J, rank, rank_stage1, chol_fail_col, status, Ahat, Rsk).
+    Q is m x n and R is n x n, both zero past the rank.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    Ahat = np.asarray(S @ A, dtype=np.float64)
+    return _core_from_sketch(A, Ahat, tol, cond_max)
+
+
+def _core_from_sketch(A, Ahat, tol, cond_max):
+    m, n = A.shape
+    out = dict(Q=np.zeros((m, n)), R=np.zeros((n, n)), J=np.arange(n), rank=0,
+               rank_stage1=0, chol_fail_col=-1, status=STATUS_OK, Ahat=Ahat, Rsk=None)
+    if not np.all(np.isfinite(Ahat)):
+        out["status"] = STATUS_NONFINITE
+        return out
+    J, Rsk = qrcp(Ahat)
+    out["J"], out["Rsk"] = J, Rsk
+    k_o = rank_stage1(Rsk, tol)
+    out["rank_stage1"] = k_o
+    if k_o == 0:
+        return out
+    # S5: M_pre R_sk[:k_o,:k_o] = A[:, J[:k_o]]  (right solve with an upper factor)
+    Mpre = scipy.linalg.solve_triangular(Rsk[:k_o, :k_o], A[:, J[:k_o]].T,
+                                         trans="T", lower=False).T
+    G = Mpre.T @ Mpre                                   # S6
+    Rpre, k_chol = cholesky_upper(G)                    # S7
+    if k_chol < k_o:
+        out["chol_fail_col"] = k_chol
+    k = rank_stage2(Rpre, cond_max) if k_chol > 0 else 0   # S8
+    out["rank"] = k
+    if k == 0:
+        return out
+    Rp = Rpre[:k, :k]
+    Q = scipy.linalg.solve_triangular(Rp, Mpre[:, :k].T, trans="T", lower=False).T  # S9
+    out["Q"][:, :k] = Q
+    out["R"][:k, :] = Rp @ Rsk[:k, :]                   # S10
+    out["Rpre"] = Rp
+    out["Mpre"] = Mpre
+    return out
+
+
+def cqrrpt(A, d, nnz, seed, tol, cond_max=10.0):
+    """Algorithm 1 with a SASO of ``nnz`` nonzeros per column and d rows."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    if not (1 <= n <= m and n <= d <= m):
+        raise ValueError("need 1 <= n <= d <= m")
+    rows, signs = saso_sample(m, d, nnz, seed)
+    Ahat = sketch(A, rows, signs, d)
+    return _core_from_sketch(A, Ahat, tol, cond_max)
+
+
+def factor_given_pivots(A, J, k):
+    """The plain definition the path must reach when rank(S A) = rank(A) = k
+    (Theorem on correctness, Sec. 2.1): with pivots J fixed, (Q_k, R_k[:, :k])
+    is the thin QR of A[:, J[:k]] with a positive diagonal, and
+    R_k[:, k:] = Q_k^T A[:, J[k:]]. Computed here through an unpivoted
+    Householder QR (a library primitive) for cross-checks.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    Ak = A[:, J[:k]]
+    Qk, Rk = np.linalg.qr(Ak)
+    sgn = np.where(np.diag(Rk) < 0.0, -1.0, 1.0)
+    Qk = Qk * sgn
+    Rk = Rk * sgn[:, None]
+    R = np.zeros((n, n))
+    R[:k, :k] = Rk
+    R[:k, k:] = Qk.T @ A[:, J[k:]]
+    Q = np.zeros((m, n))
+    Q[:, :k] = Qk
+    return Q, R

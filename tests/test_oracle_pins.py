@@ -1,0 +1,460 @@
+"""Pins for the CPU oracle: each check ties the oracle to something other than
+itself (published test vectors, exhaustive enumeration, a brute-force textbook
+algorithm, closed forms, invariants, or special cases that reduce to a library
+routine), chosen so that a dropped term, wrong sign, wrong index or transposed
+operand in the oracle fails at least one of them."""
+
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import cqrrpt_oracle as O
+from paper_2311_08316_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# Random numbers
+# ---------------------------------------------------------------------------
+
+def _kat_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            rows.append([int(x, 16) for x in line.split()])
+    return rows
+
+
+def test_philox_known_answers():
+    rows = _kat_rows()
+    assert len(rows) == 3
+    for r in rows:
+        out = O.philox4x32_10(*r[:6])
+        assert [int(x) for x in out] == r[6:]
+
+
+def test_philox_vectorised_matches_scalar():
+    c0 = np.arange(50, dtype=np.uint64) * 977
+    out = O.philox4x32_10(c0, 3, 5, 7, 11, 13)
+    for i in (0, 17, 49):
+        one = O.philox4x32_10(int(c0[i]), 3, 5, 7, 11, 13)
+        assert [int(x[i]) for x in out] == [int(x) for x in one]
+
+
+class _FixedWords:
+    """A word source returning given words in order (same for every column)."""
+
+    def __init__(self, words):
+        self.words = list(words)
+
+    def word(self, pos):
+        pos = np.asarray(pos)
+        return np.array([self.words[int(p)] for p in pos.reshape(-1)],
+                        dtype=np.uint32).reshape(pos.shape)
+
+
+def test_lemire_power_of_two_is_a_shift():
+    words = [0xDEADBEEF, 0x12345678, 0xFFFFFFFF, 0]
+    for p in (1, 5, 16, 31):
+        for x in words:
+            pos = np.zeros(1, dtype=np.int64)
+            v = O.lemire_uniform(_FixedWords([x]), pos, 1 << p)
+            assert int(v[0]) == x >> (32 - p)
+            assert int(pos[0]) == 1
+
+
+def test_lemire_rejection_rate_and_range():
+    # s = 3 * 2^30: the low word of x*s is a multiple of 2^30 and the
+    # threshold (2^32 - s) mod s equals 2^30, so exactly the x with
+    # x*3 = 0 mod 4 (one in four) are rejected: 4/3 words per draw on average.
+    s = 3 << 30
+    rng = np.random.Generator(np.random.PCG64(1))
+    words = rng.integers(0, 1 << 32, size=40000, dtype=np.uint64).astype(np.uint32)
+    src = _FixedWords(words)
+    pos = np.zeros(1, dtype=np.int64)
+    vals = []
+    while pos[0] < len(words) - 64:
+        vals.append(int(O.lemire_uniform(src, pos, s)[0]))
+    vals = np.array(vals)
+    assert vals.min() >= 0 and vals.max() < s
+    rate = pos[0] / len(vals)
+    assert abs(rate - 4.0 / 3.0) < 0.03
+    # rejected words are exactly those with x % 4 == 0
+    accepted = words[words % 4 != 0][: len(vals)]
+    assert np.array_equal(vals, (accepted.astype(np.uint64) * np.uint64(s)) >> np.uint64(32))
+
+
+def test_lemire_small_ranges_are_uniform():
+    rng = np.random.Generator(np.random.PCG64(2))
+    words = rng.integers(0, 1 << 32, size=60000, dtype=np.uint64).astype(np.uint32)
+    for s in (2, 3, 7, 10):
+        src = _FixedWords(words)
+        pos = np.zeros(1, dtype=np.int64)
+        vals = np.array([int(O.lemire_uniform(src, pos, s)[0]) for _ in range(6000)])
+        counts = np.bincount(vals, minlength=s)
+        assert len(counts) == s
+        exp = len(vals) / s
+        chi2 = np.sum((counts - exp) ** 2 / exp)
+        assert chi2 < 3.0 * s + 30
+
+
+@pytest.mark.parametrize("d,nnz", [(5, 1), (5, 2), (6, 3), (7, 4), (4, 4), (8, 3)])
+def test_floyd_exhaustive_uniform_subsets(d, nnz):
+    # Enumerate every tuple of draws r_t in [0, d-nnz+t]; each nnz-subset of
+    # [0, d) must come out exactly nnz! times, with distinct entries.
+    ranges = [range(d - nnz + t + 1) for t in range(nnz)]
+    tuples = np.array(list(itertools.product(*ranges)), dtype=np.int64)
+
+    def uniform(t):
+        return tuples[:, t - (d - nnz)]
+
+    picks = O.floyd_sample(d, nnz, uniform)
+    counts = {}
+    for row in picks:
+        assert len(set(row.tolist())) == nnz
+        assert row.min() >= 0 and row.max() < d
+        key = tuple(sorted(row.tolist()))
+        counts[key] = counts.get(key, 0) + 1
+    assert len(counts) == math.comb(d, nnz)
+    assert set(counts.values()) == {math.factorial(nnz)}
+
+
+# ---------------------------------------------------------------------------
+# The SASO (Sec. 2.3.1)
+# ---------------------------------------------------------------------------
+
+def test_saso_structure():
+    m, d, nnz = 3000, 64, 8
+    rows, signs = O.saso_sample(m, d, nnz, seed=123)
+    assert rows.shape == (m, nnz) and signs.shape == (m, nnz)
+    assert rows.min() >= 0 and rows.max() < d
+    for j in range(m):
+        assert len(set(rows[j].tolist())) == nnz
+    assert set(np.unique(signs).tolist()) == {-1, 1}
+    # every column of S has unit norm, so ||S||_F^2 = m
+    S = O.saso_matrix(m, d, nnz, 123)
+    col_norm2 = np.asarray(S.multiply(S).sum(axis=0)).ravel()
+    assert np.allclose(col_norm2, 1.0, rtol=0, atol=1e-15)
+    # sign balance (binomial, n = m*nnz)
+    npos = np.sum(signs > 0)
+    assert abs(npos - m * nnz / 2) < 5 * math.sqrt(m * nnz / 4)
+    # row occupancy is uniform (chi-square, d-1 dof)
+    occ = np.bincount(rows.ravel(), minlength=d)
+    exp = m * nnz / d
+    chi2 = np.sum((occ - exp) ** 2 / exp)
+    assert chi2 < d + 6 * math.sqrt(2 * d)
+
+
+def test_saso_counter_streams():
+    # Column j's draws depend only on (seed, j): a shorter operator is a prefix.
+    r1, s1 = O.saso_sample(500, 40, 4, seed=9)
+    r2, s2 = O.saso_sample(200, 40, 4, seed=9)
+    assert np.array_equal(r1[:200], r2) and np.array_equal(s1[:200], s2)
+    r3, _ = O.saso_sample(200, 40, 4, seed=10)
+    assert not np.array_equal(r2, r3)
+    # seeds above 2^32 use the high key word
+    r4, _ = O.saso_sample(200, 40, 4, seed=9 + (1 << 32))
+    assert not np.array_equal(r2, r4)
+
+
+def test_saso_isotropy_monte_carlo():
+    # E[S^T S] = I (Sec. 2.3.1): the diagonal is exactly 1 and the
+    # off-diagonal entries average to 0; E||S x||^2 = ||x||^2.
+    m, d, nnz = 60, 20, 4
+    rng = np.random.Generator(np.random.PCG64(0))
+    x = rng.standard_normal(m)
+    acc = np.zeros((m, m))
+    sx = []
+    trials = 400
+    for seed in range(trials):
+        S = O.saso_matrix(m, d, nnz, seed).toarray()
+        StS = S.T @ S
+        assert np.allclose(np.diag(StS), 1.0, atol=1e-15)
+        acc += StS
+        sx.append(np.sum((S @ x) ** 2))
+    off = (acc / trials)[~np.eye(m, dtype=bool)]
+    assert np.max(np.abs(off)) < 0.15
+    assert abs(np.mean(sx) / np.sum(x ** 2) - 1.0) < 0.05
+
+
+def test_sketch_matches_dense_brute_force():
+    m, n, d, nnz = 37, 5, 11, 3
+    rng = np.random.Generator(np.random.PCG64(4))
+    A = rng.standard_normal((m, n))
+    rows, signs = O.saso_sample(m, d, nnz, seed=77)
+    S = np.zeros((d, m))
+    for j in range(m):
+        for t in range(nnz):
+            S[rows[j, t], j] += signs[j, t] / math.sqrt(nnz)
+    brute = np.zeros((d, n))
+    for r in range(d):
+        for c in range(n):
+            acc = 0.0
+            for j in range(m):
+                acc += S[r, j] * A[j, c]
+            brute[r, c] = acc
+    got = O.sketch(A, rows, signs, d)
+    assert np.allclose(got, brute, rtol=1e-14, atol=1e-14)
+    # ... and the sparse operator the oracle builds is the same matrix
+    assert np.allclose(O.saso_matrix(m, d, nnz, 77).toarray(), S, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# QRCP of the sketch
+# ---------------------------------------------------------------------------
+
+def _greedy_pivots(X):
+    """Brute force max-norm pivoting: at each step pick the column farthest from
+    the span of the columns already chosen (distance from a fresh least-squares
+    fit), ties to the smallest index."""
+    d, n = X.shape
+    chosen = []
+    for _ in range(n):
+        best, bestc = -1.0, None
+        for c in range(n):
+            if c in chosen:
+                continue
+            if chosen:
+                B = X[:, chosen]
+                coef, *_ = np.linalg.lstsq(B, X[:, c], rcond=None)
+                r = np.linalg.norm(X[:, c] - B @ coef)
+            else:
+                r = np.linalg.norm(X[:, c])
+            if r > best:
+                best, bestc = r, c
+        chosen.append(bestc)
+    return np.array(chosen)
+
+
+def test_qrcp_matches_brute_force_on_separated_columns():
+    X = W.column_scaled_well_separated(30, 12, seed=5, ratio=3.0)
+    J, R = O.qrcp(X)
+    assert np.array_equal(J, _greedy_pivots(X))
+    Qn, Rn = np.linalg.qr(X[:, J])
+    sgn = np.where(np.diag(Rn) < 0, -1.0, 1.0)
+    assert np.allclose(R, Rn * sgn[:, None], rtol=0, atol=1e-14 * np.abs(R).max())
+
+
+def test_qrcp_matches_lapack_geqp3_on_separated_columns():
+    X = W.column_scaled_well_separated(200, 60, seed=6, ratio=1.5)
+    J, R = O.qrcp(X)
+    _, Rl, Pl = scipy.linalg.qr(X, mode="economic", pivoting=True)
+    assert np.array_equal(J, Pl)
+    assert np.allclose(R, np.abs(np.diag(Rl))[:, None] / np.diag(Rl)[:, None] * Rl,
+                       rtol=0, atol=1e-13 * np.abs(R).max())
+
+
+def test_qrcp_invariants():
+    rng = np.random.Generator(np.random.PCG64(8))
+    X = rng.standard_normal((50, 40)) * np.logspace(0, -6, 40)
+    J, R, refl, flip = O.qrcp(X, return_reflectors=True)
+    Q = O.qrcp_q_factor(refl, flip, 50)
+    assert sorted(J.tolist()) == list(range(40))
+    assert np.allclose(Q.T @ Q, np.eye(40), atol=1e-14)
+    assert np.allclose(Q @ R, X[:, J], atol=1e-14)
+    assert np.array_equal(R, np.triu(R))
+    dg = np.diag(R)
+    assert np.all(dg >= 0)
+    assert np.all(dg[:-1] >= dg[1:] * (1 - 1e-14))
+    for i in range(40):
+        for j in range(i, 40):
+            assert dg[i] >= np.linalg.norm(R[i:j + 1, j]) * (1 - 1e-13)
+
+
+def test_qrcp_ties_and_zero():
+    J, R = O.qrcp(np.eye(6, 4))
+    assert J.tolist() == [0, 1, 2, 3]
+    assert np.allclose(R, np.eye(4))
+    # equal norms in permuted positions: the smallest original index wins
+    X = np.zeros((5, 3))
+    X[0, 2] = 1.0
+    X[1, 0] = 1.0
+    X[2, 1] = 1.0
+    J, R = O.qrcp(X)
+    assert J.tolist() == [0, 1, 2]
+    J, R = O.qrcp(np.zeros((4, 3)))
+    assert J.tolist() == [0, 1, 2] and not R.any()
+
+
+# ---------------------------------------------------------------------------
+# Rank stages (Sec. 3.3) and Cholesky with failure index
+# ---------------------------------------------------------------------------
+
+def test_rank_stage1_exact_cases():
+    R = np.diag([1.0, 2.0 ** -10, 2.0 ** -20, 2.0 ** -30])
+    assert O.rank_stage1(R, 2.0 ** -20) == 3
+    R0 = np.diag([1.0, 2.0 ** -10, 2.0 ** -20, 0.0])
+    # ||C_2||_F = 2^-20 = tol * s exactly: the threshold is inclusive
+    assert O.rank_stage1(R0, 2.0 ** -20) == 2
+    assert O.rank_stage1(R0, 2.0 ** -20 * (1 - 2 ** -40)) == 3
+    assert O.rank_stage1(np.zeros((3, 3)), 1e-14) == 0
+    assert O.rank_stage1(np.triu(np.ones((4, 4))), 0.0) == 4
+    # s is the max |entry| (here off the diagonal), not the first diagonal
+    Rs = np.array([[0.5, -4.0], [0.0, 0.25]])
+    assert O.rank_stage1(Rs, 0.25 / 4.0) == 1
+    assert O.rank_stage1(Rs, 0.25 / 4.0 * (1 - 2 ** -40)) == 2
+    # the Frobenius norm of the whole trailing block counts, not its diagonal
+    Rt = np.array([[1.0, 0.0, 0.0], [0.0, 2.0 ** -10, 2.0 ** -10], [0.0, 0.0, 0.0]])
+    assert O.rank_stage1(Rt, 2.0 ** -10) == 2
+    assert O.rank_stage1(Rt, 2.0 ** -9.5) == 1
+
+
+def test_rank_stage2_cases():
+    assert O.rank_stage2(np.diag([10.0, 1.0])) == 2
+    assert O.rank_stage2(np.diag([10.0, 1.0, 0.999])) == 2
+    assert O.rank_stage2(np.diag([1.0, 10.0, 2.0])) == 3
+    assert O.rank_stage2(np.diag([-3.0, 1.0, 0.25])) == 2
+    assert O.rank_stage2(np.zeros((0, 0))) == 0
+    assert O.rank_stage2(np.diag([2.0])) == 1
+
+
+def test_cholesky_against_library_and_failures():
+    rng = np.random.Generator(np.random.PCG64(3))
+    B = rng.standard_normal((40, 12))
+    G = B.T @ B
+    R, k = O.cholesky_upper(G)
+    assert k == 12
+    assert np.allclose(R, np.linalg.cholesky(G).T, rtol=1e-13, atol=1e-13)
+    R, k = O.cholesky_upper(np.diag([4.0, 1.0, -1.0, 5.0]))
+    assert k == 2 and np.allclose(R, np.diag([2.0, 1.0]))
+    R, k = O.cholesky_upper(np.array([[1.0, 1.0], [1.0, 1.0]]))
+    assert k == 1 and np.allclose(R, [[1.0]])
+    R, k = O.cholesky_upper(np.array([[np.nan, 0.0], [0.0, 1.0]]))
+    assert k == 0
+    # a leading block that is PD survives a later failure unchanged
+    Gb = G.copy()
+    Gb[7, 7] = -1.0
+    R7, k7 = O.cholesky_upper(Gb)
+    assert k7 == 7
+    assert np.allclose(R7, np.linalg.cholesky(G[:7, :7]).T, rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# The whole path
+# ---------------------------------------------------------------------------
+
+def _c1_small(m=3000, n=60, cond=1e6, seed=0):
+    s = W.logspaced_spectrum(n, cond)
+    return W.spectrum_matrix(m, n, s, seed)
+
+
+def test_path_reconstruction_orthogonality_and_definition():
+    A = _c1_small()
+    out = O.cqrrpt(A, d=75, nnz=4, seed=0, tol=1e-14)
+    Q, R, J, k = out["Q"], out["R"], out["J"], out["rank"]
+    assert k == 60 and out["status"] == 0 and out["chol_fail_col"] == -1
+    assert np.linalg.norm(A[:, J] - Q @ R) / np.linalg.norm(A) < 1e-14
+    assert np.linalg.norm(Q.T @ Q - np.eye(60), 2) < 1e-13
+    assert np.array_equal(R, np.triu(R)) and np.all(np.diag(R) > 0)
+    # Theorem (correctness): given J and k, (Q, R) is the positive-diagonal
+    # QR of A[:, J]; R is reached to ~u, Q to ~u * cond.
+    Qd, Rd = O.factor_given_pivots(A, J, k)
+    assert np.linalg.norm(R - Rd) / np.linalg.norm(Rd) < 1e-13
+    assert np.linalg.norm(Q - Qd) / np.linalg.norm(Qd) < 1e-16 * 1e6 * 100
+
+
+def test_path_with_signed_permutation_is_plain_qrcp():
+    # S a signed permutation (d = m): the sketch is an orthogonal image of A,
+    # so CQRRPT reduces to Householder QRCP of A and R_pre = I.
+    rng = np.random.Generator(np.random.PCG64(11))
+    A = W.column_scaled_well_separated(120, 20, seed=12, ratio=1.3)
+    perm = rng.permutation(120)
+    sg = rng.choice([-1.0, 1.0], size=120)
+    S = np.zeros((120, 120))
+    S[perm, np.arange(120)] = sg
+    out = O.cqrrpt_core(A, S, tol=1e-14)
+    Jq, Rq = O.qrcp(A)
+    assert np.array_equal(out["J"], Jq)
+    assert np.allclose(out["R"], Rq, rtol=0, atol=1e-14 * np.abs(Rq).max())
+    assert np.allclose(out["Rpre"], np.eye(20), atol=1e-14)
+
+
+def test_path_preconditioned_spectrum_theorem():
+    # Theorem on the spectrum of M_pre: sigma_i(M_pre) = 1/sigma_{k-i+1}(S U),
+    # U an orthonormal basis of range(A); also S M_pre is orthonormal.
+    A = _c1_small(m=2000, n=40, cond=1e4, seed=3)
+    S = O.saso_matrix(2000, 50, 4, seed=5)
+    out = O.cqrrpt_core(A, S, tol=1e-14)
+    assert out["rank_stage1"] == 40
+    U, _ = np.linalg.qr(A)
+    sv_su = np.linalg.svd((S @ U), compute_uv=False)
+    sv_pre = np.linalg.svd(out["Mpre"], compute_uv=False)
+    assert np.allclose(sv_pre, 1.0 / sv_su[::-1], rtol=1e-10)
+    SM = S @ out["Mpre"]
+    assert np.allclose(SM.T @ SM, np.eye(40), atol=1e-12)
+
+
+def test_path_scale_invariance():
+    A = _c1_small(m=1500, n=30, cond=1e5, seed=4)
+    S = O.saso_matrix(1500, 40, 4, seed=6)
+    base = O.cqrrpt_core(A, S, tol=1e-14)
+    # scaling A by a power of two scales R exactly and leaves J, Q unchanged
+    sc = O.cqrrpt_core(A * 2.0 ** 7, S, tol=1e-14)
+    assert np.array_equal(sc["J"], base["J"])
+    assert np.array_equal(sc["Q"], base["Q"])
+    assert np.array_equal(sc["R"], base["R"] * 2.0 ** 7)
+    # scaling S changes nothing in exact arithmetic (Q, R, J)
+    s2 = O.cqrrpt_core(A, S * 3.0, tol=1e-14)
+    assert np.array_equal(s2["J"], base["J"])
+    assert np.allclose(s2["R"], base["R"], rtol=0, atol=1e-13 * np.abs(base["R"]).max())
+
+
+def test_path_tiny_and_degenerate_cases():
+    rng = np.random.Generator(np.random.PCG64(21))
+    a = rng.standard_normal((50, 1))
+    out = O.cqrrpt(a, d=2, nnz=1, seed=1, tol=1e-14)
+    assert out["rank"] == 1
+    assert np.isclose(out["R"][0, 0], np.linalg.norm(a), rtol=1e-15)
+    assert np.allclose(out["Q"][:, 0], a[:, 0] / np.linalg.norm(a), rtol=1e-14)
+    # orthonormal input: R = I and Q = A[:, J]
+    U = W.haar_orthonormal(rng, 400, 16)
+    out = O.cqrrpt(U, d=20, nnz=4, seed=2, tol=1e-14)
+    assert out["rank"] == 16
+    assert np.allclose(out["R"], np.eye(16), atol=1e-14)
+    assert np.allclose(out["Q"], U[:, out["J"]], atol=1e-14)
+    # zero input: rank 0, not an error
+    out = O.cqrrpt(np.zeros((30, 4)), d=5, nnz=2, seed=0, tol=1e-14)
+    assert out["rank"] == 0 and out["status"] == O.STATUS_OK
+    assert not out["Q"].any() and not out["R"].any()
+    # a non-finite entry is reported
+    bad = rng.standard_normal((30, 4))
+    bad[3, 2] = np.inf
+    out = O.cqrrpt(bad, d=5, nnz=2, seed=0, tol=1e-14)
+    assert out["status"] == O.STATUS_NONFINITE
+
+
+def test_path_planted_rank_recovery():
+    # noise-free rank-r input: stage 1 recovers r for tol inside the gap
+    m, n, r = 4000, 48, 20
+    s = np.zeros(n)
+    s[:r] = W.logspaced_spectrum(r, 1e3)
+    A = W.spectrum_matrix(m, n, s, seed=7)
+    for tol in (1e-11, 1e-8, 1e-5):
+        out = O.cqrrpt(A, d=60, nnz=8, seed=3, tol=tol)
+        assert out["rank"] == r, tol
+        Q, R, J = out["Q"], out["R"], out["J"]
+        assert np.linalg.norm(A[:, J] - Q @ R) / np.linalg.norm(A) < 1e-12
+        assert np.linalg.norm(Q[:, :r].T @ Q[:, :r] - np.eye(r), 2) < 1e-13
+        assert not Q[:, r:].any() and not R[r:, :].any()
+
+
+def test_path_stage2_truncates_ill_conditioned_preconditioner():
+    # Two identical columns with tol = 0: stage 1 keeps everything, the
+    # duplicate's preconditioned column is noise-dominated, and stage 2 (or the
+    # Cholesky failure rule) truncates the rank below n.
+    rng = np.random.Generator(np.random.PCG64(31))
+    A = rng.standard_normal((500, 8))
+    A[:, 5] = A[:, 2]
+    out = O.cqrrpt(A, d=10, nnz=4, seed=1, tol=0.0)
+    assert out["rank_stage1"] == 8
+    assert out["rank"] == 7
+    Q, R, J = out["Q"], out["R"], out["J"]
+    assert np.linalg.norm(A[:, J] - Q @ R) / np.linalg.norm(A) < 1e-14
+    assert np.linalg.norm(Q[:, :7].T @ Q[:, :7] - np.eye(7), 2) < 1e-14
