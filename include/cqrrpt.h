@@ -1,0 +1,172 @@
+/*
+ * cqrrpt.h -- C ABI of the MI355X (gfx950) CQRRPT library.
+ *
+ * CQRRPT is the randomized, pivoted CholeskyQR for tall matrices of
+ * Melnichenko, Balabanov, Murray, Demmel, Mahoney and Luszczek,
+ * arXiv:2311.08316 ("CholeskyQR with Randomization and Pivoting for Tall
+ * Matrices"). Given an m x n matrix A (m >= n) it returns a column pivot
+ * order J, an m x k matrix Q with orthonormal columns, a k x n upper
+ * trapezoidal R and the numerical rank k such that A[:, J] = Q R
+ * (Algorithm 1 with the core of Algorithm 2; Theorem "correctness", Sec. 2.1).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are FP64, column-major: element (i, j) of X is X[i + j*ldx].
+ *   - Every array argument is a DEVICE pointer (hipMalloc / PyTorch tensor
+ *     storage) unless the comment says "host". The caller owns all inputs and
+ *     outputs; the library never allocates or frees them and never writes to A.
+ *   - Indices (J) are 0-based int64.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Entry points taking a stream are stream-ordered and return before the
+ *     GPU work finishes; entry points without one are synchronous.
+ *   - Return value: 0 on success; -i when argument i (1-based, in the order of
+ *     the prototype) is invalid, LAPACK INFO style, and nothing is launched;
+ *     a positive CQRRPT_E* code for runtime failures (see below).
+ *   - Calls on different streams with disjoint buffers may run concurrently.
+ *     Results are deterministic: identical inputs give bit-identical outputs
+ *     on the same GPU (no floating-point atomics; fixed reduction orders).
+ */
+#ifndef CQRRPT_H
+#define CQRRPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Positive status codes. */
+#define CQRRPT_OK            0
+#define CQRRPT_ENONFINITE    1  /* A holds a NaN/Inf (seen as a non-finite sketch); rank = 0 */
+#define CQRRPT_EBUDGET       2  /* request exceeds the server's device-memory budget        */
+#define CQRRPT_EHIP          3  /* a HIP runtime call failed                                 */
+#define CQRRPT_EWORKSPACE    4  /* workspace smaller than cqrrpt_workspace_bytes()           */
+#define CQRRPT_EBARRIER      5  /* a persistent kernel's grid barrier timed out              */
+#define CQRRPT_ELIMIT        6  /* size beyond what this build supports (see limits below)   */
+
+/* Precision modes (Sec. 3, Theorem "simple stability": the preconditioning
+ * solve may run at a larger unit roundoff than the other steps).
+ *   CQRRPT_FP64 : every step in FP64.
+ *   CQRRPT_MIXED: the preconditioning solve M_pre = A[:,J] R_sk^{-1} runs on
+ *                 FP32 matrix cores and stores M_pre in FP32; the Gram, the
+ *                 Q solve, the sketch QRCP, Cholesky and R = R_pre R_sk stay
+ *                 FP64; one extra CholeskyQR pass (Sec. 1.2, "CholeskyQR2")
+ *                 runs when the estimated orthogonality loss exceeds 1e-13. */
+typedef enum { CQRRPT_FP64 = 0, CQRRPT_MIXED = 1 } cqrrpt_mode_t;
+
+/* Per-call diagnostics, written to DEVICE memory by cqrrpt_factor_ex and
+ * copied to the host by cqrrpt_factor. */
+typedef struct {
+    int64_t rank;            /* k: final numerical rank (Sec. 3.3, second stage)          */
+    int64_t rank_stage1;     /* k_o: first-stage bound (Sec. 3.3, first stage)             */
+    int64_t chol_fail_col;   /* 0-based column where Cholesky stopped, -1 if it did not
+                                (Remark on Cholesky failure, Sec. 3.3)                      */
+    int32_t status;          /* CQRRPT_OK, CQRRPT_ENONFINITE or CQRRPT_EBARRIER             */
+    int32_t cholqr2_passes;  /* extra CholeskyQR passes run (mixed mode), 0 or 1            */
+    double  smax;            /* max |R_sk|, the scale of the first-stage test               */
+    double  orth_est;        /* mixed mode: max |G2 - I| of the re-orthogonalisation Gram;
+                                0 when no estimate was formed                               */
+} cqrrpt_info_t;
+
+/* Limits of this build: n <= 8192, d <= 16384, 1 <= nnz <= 32. */
+
+/* ------------------------------------------------------------------------
+ * Sketching operator (Sec. 2.3.1, SASO)
+ * ------------------------------------------------------------------------
+ * Writes the d x m sparse sign operator S with exactly nnz nonzeros per
+ * column: for source row j (column j of S) and t < nnz,
+ *   rows[j*nnz + t]  = the row of S holding the t-th nonzero (distinct per j),
+ *   signs[j*nnz + t] = +1 or -1; the value is signs/sqrt(nnz).
+ * Rows are drawn by Floyd's subset sampler from exact uniform integers
+ * (Lemire's multiply-shift with rejection) fed by Philox4x32-10 keyed by
+ * `seed`, one counter stream per j; the sign bits are the stream's first
+ * word. The operator therefore depends only on (seed, d, nnz, j) and is
+ * bit-identical to any implementation of the same definition.
+ * rows: int32[m*nnz], signs: int8[m*nnz], both device, caller-owned.
+ * Errors: -1 m < 1, -2 d < 1, -3 nnz outside [1, min(32, d)], -5/-6 NULL. */
+int cqrrpt_saso_sample(int64_t m, int64_t d, int32_t nnz, uint64_t seed,
+                       int32_t* rows, int8_t* signs, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Sketch Ahat = S A (Algorithm 2, first step)
+ * ------------------------------------------------------------------------
+ * A: m x n (lda >= m). Ahat: d x n (ldah >= d). S as in cqrrpt_saso_sample.
+ * ws: device workspace of at least cqrrpt_sketch_workspace_bytes(m,n,d,nnz)
+ * bytes. Each entry of Ahat is 1/sqrt(nnz) times a signed sum of entries of
+ * A, accumulated in a fixed order (deterministic).
+ * Returns CQRRPT_ENONFINITE (after the work completes on `stream`, i.e. the
+ * check is synchronous) is NOT reported here; use cqrrpt_factor_ex's info.
+ * Errors: -1..-8 bad sizes/pointers, CQRRPT_EWORKSPACE. */
+size_t cqrrpt_sketch_workspace_bytes(int64_t m, int64_t n, int64_t d, int32_t nnz);
+int cqrrpt_sketch(const double* A, int64_t lda, int64_t m, int64_t n,
+                  int64_t d, int32_t nnz, uint64_t seed,
+                  double* Ahat, int64_t ldah,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * QR with column pivoting of a short-wide-ish d x n matrix (Algorithm 2,
+ * second step; Householder QR with max-norm pivoting as in LAPACK GEQP3)
+ * ------------------------------------------------------------------------
+ * X: d x n (ldx >= d, d >= n), OVERWRITTEN (it is the working array).
+ * J: int64[n], the 0-based pivot order, always full length.
+ * R: n x n (ldr >= n), upper triangular with non-negative diagonal; entries
+ *    below the diagonal are written as zero.
+ * Column norms are recomputed exactly at every step; ties go to the smallest
+ * original column index. Runs as one cooperative (grid-synchronised) launch.
+ * ws: at least cqrrpt_qrcp_workspace_bytes(d, n) bytes.
+ * Errors: bad sizes/pointers (negative), CQRRPT_EWORKSPACE, CQRRPT_EHIP. */
+size_t cqrrpt_qrcp_workspace_bytes(int64_t d, int64_t n);
+int cqrrpt_qrcp(double* X, int64_t ldx, int64_t d, int64_t n,
+                int64_t* J, double* R, int64_t ldr,
+                void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * The whole factorization (Algorithm 1 with Algorithm 2's core)
+ * ------------------------------------------------------------------------
+ * A:    m x n input (lda >= m), read only.
+ * d:    sketch rows, n <= d <= m (Algorithm 2's input condition); the paper's
+ *       default is d = ceil(1.25 n) (Algorithm 1).
+ * nnz:  nonzeros per column of the SASO, 1 <= nnz <= min(32, d).
+ * seed: selects the sketching operator (see cqrrpt_saso_sample).
+ * tol:  first-stage rank tolerance (takes the place of the unit roundoff u
+ *       in the first-stage bound of Sec. 3.3), finite and >= 0; 1e-14 is a
+ *       good default in FP64. The second stage keeps the largest leading
+ *       block whose diagonal condition estimate is <= sqrt(100) = 10.
+ * Q:    m x n output (ldq >= m): Q[:, :rank] orthonormal, Q[:, rank:] = 0.
+ * R:    n x n output (ldr >= n): R[:rank, :] upper trapezoidal with a
+ *       non-negative diagonal, R[rank:, :] = 0.
+ * J:    int64[n] output, 0-based pivots, always the full permutation.
+ * rank: HOST pointer receiving k.
+ * Synchronous; allocates and frees its own workspace. A rank of 0 (A = 0)
+ * is a valid result. A Cholesky failure is not an error: it truncates the
+ * rank. Returns CQRRPT_ENONFINITE when A holds a NaN or Inf. */
+int cqrrpt_factor(const double* A, int64_t lda, int64_t m, int64_t n,
+                  int64_t d, int32_t nnz, uint64_t seed, double tol,
+                  double* Q, int64_t ldq, double* R, int64_t ldr,
+                  int64_t* J, int64_t* rank);
+
+/* Workspace for cqrrpt_factor_ex, in bytes (256-byte aligned base needed). */
+size_t cqrrpt_workspace_bytes(int64_t m, int64_t n, int64_t d, int32_t nnz,
+                              cqrrpt_mode_t mode);
+
+/* Stream-ordered form of cqrrpt_factor: no host synchronisation, no
+ * allocation. ws: caller-owned device workspace of at least
+ * cqrrpt_workspace_bytes() bytes (contents on entry are ignored).
+ * info: DEVICE pointer to one cqrrpt_info_t (required; holds the rank).
+ * Argument order: A lda m n d nnz seed tol Q ldq R ldr J mode ws ws_bytes
+ * stream info. */
+int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n,
+                     int64_t d, int32_t nnz, uint64_t seed, double tol,
+                     double* Q, int64_t ldq, double* R, int64_t ldr,
+                     int64_t* J, cqrrpt_mode_t mode,
+                     void* ws, size_t ws_bytes, void* stream,
+                     cqrrpt_info_t* info);
+
+/* Human-readable name of a return code. */
+const char* cqrrpt_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CQRRPT_H */

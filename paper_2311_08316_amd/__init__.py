@@ -1,0 +1,15 @@
+"""CQRRPT on MI355X (gfx950): randomized pivoted CholeskyQR for tall matrices.
+
+The computation runs in the HIP library ``libcqrrpt.so`` (C ABI in
+``include/cqrrpt.h``); this package is its Python binding.
+"""
+
+from ._binding import (CQRRPT_FP64, CQRRPT_MIXED, CqrrptError, CqrrptInfo, Factorization,
+                       colmajor, empty_colmajor, factor, factor_sync, lib, qrcp, saso_sample,
+                       sketch, workspace_bytes)
+
+__all__ = [
+    "CQRRPT_FP64", "CQRRPT_MIXED", "CqrrptError", "CqrrptInfo", "Factorization", "colmajor",
+    "empty_colmajor", "factor", "factor_sync", "lib", "qrcp", "saso_sample", "sketch",
+    "workspace_bytes",
+]

@@ -1,0 +1,220 @@
+"""ctypes binding to ``libcqrrpt.so`` (the C ABI of ``include/cqrrpt.h``).
+
+Argument marshalling only: every function here checks tensor placement and
+layout, passes raw device pointers and the current HIP stream to the library,
+and returns. There is no CPU fallback; a missing library or a tensor that is
+not on the GPU raises.
+
+Matrices are FP64 and column-major. A torch tensor ``A`` of shape (m, n) is
+column-major when ``A.stride(0) == 1``; ``colmajor(A)`` returns such a view
+(copying if needed), and ``empty_colmajor`` allocates one.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcqrrpt.so")
+
+CQRRPT_FP64 = 0
+CQRRPT_MIXED = 1
+
+STATUS = {
+    0: "ok", 1: "non-finite input", 2: "device-memory budget exceeded",
+    3: "HIP runtime error", 4: "workspace too small", 5: "grid barrier timed out",
+    6: "size beyond this build's limits",
+}
+
+
+class CqrrptInfo(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int64), ("rank_stage1", ctypes.c_int64),
+                ("chol_fail_col", ctypes.c_int64), ("status", ctypes.c_int32),
+                ("cholqr2_passes", ctypes.c_int32), ("smax", ctypes.c_double),
+                ("orth_est", ctypes.c_double)]
+
+
+INFO_BYTES = ctypes.sizeof(CqrrptInfo)
+
+_lib = None
+
+_i64, _i32, _u64, _dbl, _vp, _sz = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
+                                    ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t)
+_SIGS = {
+    "cqrrpt_saso_sample": (ctypes.c_int, [_i64, _i64, _i32, _u64, _vp, _vp, _vp]),
+    "cqrrpt_sketch_workspace_bytes": (_sz, [_i64, _i64, _i64, _i32]),
+    "cqrrpt_sketch": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i32, _u64, _vp, _i64,
+                                     _vp, _sz, _vp]),
+    "cqrrpt_qrcp_workspace_bytes": (_sz, [_i64, _i64]),
+    "cqrrpt_qrcp": (ctypes.c_int, [_vp, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _sz, _vp]),
+    "cqrrpt_factor": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i32, _u64, _dbl,
+                                     _vp, _i64, _vp, _i64, _vp, ctypes.POINTER(_i64)]),
+    "cqrrpt_workspace_bytes": (_sz, [_i64, _i64, _i64, _i32, ctypes.c_int]),
+    "cqrrpt_factor_ex": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i32, _u64, _dbl,
+                                        _vp, _i64, _vp, _i64, _vp, ctypes.c_int,
+                                        _vp, _sz, _vp, _vp]),
+    "cqrrpt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+
+def lib():
+    """Load the shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing; build it with "
+                               "`python paper_2311_08316_amd/build_lib.py`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class CqrrptError(RuntimeError):
+    pass
+
+
+def _check(rc, what):
+    if rc != 0:
+        if rc < 0:
+            raise CqrrptError(f"{what}: argument {-rc} is invalid")
+        raise CqrrptError(f"{what}: {STATUS.get(rc, rc)}")
+
+
+def _stream_handle(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _on_gpu(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise CqrrptError(f"{name} must be a GPU tensor")
+
+
+def colmajor(A):
+    """Column-major FP64 view of a 2-D GPU tensor (copying only if needed)."""
+    _on_gpu(A, "A")
+    if A.dtype != torch.float64:
+        raise CqrrptError("A must be float64")
+    if A.dim() != 2:
+        raise CqrrptError("A must be 2-D")
+    if A.stride(0) == 1 and A.stride(1) >= max(1, A.shape[0]):
+        return A
+    return A.t().contiguous().t()
+
+
+def empty_colmajor(m, n, device, dtype=torch.float64):
+    return torch.empty((n, m), dtype=dtype, device=device).t()
+
+
+def _ld(A):
+    return max(1, A.stride(1)) if A.shape[1] > 1 else max(1, A.shape[0])
+
+
+def saso_sample(m, d, nnz, seed, device="cuda"):
+    """Rows (int32[m, nnz]) and signs (int8[m, nnz]) of the sketching operator."""
+    rows = torch.empty((m, nnz), dtype=torch.int32, device=device)
+    signs = torch.empty((m, nnz), dtype=torch.int8, device=device)
+    rc = lib().cqrrpt_saso_sample(m, d, nnz, seed, rows.data_ptr(), signs.data_ptr(),
+                                  _stream_handle(rows.device))
+    _check(rc, "cqrrpt_saso_sample")
+    return rows, signs
+
+
+def sketch(A, d, nnz, seed):
+    """Ahat = S A as a column-major d x n GPU tensor."""
+    A = colmajor(A)
+    m, n = A.shape
+    out = empty_colmajor(d, n, A.device)
+    wsb = lib().cqrrpt_sketch_workspace_bytes(m, n, d, nnz)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=A.device)
+    rc = lib().cqrrpt_sketch(A.data_ptr(), _ld(A), m, n, d, nnz, seed, out.data_ptr(), d,
+                             ws.data_ptr(), wsb, _stream_handle(A.device))
+    _check(rc, "cqrrpt_sketch")
+    return out
+
+
+def qrcp(X):
+    """Householder QRCP of a d x n GPU matrix (d >= n). Returns (J, R); X is
+    copied, not overwritten."""
+    src = colmajor(X)
+    d, n = src.shape
+    X = empty_colmajor(d, n, src.device)
+    X.copy_(src)
+    J = torch.empty(n, dtype=torch.int64, device=X.device)
+    R = empty_colmajor(n, n, X.device)
+    wsb = lib().cqrrpt_qrcp_workspace_bytes(d, n)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=X.device)
+    rc = lib().cqrrpt_qrcp(X.data_ptr(), d, d, n, J.data_ptr(), R.data_ptr(), n, ws.data_ptr(),
+                           wsb, _stream_handle(X.device))
+    _check(rc, "cqrrpt_qrcp")
+    return J, R
+
+
+def workspace_bytes(m, n, d, nnz, mode=CQRRPT_FP64):
+    return lib().cqrrpt_workspace_bytes(m, n, d, nnz, mode)
+
+
+class Factorization:
+    """Preallocated outputs and workspace for repeated stream-ordered calls."""
+
+    def __init__(self, m, n, d, nnz, mode=CQRRPT_FP64, device="cuda"):
+        self.m, self.n, self.d, self.nnz, self.mode = m, n, d, nnz, mode
+        self.device = torch.device(device)
+        self.Q = empty_colmajor(m, n, self.device)
+        self.R = empty_colmajor(n, n, self.device)
+        self.J = torch.empty(n, dtype=torch.int64, device=self.device)
+        self.ws_bytes = workspace_bytes(m, n, d, nnz, mode)
+        if self.ws_bytes == 0:
+            raise CqrrptError("unsupported sizes")
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.info_buf = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=self.device)
+
+    def run(self, A, seed, tol, stream=None):
+        """Enqueue one factorization of A on the current (or given) stream."""
+        A = colmajor(A)
+        if tuple(A.shape) != (self.m, self.n):
+            raise CqrrptError("A has the wrong shape")
+        s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else \
+            _stream_handle(self.device)
+        rc = lib().cqrrpt_factor_ex(A.data_ptr(), _ld(A), self.m, self.n, self.d, self.nnz,
+                                    seed, tol, self.Q.data_ptr(), self.m, self.R.data_ptr(),
+                                    self.n, self.J.data_ptr(), self.mode, self.ws.data_ptr(),
+                                    self.ws_bytes, s, self.info_buf.data_ptr())
+        _check(rc, "cqrrpt_factor_ex")
+
+    def info(self):
+        """Copy the device-side diagnostics to the host (synchronises)."""
+        raw = bytes(self.info_buf.cpu().numpy().tobytes())
+        return CqrrptInfo.from_buffer_copy(raw)
+
+
+def factor(A, d, nnz, seed, tol, mode=CQRRPT_FP64):
+    """One factorization: returns (Q, R, J, info). Q is m x n, R is n x n
+    (both column-major, zero past the rank), J holds 0-based pivots."""
+    A = colmajor(A)
+    m, n = A.shape
+    f = Factorization(m, n, d, nnz, mode, A.device)
+    f.run(A, seed, tol)
+    info = f.info()
+    if info.status != 0:
+        _check(info.status, "cqrrpt_factor_ex")
+    return f.Q, f.R, f.J, info
+
+
+def factor_sync(A, d, nnz, seed, tol):
+    """The synchronous C entry point ``cqrrpt_factor`` (allocates internally)."""
+    A = colmajor(A)
+    m, n = A.shape
+    Q = empty_colmajor(m, n, A.device)
+    R = empty_colmajor(n, n, A.device)
+    J = torch.empty(n, dtype=torch.int64, device=A.device)
+    rank = ctypes.c_int64(-1)
+    torch.cuda.synchronize(A.device)
+    rc = lib().cqrrpt_factor(A.data_ptr(), _ld(A), m, n, d, nnz, seed, tol, Q.data_ptr(), m,
+                             R.data_ptr(), n, J.data_ptr(), ctypes.byref(rank))
+    _check(rc, "cqrrpt_factor")
+    return Q, R, J, rank.value

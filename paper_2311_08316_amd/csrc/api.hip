@@ -1,0 +1,285 @@
+// C ABI of the library (declared in include/cqrrpt.h): argument checks,
+// workspace layout and the stream-ordered launch sequence of Algorithm 2.
+#include <math.h>
+#include <mutex>
+
+#include "common.h"
+
+namespace cqh {
+
+const Device& device_info() {
+  static Device dev{-1, 0, 0};
+  static std::mutex mu;
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) cur = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  if (dev.id != cur) {
+    int cu = 0, lds = 0;
+    hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, cur);
+    hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, cur);
+    dev.id = cur;
+    dev.num_cu = cu > 0 ? cu : 1;
+    dev.lds_per_block = lds > 0 ? (size_t)lds : 65536;
+  }
+  return dev;
+}
+
+}  // namespace cqh
+
+namespace {
+
+constexpr int kMaxN = 8192;
+constexpr int kMaxD = 16384;
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+__global__ void info_init_kernel(cqrrpt_info_t* info) {
+  if (threadIdx.x == 0) {
+    info->rank = 0;
+    info->rank_stage1 = 0;
+    info->chol_fail_col = -1;
+    info->status = 0;
+    info->cholqr2_passes = 0;
+    info->smax = 0.0;
+    info->orth_est = 0.0;
+  }
+}
+
+// Offsets of every buffer inside the factorization workspace.
+struct Layout {
+  cqh::SketchPlan sk;
+  cqh::QrcpPlan qr;
+  size_t off_ahat, off_sketch, off_qrcp, off_rsk, off_rn2, off_bmax, off_k, off_syrkp, off_g,
+      off_chol, off_mpre32, total;
+};
+
+Layout make_layout(int64_t m, int64_t n, int64_t d, int nnz, cqrrpt_mode_t mode) {
+  Layout L;
+  L.sk = cqh::plan_sketch(m, n, (int)d, nnz);
+  L.qr = cqh::plan_qrcp((int)d, (int)n);
+  size_t o = 0;
+  L.off_ahat = o; o += align256((size_t)d * n * 8);
+  L.off_sketch = o; o += align256(cqh::sketch_ws_bytes(L.sk));
+  L.off_qrcp = o; o += align256(cqh::qrcp_ws_bytes(L.qr));
+  L.off_rsk = o; o += align256((size_t)n * n * 8);
+  L.off_rn2 = o; o += align256((size_t)n * 8);
+  L.off_bmax = o; o += align256((size_t)((n + 255) / 256) * 8);
+  L.off_k = o; o += 256;
+  L.off_syrkp = o; o += align256(cqh::syrk_ws_bytes(m, (int)n));
+  L.off_g = o; o += align256((size_t)n * n * 8);
+  L.off_chol = o; o += align256(cqh::chol_ws_bytes((int)n));
+  L.off_mpre32 = o;
+  if (mode == CQRRPT_MIXED) o += align256((size_t)m * n * 4);
+  L.total = o;
+  return L;
+}
+
+int check_common(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, int32_t nnz,
+                 double tol) {
+  if (!A) return -1;
+  if (m < 1) return -3;
+  if (n < 1 || n > m) return -4;
+  if (lda < m) return -2;
+  if (d < n || d > m) return -5;
+  if (nnz < 1 || nnz > 32 || nnz > d) return -6;
+  if (!(tol >= 0.0) || !isfinite(tol)) return -8;
+  return 0;
+}
+
+int to_status(hipError_t e) { return e == hipSuccess ? CQRRPT_OK : CQRRPT_EHIP; }
+
+#define CQ_TRY(expr)                       \
+  do {                                     \
+    hipError_t _e = (expr);                \
+    if (_e != hipSuccess) return CQRRPT_EHIP; \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* cqrrpt_status_string(int code) {
+  switch (code) {
+    case CQRRPT_OK: return "ok";
+    case CQRRPT_ENONFINITE: return "input holds a NaN or Inf";
+    case CQRRPT_EBUDGET: return "request exceeds the device-memory budget";
+    case CQRRPT_EHIP: return "HIP runtime error";
+    case CQRRPT_EWORKSPACE: return "workspace too small";
+    case CQRRPT_EBARRIER: return "grid barrier timed out";
+    case CQRRPT_ELIMIT: return "size beyond this build's limits";
+    default: return code < 0 ? "invalid argument" : "unknown status";
+  }
+}
+
+int cqrrpt_saso_sample(int64_t m, int64_t d, int32_t nnz, uint64_t seed, int32_t* rows,
+                       int8_t* signs, void* stream) {
+  if (m < 1) return -1;
+  if (d < 1) return -2;
+  if (nnz < 1 || nnz > 32 || nnz > d) return -3;
+  if (!rows) return -5;
+  if (!signs) return -6;
+  if (d > kMaxD) return CQRRPT_ELIMIT;
+  return to_status(cqh::launch_saso_sample(m, (int)d, nnz, seed, rows, signs,
+                                           static_cast<hipStream_t>(stream)));
+}
+
+size_t cqrrpt_sketch_workspace_bytes(int64_t m, int64_t n, int64_t d, int32_t nnz) {
+  if (m < 1 || n < 1 || d < 1 || nnz < 1 || d > kMaxD) return 0;
+  const cqh::SketchPlan p = cqh::plan_sketch(m, n, (int)d, nnz);
+  return cqh::sketch_ws_bytes(p) + 256;  // + a device status word
+}
+
+int cqrrpt_sketch(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, int32_t nnz,
+                  uint64_t seed, double* Ahat, int64_t ldah, void* ws, size_t ws_bytes,
+                  void* stream) {
+  if (!A) return -1;
+  if (m < 1) return -3;
+  if (lda < m) return -2;
+  if (n < 1) return -4;
+  if (d < 1) return -5;
+  if (nnz < 1 || nnz > 32 || nnz > d) return -6;
+  if (!Ahat) return -8;
+  if (ldah < d) return -9;
+  if (!ws) return -10;
+  if (d > kMaxD || !cqh::sketch_fits((int)d, nnz)) return CQRRPT_ELIMIT;
+  const cqh::SketchPlan p = cqh::plan_sketch(m, n, (int)d, nnz);
+  if (ws_bytes < cqh::sketch_ws_bytes(p) + 256) return CQRRPT_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  cqrrpt_info_t* info =
+      reinterpret_cast<cqrrpt_info_t*>(static_cast<char*>(ws) + cqh::sketch_ws_bytes(p));
+  hipLaunchKernelGGL(info_init_kernel, dim3(1), dim3(64), 0, s, info);
+  CQ_TRY(hipGetLastError());
+  return to_status(cqh::launch_sketch(p, A, lda, m, n, (int)d, nnz, seed, Ahat, ldah, ws, info, s));
+}
+
+size_t cqrrpt_qrcp_workspace_bytes(int64_t d, int64_t n) {
+  if (d < 1 || n < 1 || n > kMaxN || d > kMaxD) return 0;
+  return cqh::qrcp_ws_bytes(cqh::plan_qrcp((int)d, (int)n)) + 256;
+}
+
+int cqrrpt_qrcp(double* X, int64_t ldx, int64_t d, int64_t n, int64_t* J, double* R,
+                int64_t ldr, void* ws, size_t ws_bytes, void* stream) {
+  if (!X) return -1;
+  if (d < 1) return -3;
+  if (ldx < d) return -2;
+  if (n < 1 || n > d) return -4;
+  if (!J) return -5;
+  if (!R) return -6;
+  if (ldr < n) return -7;
+  if (!ws) return -8;
+  if (n > kMaxN || d > kMaxD) return CQRRPT_ELIMIT;
+  const cqh::QrcpPlan p = cqh::plan_qrcp((int)d, (int)n);
+  if (ws_bytes < cqh::qrcp_ws_bytes(p) + 256) return CQRRPT_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  cqrrpt_info_t* info =
+      reinterpret_cast<cqrrpt_info_t*>(static_cast<char*>(ws) + cqh::qrcp_ws_bytes(p));
+  hipLaunchKernelGGL(info_init_kernel, dim3(1), dim3(64), 0, s, info);
+  CQ_TRY(hipGetLastError());
+  return to_status(cqh::launch_qrcp(p, X, ldx, (int)d, (int)n, J, R, ldr, ws, info, s));
+}
+
+size_t cqrrpt_workspace_bytes(int64_t m, int64_t n, int64_t d, int32_t nnz, cqrrpt_mode_t mode) {
+  if (m < 1 || n < 1 || n > m || d < n || d > m || nnz < 1 || nnz > 32 || nnz > d) return 0;
+  if (n > kMaxN || d > kMaxD) return 0;
+  return make_layout(m, n, d, nnz, mode).total;
+}
+
+int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, int32_t nnz,
+                     uint64_t seed, double tol, double* Q, int64_t ldq, double* R, int64_t ldr,
+                     int64_t* J, cqrrpt_mode_t mode, void* ws, size_t ws_bytes, void* stream,
+                     cqrrpt_info_t* info) {
+  const int c = check_common(A, lda, m, n, d, nnz, tol);
+  if (c) return c;
+  if (!Q) return -9;
+  if (ldq < m) return -10;
+  if (!R) return -11;
+  if (ldr < n) return -12;
+  if (!J) return -13;
+  if (mode != CQRRPT_FP64 && mode != CQRRPT_MIXED) return -14;
+  if (!ws) return -15;
+  if (!info) return -18;
+  if (n > kMaxN || d > kMaxD || !cqh::sketch_fits((int)d, nnz)) return CQRRPT_ELIMIT;
+  const Layout L = make_layout(m, n, d, nnz, mode);
+  if (ws_bytes < L.total) return CQRRPT_EWORKSPACE;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  double* Ahat = reinterpret_cast<double*>(base + L.off_ahat);
+  double* Rsk = reinterpret_cast<double*>(base + L.off_rsk);
+  double* rn2 = reinterpret_cast<double*>(base + L.off_rn2);
+  double* bmax = reinterpret_cast<double*>(base + L.off_bmax);
+  int64_t* kv = reinterpret_cast<int64_t*>(base + L.off_k);
+  int64_t* ko_dev = kv;
+  int64_t* k_dev = kv + 1;
+  double* Gp = reinterpret_cast<double*>(base + L.off_syrkp);
+  double* G = reinterpret_cast<double*>(base + L.off_g);
+  const int ni = (int)n;
+
+  hipLaunchKernelGGL(info_init_kernel, dim3(1), dim3(64), 0, s, info);
+  CQ_TRY(hipGetLastError());
+  // S1-S2: sketch.
+  CQ_TRY(cqh::launch_sketch(L.sk, A, lda, m, n, (int)d, nnz, seed, Ahat, d, base + L.off_sketch,
+                            info, s));
+  // S3: QRCP of the sketch -> J, R_sk.
+  CQ_TRY(cqh::launch_qrcp(L.qr, Ahat, d, (int)d, ni, J, Rsk, n, base + L.off_qrcp, info, s));
+  // S4: first-stage rank k_o.
+  CQ_TRY(cqh::launch_rank_stage1(Rsk, n, ni, tol, rn2, bmax, ko_dev, info, s));
+  if (mode == CQRRPT_FP64) {
+    // S5: M_pre = A[:, J[:k_o]] R_sk^{-1}, written into Q.
+    CQ_TRY(cqh::launch_trsm_f64(A, lda, J, Q, ldq, Rsk, n, m, ko_dev, ni, info, s));
+    // S6: G = M_pre^T M_pre.
+    CQ_TRY(cqh::launch_syrk<double>(Q, ldq, m, ko_dev, ni, Gp, G, n, info, s));
+  } else {
+    float* M32 = reinterpret_cast<float*>(base + L.off_mpre32);
+    CQ_TRY(cqh::launch_trsm_mixed(A, lda, J, M32, m, Rsk, n, m, ko_dev, ni, info, s));
+    CQ_TRY(cqh::launch_syrk<float>(M32, m, m, ko_dev, ni, Gp, G, n, info, s));
+  }
+  // S7-S8: R_pre = chol(G) in place, second-stage rank k.
+  CQ_TRY(cqh::launch_cholesky(G, n, ko_dev, ni, k_dev, base + L.off_chol, info, s));
+  // S9: Q = M_pre[:, :k] R_pre^{-1}.
+  if (mode == CQRRPT_FP64) {
+    CQ_TRY(cqh::launch_trsm_f64(Q, ldq, nullptr, Q, ldq, G, n, m, k_dev, ni, info, s));
+  } else {
+    float* M32 = reinterpret_cast<float*>(base + L.off_mpre32);
+    CQ_TRY(cqh::launch_trsm_f32in(M32, m, Q, ldq, G, n, m, k_dev, ni, info, s));
+  }
+  // S10: R = R_pre R_sk[:k, :]; zero Q past the rank.
+  CQ_TRY(cqh::launch_trmm_r(G, n, Rsk, n, R, ldr, ni, k_dev, s));
+  CQ_TRY(cqh::launch_zero_cols(Q, ldq, m, ni, k_dev, s));
+  return CQRRPT_OK;
+}
+
+int cqrrpt_factor(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, int32_t nnz,
+                  uint64_t seed, double tol, double* Q, int64_t ldq, double* R, int64_t ldr,
+                  int64_t* J, int64_t* rank) {
+  const int c = check_common(A, lda, m, n, d, nnz, tol);
+  if (c) return c;
+  if (!Q) return -9;
+  if (ldq < m) return -10;
+  if (!R) return -11;
+  if (ldr < n) return -12;
+  if (!J) return -13;
+  if (!rank) return -14;
+  if (n > kMaxN || d > kMaxD || !cqh::sketch_fits((int)d, nnz)) return CQRRPT_ELIMIT;
+  const size_t wsb = make_layout(m, n, d, nnz, CQRRPT_FP64).total;
+  void* ws = nullptr;
+  cqrrpt_info_t* info = nullptr;
+  if (hipMalloc(&ws, wsb) != hipSuccess) return CQRRPT_EHIP;
+  if (hipMalloc((void**)&info, sizeof(cqrrpt_info_t)) != hipSuccess) {
+    hipFree(ws);
+    return CQRRPT_EHIP;
+  }
+  int rc = cqrrpt_factor_ex(A, lda, m, n, d, nnz, seed, tol, Q, ldq, R, ldr, J, CQRRPT_FP64, ws,
+                            wsb, nullptr, info);
+  cqrrpt_info_t h{};
+  if (rc == CQRRPT_OK) {
+    if (hipMemcpy(&h, info, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) rc = CQRRPT_EHIP;
+    else if (h.status != 0) rc = h.status;
+  }
+  *rank = h.rank;
+  hipFree(info);
+  hipFree(ws);
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,271 @@
+// Shared device helpers for the gfx950 CQRRPT kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/cqrrpt.h"
+
+#define CQ_INLINE __device__ __forceinline__
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+namespace cq {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): the counter-based
+// generator that draws the sketching operator. One round maps
+// (c0, c1, c2, c3) under key (k0, k1) to
+//   (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1, lo(M0*c0)),
+// and the key advances by the Weyl increments between rounds.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+// Fourth counter word of every sketch draw (ASCII "SAS0").
+constexpr uint32_t kSasoDomain = 0x53415330u;
+
+CQ_INLINE void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                             uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += kPhiloxW0;
+      k1 += kPhiloxW1;
+    }
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+  }
+}
+
+// The word stream of one column j of S: word w is output word (w mod 4) of
+// Philox applied to counter (lo32(j), hi32(j), w / 4, "SAS0").
+struct SasoStream {
+  uint32_t k0, k1, j0, j1, blk;
+  uint32_t w[4];
+  int pos;
+
+  CQ_INLINE SasoStream(uint64_t seed, uint64_t col)
+      : k0((uint32_t)seed), k1((uint32_t)(seed >> 32)), j0((uint32_t)col),
+        j1((uint32_t)(col >> 32)), blk(0), pos(4) {}
+
+  CQ_INLINE uint32_t next() {
+    if (pos == 4) {
+      uint32_t c0 = j0, c1 = j1, c2 = blk, c3 = kSasoDomain;
+      philox4x32_10(c0, c1, c2, c3, k0, k1);
+      w[0] = c0; w[1] = c1; w[2] = c2; w[3] = c3;
+      ++blk;
+      pos = 0;
+    }
+    const int p = pos++;
+    return p == 0 ? w[0] : p == 1 ? w[1] : p == 2 ? w[2] : w[3];
+  }
+
+  // Exact uniform integer in [0, s) (Lemire, ACM TOMACS 2019): take the high
+  // word of x*s unless the low word is below (2^32 - s) mod s.
+  CQ_INLINE uint32_t uniform(uint32_t s) {
+    uint64_t prod = (uint64_t)next() * s;
+    uint32_t low = (uint32_t)prod;
+    if (low < s) {
+      const uint32_t thresh = (0u - s) % s;
+      while (low < thresh) {
+        prod = (uint64_t)next() * s;
+        low = (uint32_t)prod;
+      }
+    }
+    return (uint32_t)(prod >> 32);
+  }
+};
+
+// Column j of the SASO: nnz distinct rows by Floyd's sampler (Bentley and
+// Floyd, CACM 1987) and the sign bits (bit t set = negative), word 0.
+CQ_INLINE uint32_t saso_column(uint64_t seed, uint64_t j, int d, int nnz, int* rows) {
+  SasoStream st(seed, j);
+  const uint32_t signs = st.next();
+  for (int t = 0; t < nnz; ++t) {
+    const uint32_t top = (uint32_t)(d - nnz + t);
+    const uint32_t r = st.uniform(top + 1u);
+    bool taken = false;
+    for (int q = 0; q < t; ++q) taken |= (rows[q] == (int)r);
+    rows[t] = taken ? (int)top : (int)r;
+  }
+  return signs;
+}
+
+// ---------------------------------------------------------------------------
+// Reductions with a fixed combination order (butterfly), so results do not
+// depend on timing.
+// ---------------------------------------------------------------------------
+CQ_INLINE double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+CQ_INLINE double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Grid barrier for cooperative launches. Arrival counter plus a generation
+// word, both in device memory; agent-scope release/acquire orders every
+// wave's global writes before the barrier against reads after it. The spin is
+// bounded: on timeout the barrier raises *abort, which every participant
+// checks, so all workgroups leave the kernel.
+// ---------------------------------------------------------------------------
+struct GridBarrier {
+  unsigned* count;
+  unsigned* gen;
+  int* abort;
+  unsigned nblocks;
+};
+
+constexpr unsigned kSpinLimit = 1u << 24;
+
+// Returns false if the barrier was aborted.
+CQ_INLINE bool grid_sync(const GridBarrier& b) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    if (b.nblocks > 1) {
+      const unsigned g = __hip_atomic_load(b.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned arrived =
+          __hip_atomic_fetch_add(b.count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (arrived == b.nblocks - 1) {
+        __hip_atomic_store(b.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(b.gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        unsigned spins = 0;
+        while (__hip_atomic_load(b.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+          if (__hip_atomic_load(b.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            ok = 0;
+            break;
+          }
+          if (++spins > kSpinLimit) {
+            __hip_atomic_store(b.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      if (__hip_atomic_load(b.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// Agent-scope (device-coherent) loads and stores for data exchanged between
+// workgroups of one launch. Relaxed; ordering comes from grid_sync.
+CQ_INLINE double ld_agent(const double* p) {
+  const uint64_t v = __hip_atomic_load(reinterpret_cast<uint64_t*>(const_cast<double*>(p)),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __longlong_as_double((long long)v);
+}
+CQ_INLINE void st_agent(double* p, double x) {
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), (uint64_t)__double_as_longlong(x),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+CQ_INLINE int ld_agent(const int* p) {
+  return __hip_atomic_load(const_cast<int*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+CQ_INLINE void st_agent(int* p, int x) {
+  __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Device-side status word helpers (cqrrpt_info_t lives in device memory).
+CQ_INLINE void set_status(cqrrpt_info_t* info, int code) {
+  __hip_atomic_store(&info->status, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace cq
+
+// Host-side launcher prototypes (defined in the .hip files).
+namespace cqh {
+
+struct Device {
+  int id;
+  int num_cu;
+  size_t lds_per_block;
+};
+const Device& device_info();
+
+hipError_t launch_saso_sample(int64_t m, int d, int nnz, uint64_t seed, int32_t* rows,
+                              int8_t* signs, hipStream_t s);
+
+struct SketchPlan {
+  int ts;       // source rows per sub-chunk
+  int nsub;     // number of sub-chunks
+  int nc;       // columns per workgroup
+  int nchunk;   // row chunks (partial sums)
+  int subs_per_chunk;
+  size_t lds_bytes;
+  size_t seg_bytes, list_bytes, part_bytes;
+};
+SketchPlan plan_sketch(int64_t m, int64_t n, int d, int nnz);
+bool sketch_fits(int d, int nnz);
+size_t sketch_ws_bytes(const SketchPlan& p);
+hipError_t launch_sketch(const SketchPlan& p, const double* A, int64_t lda, int64_t m, int64_t n,
+                         int d, int nnz, uint64_t seed, double* Ahat, int64_t ldah, void* ws,
+                         cqrrpt_info_t* info, hipStream_t s);
+
+struct QrcpPlan {
+  int nblocks;
+  int cols_per_block;
+  bool lds_resident;
+  size_t lds_bytes;
+  size_t stage_bytes, cand_bytes, beta_bytes, sync_bytes;
+};
+QrcpPlan plan_qrcp(int d, int n);
+size_t qrcp_ws_bytes(const QrcpPlan& p);
+hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, int64_t* J,
+                       double* R, int64_t ldr, void* ws, cqrrpt_info_t* info, hipStream_t s);
+
+hipError_t launch_rank_stage1(const double* R, int64_t ldr, int n, double tol, double* rn2,
+                              double* bmax, int64_t* kdev, cqrrpt_info_t* info, hipStream_t s);
+
+// X[:, :k] = B[:, gather[:k]] * R[:k, :k]^{-1}  (right, upper, non-unit).
+hipError_t launch_trsm_f64(const double* B, int64_t ldb, const int64_t* gather, double* X,
+                           int64_t ldx, const double* R, int64_t ldr, int64_t m,
+                           const int64_t* kdev, int kmax, const cqrrpt_info_t* info,
+                           hipStream_t s);
+hipError_t launch_trsm_mixed(const double* B, int64_t ldb, const int64_t* gather, float* X,
+                             int64_t ldx, const double* R, int64_t ldr, int64_t m,
+                             const int64_t* kdev, int kmax, const cqrrpt_info_t* info,
+                             hipStream_t s);
+hipError_t launch_trsm_f32in(const float* B, int64_t ldb, double* X, int64_t ldx,
+                             const double* R, int64_t ldr, int64_t m, const int64_t* kdev,
+                             int kmax, const cqrrpt_info_t* info, hipStream_t s);
+
+int syrk_splits(int64_t m, int kmax);
+size_t syrk_ws_bytes(int64_t m, int kmax);
+template <typename T>
+hipError_t launch_syrk(const T* X, int64_t ldx, int64_t m, const int64_t* kdev, int kmax,
+                       double* partials, double* G, int64_t ldg, const cqrrpt_info_t* info,
+                       hipStream_t s);
+
+size_t chol_ws_bytes(int kmax);
+hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int kmax,
+                           int64_t* k_dev, void* ws, cqrrpt_info_t* info, hipStream_t s);
+
+hipError_t launch_trmm_r(const double* Rpre, int64_t ldp, const double* Rsk, int64_t ldk,
+                         double* R, int64_t ldr, int n, const int64_t* kdev, hipStream_t s);
+hipError_t launch_zero_cols(double* Q, int64_t ldq, int64_t m, int n, const int64_t* kdev,
+                            hipStream_t s);
+
+}  // namespace cqh

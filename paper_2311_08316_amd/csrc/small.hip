@@ -1,0 +1,372 @@
+// The n x n steps of Algorithm 2:
+//   * R_pre = chol(G), stopping at the first pivot that is <= 0 or not finite
+//     (Remark on Cholesky failure, Sec. 3.3: the leading block is exact);
+//   * the second-stage rank (Sec. 3.3): the largest l with
+//     max|diag R_pre[:l,:l]| / min|diag R_pre[:l,:l]| <= sqrt(100) = 10;
+//   * R = R_pre[:k,:k] R_sk[:k,:]   (undo preconditioning);
+//   * zero fill of Q's columns past the rank.
+//
+// The Cholesky factorization is one cooperative launch, right-looking over
+// 64-column blocks with three phases per block separated by grid barriers:
+// factor the diagonal block (one wave, column per lane), solve the block row
+// (one wave per 64-column tile, column per lane), update the trailing upper
+// tiles (one workgroup per tile). G is overwritten by R_pre in place. All
+// reads and writes of G go through device-coherent (agent-scope) accesses
+// because other workgroups produce them within the same launch.
+#include <math.h>
+
+#include "common.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kB = 64;
+constexpr int kLd = kB + 1;
+
+struct CholArgs {
+  double* G;
+  int64_t ldg;
+  const int64_t* ko;
+  int64_t* kout;
+  int* flags;  // flags[0]: failing column (-1 = none) of the current block
+  cqrrpt_info_t* info;
+  cq::GridBarrier bar;
+  double cond_max;
+};
+
+__global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
+  __shared__ double D[kB * kLd];
+  __shared__ double TA[kB * kLd];
+  __shared__ double TB[kB * kLd];
+  __shared__ double rinv[kB];
+  __shared__ int s_fail;
+
+  const int G = gridDim.x;
+  const int g = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  int64_t ko = *a.ko;
+  if (cq::ld_agent(&a.info->status) != 0) ko = 0;
+  const int nblk = (int)((ko + kB - 1) / kB);
+  const int64_t ldg = a.ldg;
+  double* Gm = a.G;
+  int fail = -1;
+
+  auto ldg_at = [&](int64_t i, int64_t j) -> double { return cq::ld_agent(Gm + i + j * ldg); };
+  auto stg_at = [&](int64_t i, int64_t j, double v) { cq::st_agent(Gm + i + j * ldg, v); };
+
+  for (int jb = 0; jb < nblk; ++jb) {
+    const int64_t c0 = (int64_t)jb * kB;
+    // Phase 1: factor the diagonal block.
+    if (g == 0) {
+      for (int e = tid; e < kB * kB; e += kThreads) {
+        const int i = e & (kB - 1);
+        const int j = e >> 6;
+        double v;
+        if (c0 + i < ko && c0 + j < ko)
+          v = i <= j ? ldg_at(c0 + i, c0 + j) : 0.0;
+        else
+          v = i == j ? 1.0 : 0.0;
+        D[i * kLd + j] = v;
+      }
+      if (tid == 0) s_fail = -1;
+      __syncthreads();
+      if (wave == 0) {
+        for (int j = 0; j < kB; ++j) {
+          const double piv = D[j * kLd + j];
+          if (!(piv > 0.0) || !isfinite(piv)) {
+            if (lane == 0) s_fail = (int)(c0 + j);
+            break;
+          }
+          const double rj = sqrt(piv);
+          if (lane == j) D[j * kLd + j] = rj;
+          if (lane > j) D[j * kLd + lane] = D[j * kLd + lane] / rj;
+          __builtin_amdgcn_wave_barrier();
+          if (lane > j) {
+            const double rjl = D[j * kLd + lane];
+            for (int c1 = j + 1; c1 <= lane; ++c1) D[c1 * kLd + lane] -= D[j * kLd + c1] * rjl;
+          }
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < kB * kB; e += kThreads) {
+        const int i = e & (kB - 1);
+        const int j = e >> 6;
+        if (i <= j && c0 + i < ko && c0 + j < ko) stg_at(c0 + i, c0 + j, D[i * kLd + j]);
+      }
+      if (tid == 0) cq::st_agent(&a.flags[0], s_fail);
+    }
+    if (!cq::grid_sync(a.bar)) {
+      if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
+      return;
+    }
+    fail = cq::ld_agent(&a.flags[0]);
+    if (fail >= 0) break;
+    const int nrest = nblk - jb - 1;
+    if (nrest == 0) break;
+
+    // Phase 2: block row R[block, jc] = D^{-T} G[block, jc]. One workgroup
+    // per 64-column tile, one thread per column, 16-row chunks in LDS (TA).
+    bool have_d = false;
+    for (int tile = g; tile < nrest; tile += G) {
+      if (!have_d) {
+        for (int e = tid; e < kB * kB; e += kThreads) {
+          const int i = e & (kB - 1);
+          const int j = e >> 6;
+          double v;
+          if (c0 + i < ko && c0 + j < ko)
+            v = i <= j ? ldg_at(c0 + i, c0 + j) : 0.0;
+          else
+            v = i == j ? 1.0 : 0.0;
+          D[i * kLd + j] = v;
+        }
+        __syncthreads();
+        if (tid < kB) rinv[tid] = 1.0 / D[tid * kLd + tid];
+        __syncthreads();
+        have_d = true;
+      }
+      const int64_t cbase = (int64_t)(jb + 1 + tile) * kB;
+      for (int e = tid; e < kB * kB; e += kThreads) {
+        const int i = e >> 6;
+        const int cl = e & (kB - 1);
+        const int64_t col = cbase + cl;
+        TA[i * kLd + cl] = (col < ko && c0 + i < ko) ? ldg_at(c0 + i, col) : 0.0;
+      }
+      __syncthreads();
+      if (tid < kB) {
+        for (int c = 0; c < kB / 16; ++c) {
+          double y[16];
+#pragma unroll
+          for (int ii = 0; ii < 16; ++ii) y[ii] = TA[(16 * c + ii) * kLd + tid];
+          for (int i = 0; i < 16 * c; ++i) {
+            const double yi = TA[i * kLd + tid];
+            const double* drow = D + i * kLd + 16 * c;
+#pragma unroll
+            for (int ii = 0; ii < 16; ++ii) y[ii] -= drow[ii] * yi;
+          }
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const double yi = y[i] * rinv[16 * c + i];
+            y[i] = yi;
+            const double* drow = D + (16 * c + i) * kLd + 16 * c;
+#pragma unroll
+            for (int ii = 0; ii < 16; ++ii)
+              if (ii > i) y[ii] -= drow[ii] * yi;
+          }
+#pragma unroll
+          for (int ii = 0; ii < 16; ++ii) TA[(16 * c + ii) * kLd + tid] = y[ii];
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < kB * kB; e += kThreads) {
+        const int i = e >> 6;
+        const int cl = e & (kB - 1);
+        const int64_t col = cbase + cl;
+        if (col < ko && c0 + i < ko) stg_at(c0 + i, col, TA[i * kLd + cl]);
+      }
+      __syncthreads();
+    }
+    if (!cq::grid_sync(a.bar)) {
+      if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
+      return;
+    }
+
+    // Phase 3: trailing update G[jc1, jc2] -= R[block, jc1]^T R[block, jc2].
+    const int ntr = nrest * (nrest + 1) / 2;
+    for (int t = g; t < ntr; t += G) {
+      int q = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+      while ((q + 1) * (q + 2) / 2 <= t) ++q;
+      while (q * (q + 1) / 2 > t) --q;
+      const int p = t - q * (q + 1) / 2;  // p <= q
+      const int64_t ca = (int64_t)(jb + 1 + p) * kB;
+      const int64_t cb = (int64_t)(jb + 1 + q) * kB;
+      for (int e = tid; e < kB * kB; e += kThreads) {
+        const int l = e & (kB - 1);
+        const int c = e >> 6;
+        const bool lv = c0 + l < ko;
+        TA[l * kLd + c] = (lv && ca + c < ko) ? ldg_at(c0 + l, ca + c) : 0.0;
+        TB[l * kLd + c] = (lv && cb + c < ko) ? ldg_at(c0 + l, cb + c) : 0.0;
+      }
+      __syncthreads();
+      const int ti = tid >> 4;
+      const int tj = tid & 15;
+      double acc[4][4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+      for (int l = 0; l < kB; ++l) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) av[x] = TA[l * kLd + 4 * ti + x];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) bv[y] = TB[l * kLd + 4 * tj + y];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] += av[x] * bv[y];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          const int64_t i = ca + 4 * ti + x;
+          const int64_t j = cb + 4 * tj + y;
+          if (i <= j && j < ko) stg_at(i, j, ldg_at(i, j) - acc[x][y]);
+        }
+      __syncthreads();
+    }
+    if (!cq::grid_sync(a.bar)) {
+      if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
+      return;
+    }
+  }
+
+  // Second-stage rank on the (possibly truncated) factor.
+  if (g == 0 && tid == 0) {
+    const int64_t kc = fail >= 0 ? fail : ko;
+    int64_t k = 0;
+    double dmax = 0.0, dmin = INFINITY;
+    for (int64_t l = 1; l <= kc; ++l) {
+      const double v = fabs(ldg_at(l - 1, l - 1));
+      dmax = fmax(dmax, v);
+      dmin = fmin(dmin, v);
+      if (dmax / dmin <= a.cond_max) k = l;
+      else break;
+    }
+    a.kout[0] = k;
+    a.info->rank = k;
+    a.info->chol_fail_col = fail >= 0 ? fail : -1;
+  }
+}
+
+__global__ void chol_reset_kernel(unsigned* w, int nw) {
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) w[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// R = R_pre[:k,:k] R_sk[:k,:], written as a full n x n array (zeros below the
+// diagonal and in rows >= k). 64 x 64 tiles, 4 x 4 outputs per thread.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads)
+trmm_kernel(const double* __restrict__ P, int64_t ldp, const double* __restrict__ S, int64_t lds,
+            double* __restrict__ R, int64_t ldr, int n, const int64_t* kdev) {
+  __shared__ double PA[32 * kLd];
+  __shared__ double SB[32 * kLd];
+  const int64_t k = *kdev;
+  const int64_t i0 = (int64_t)blockIdx.x * kB;
+  const int64_t j0 = (int64_t)blockIdx.y * kB;
+  const int tid = threadIdx.x;
+  const int ti = tid >> 4;
+  const int tj = tid & 15;
+  double acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+  if (i0 < k && i0 <= j0 + kB - 1) {
+    const int64_t lend = (j0 + kB) < k ? (j0 + kB) : k;
+    for (int64_t l0 = i0; l0 < lend; l0 += 32) {
+      for (int e = tid; e < 32 * kB; e += kThreads) {
+        const int ii = e & (kB - 1);
+        const int ll = e >> 6;
+        const int64_t i = i0 + ii;
+        const int64_t l = l0 + ll;
+        PA[ll * kLd + ii] = (i < k && l < lend && i <= l) ? P[i + l * ldp] : 0.0;
+        const int jj = e & (kB - 1);
+        const int64_t j = j0 + jj;
+        SB[ll * kLd + jj] = (l < lend && j < n) ? S[l + j * lds] : 0.0;
+      }
+      __syncthreads();
+      for (int ll = 0; ll < 32; ++ll) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) av[x] = PA[ll * kLd + 4 * ti + x];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) bv[y] = SB[ll * kLd + 4 * tj + y];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] += av[x] * bv[y];
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int64_t i = i0 + 4 * ti + x;
+      const int64_t j = j0 + 4 * tj + y;
+      if (i < n && j < n) R[i + j * ldr] = (i < k && i <= j) ? acc[x][y] : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads)
+zero_cols_kernel(double* Q, int64_t ldq, int64_t m, int n, const int64_t* kdev) {
+  const int64_t c = blockIdx.y;
+  if (c < *kdev || c >= n) return;
+  double* col = Q + c * ldq;
+  for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < m;
+       r += (int64_t)gridDim.x * kThreads)
+    col[r] = 0.0;
+}
+
+}  // namespace
+
+namespace cqh {
+
+size_t chol_ws_bytes(int kmax) {
+  (void)kmax;
+  return 256;
+}
+
+hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int kmax,
+                           int64_t* k_dev, void* ws, cqrrpt_info_t* info, hipStream_t s) {
+  (void)kmax;
+  unsigned* w = static_cast<unsigned*>(ws);
+  hipLaunchKernelGGL(chol_reset_kernel, dim3(1), dim3(64), 0, s, w, 8);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  CholArgs a;
+  a.G = G;
+  a.ldg = ldg;
+  a.ko = ko_dev;
+  a.kout = k_dev;
+  a.flags = reinterpret_cast<int*>(w + 4);
+  a.info = info;
+  a.bar.count = w;
+  a.bar.gen = w + 1;
+  a.bar.abort = reinterpret_cast<int*>(w + 2);
+  a.cond_max = 10.0;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)chol_kernel, kThreads, 0);
+  if (e != hipSuccess) return e;
+  int nblocks = device_info().num_cu;
+  if (per_cu < 1) return hipErrorCooperativeLaunchTooLarge;
+  a.bar.nblocks = (unsigned)nblocks;
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel((const void*)chol_kernel, dim3(nblocks), dim3(kThreads), args,
+                                    0, s);
+}
+
+hipError_t launch_trmm_r(const double* Rpre, int64_t ldp, const double* Rsk, int64_t ldk,
+                         double* R, int64_t ldr, int n, const int64_t* kdev, hipStream_t s) {
+  const int nt = (n + kB - 1) / kB;
+  hipLaunchKernelGGL(trmm_kernel, dim3(nt, nt), dim3(kThreads), 0, s, Rpre, ldp, Rsk, ldk, R, ldr,
+                     n, kdev);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_cols(double* Q, int64_t ldq, int64_t m, int n, const int64_t* kdev,
+                            hipStream_t s) {
+  int64_t gx = (m + kThreads - 1) / kThreads;
+  if (gx > 64) gx = 64;
+  hipLaunchKernelGGL(zero_cols_kernel, dim3((unsigned)gx, n), dim3(kThreads), 0, s, Q, ldq, m, n,
+                     kdev);
+  return hipGetLastError();
+}
+
+}  // namespace cqh

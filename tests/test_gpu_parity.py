@@ -1,0 +1,221 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Bars:
+  * sketching operator positions and signs: bit-exact;
+  * sketch: within the componentwise rounding bound of a p-term sum, p the
+    largest number of nonzeros in a row of S;
+  * pivots J and ranks: identical on inputs whose pivot decisions have a
+    margin (well-separated column norms, or the spectra used here);
+  * R: ||R - R_oracle||_F / ||R_oracle||_F <= 1e-12;
+  * Q: ||Q - Q_oracle||_F / ||Q_oracle||_F <= max(1e-12, 100 u cond(R[:, :k]));
+  * reconstruction ||A[:, J] - Q R||_F / ||A||_F and orthogonality
+    ||Q^T Q - I||_2 <= 1e-12 in FP64;
+  * repeated calls are bit-identical.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import cqrrpt_oracle as O
+from paper_2311_08316_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    import paper_2311_08316_amd as pkg
+    pkg.lib()  # raises if the HIP library is not built
+    return pkg
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_gpu(A):
+    t = torch.from_numpy(np.asfortranarray(A)).to("cuda")
+    if t.stride(0) != 1:
+        t = t.t().contiguous().t()
+    return t
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def metrics(A, Q, R, J, k):
+    n = A.shape[1]
+    recon = np.linalg.norm(A[:, J] - Q @ R) / np.linalg.norm(A)
+    Qk = Q[:, :k]
+    orth = np.linalg.norm(Qk.T @ Qk - np.eye(k), 2) if k else 0.0
+    return recon, orth
+
+
+def compare_factor(A, gpu, orc, label, q_extra=1.0):
+    Qg, Rg, Jg, info = gpu
+    Qg, Rg, Jg = to_np(Qg), to_np(Rg), to_np(Jg)
+    k = orc["rank"]
+    assert info.rank == k, f"{label}: rank {info.rank} vs oracle {k}"
+    assert info.rank_stage1 == orc["rank_stage1"], label
+    assert np.array_equal(Jg, orc["J"]), f"{label}: pivots differ"
+    Ro, Qo = orc["R"], orc["Q"]
+    if k == 0:
+        assert not Qg.any() and not Rg.any()
+        return
+    dR = np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro)
+    assert dR <= 1e-12, f"{label}: dR {dR:.3e}"
+    kap = np.linalg.cond(Ro[:k, :k])
+    dQ = np.linalg.norm(Qg - Qo) / np.linalg.norm(Qo)
+    assert dQ <= max(1e-12, 100 * U64 * kap) * q_extra, f"{label}: dQ {dQ:.3e} (cond {kap:.2e})"
+    recon, orth = metrics(A, Qg, Rg, Jg, k)
+    # The reconstruction is exact only when rank(S A) = rank(A) (Theorem on
+    # correctness); otherwise the GPU must reach what the oracle reaches.
+    recon_o, _ = metrics(A, Qo, Ro, orc["J"], k)
+    assert recon <= max(1e-12, recon_o * (1 + 1e-6)), f"{label}: recon {recon:.3e}"
+    assert orth <= 1e-12, f"{label}: orth {orth:.3e}"
+    assert not Qg[:, k:].any() and not Rg[k:, :].any()
+    assert np.array_equal(Rg, np.triu(Rg)) and np.all(np.diag(Rg)[:k] > 0)
+    say(f"  {label}: rank {k} dR {dR:.2e} dQ {dQ:.2e} recon {recon:.2e} orth {orth:.2e}")
+
+
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,d,nnz,seed", [(1, 1, 1, 0), (1000, 13, 4, 0), (5000, 125, 4, 7),
+                                          (777, 640, 8, 2 ** 40 + 3), (300, 32, 32, 5),
+                                          (4097, 1280, 8, 123456789)])
+def test_saso_bit_exact(P, m, d, nnz, seed):
+    say(f"saso m={m} d={d} nnz={nnz} seed={seed}")
+    rows, signs = P.saso_sample(m, d, nnz, seed)
+    ro, so = O.saso_sample(m, d, nnz, seed)
+    assert np.array_equal(to_np(rows).astype(np.int64), ro)
+    assert np.array_equal(to_np(signs).astype(np.int64), so.astype(np.int64))
+
+
+@pytest.mark.parametrize("m,n,d,nnz", [(1000, 7, 13, 4), (5000, 37, 50, 8), (20000, 100, 125, 4),
+                                       (3001, 130, 170, 1), (70000, 20, 25, 8),
+                                       (2000, 9, 640, 32)])
+def test_sketch_parity(P, m, n, d, nnz):
+    say(f"sketch m={m} n={n} d={d} nnz={nnz}")
+    A = W.gaussian_matrix(m, n, seed=m + n)
+    Ag = to_gpu(A)
+    seed = 11
+    S1 = to_np(P.sketch(Ag, d, nnz, seed))
+    S2 = to_np(P.sketch(Ag, d, nnz, seed))
+    assert np.array_equal(S1, S2), "sketch is not deterministic"
+    rows, signs = O.saso_sample(m, d, nnz, seed)
+    So = O.sketch(A, rows, signs, d)
+    absS = O.sketch(np.abs(A), rows, np.ones_like(signs), d)
+    p = np.bincount(rows.ravel(), minlength=d).max()
+    bound = (2 * p + 4) * U64 * absS
+    assert np.all(np.abs(S1 - So) <= bound + 1e-300)
+
+
+@pytest.mark.parametrize("d,n", [(13, 10), (125, 100), (170, 130), (300, 257), (640, 512)])
+def test_qrcp_parity_separated(P, d, n):
+    say(f"qrcp d={d} n={n}")
+    X = W.column_scaled_well_separated(d, n, seed=d * 7 + n, ratio=1.05)
+    Jg, Rg = P.qrcp(to_gpu(X))
+    Jo, Ro = O.qrcp(X)
+    Jg, Rg = to_np(Jg), to_np(Rg)
+    assert np.array_equal(Jg, Jo)
+    assert np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro) <= 1e-13
+    assert np.array_equal(Rg, np.triu(Rg))
+
+
+def test_qrcp_ties_zero_and_identity(P):
+    say("qrcp ties")
+    Jg, Rg = P.qrcp(to_gpu(np.eye(9, 6)))
+    assert to_np(Jg).tolist() == list(range(6))
+    assert np.array_equal(to_np(Rg), np.eye(6))
+    Jg, Rg = P.qrcp(to_gpu(np.zeros((8, 5))))
+    assert to_np(Jg).tolist() == list(range(5)) and not to_np(Rg).any()
+
+
+CASES = [
+    # label, m, n, d, nnz, spectrum kind, cond, tol
+    ("c1-like-small", 3000, 60, 75, 4, "log", 1e6, 1e-14),
+    ("ragged", 5007, 150, 188, 4, "log", 1e4, 1e-14),
+    ("n1", 500, 1, 2, 1, "log", 1.0, 1e-14),
+    ("tiles-and-tail", 20003, 200, 250, 8, "log", 1e8, 1e-14),
+    ("nnz1-gamma1", 4000, 64, 64, 1, "log", 1e3, 1e-14),
+]
+
+
+@pytest.mark.parametrize("label,m,n,d,nnz,kind,cond,tol", CASES)
+def test_factor_parity(P, label, m, n, d, nnz, kind, cond, tol):
+    say(f"factor {label} m={m} n={n} d={d} nnz={nnz}")
+    A = W.spectrum_matrix(m, n, W.logspaced_spectrum(n, cond), seed=m % 97)
+    orc = O.cqrrpt(A, d, nnz, seed=5, tol=tol)
+    gpu = P.factor(to_gpu(A), d, nnz, 5, tol)
+    compare_factor(A, gpu, orc, label)
+
+
+def test_factor_config_10000x100(P):
+    """The 10,000 x 100 workload (cond 1e6, d = 125, nnz = 4, tol 1e-14)."""
+    say("factor 10000x100")
+    A, w = W.make_workload("fp64_10000x100_cond1e6")
+    orc = O.cqrrpt(A, w["d"], w["nnz"], seed=0, tol=w["tol"])
+    gpu = P.factor(to_gpu(A), w["d"], w["nnz"], 0, w["tol"])
+    compare_factor(A, gpu, orc, "10000x100")
+
+
+def test_factor_planted_rank(P):
+    say("factor planted rank")
+    m, n, r = 6000, 96, 40
+    s = np.zeros(n)
+    s[:r] = W.logspaced_spectrum(r, 1e3)
+    A = W.spectrum_matrix(m, n, s, seed=3)
+    for tol in (1e-11, 1e-6):
+        orc = O.cqrrpt(A, 120, 8, seed=9, tol=tol)
+        gpu = P.factor(to_gpu(A), 120, 8, 9, tol)
+        assert orc["rank"] == r
+        Qg, Rg, Jg, info = gpu
+        assert info.rank == r
+        assert np.array_equal(to_np(Jg)[:r], orc["J"][:r])
+        Qn, Rn = to_np(Qg), to_np(Rg)
+        recon, orth = metrics(A, Qn, Rn, to_np(Jg), r)
+        assert recon <= 1e-12 and orth <= 1e-12
+        assert not Qn[:, r:].any() and not Rn[r:, :].any()
+
+
+def test_factor_degenerate(P):
+    say("factor zero / nonfinite")
+    Z = np.zeros((400, 12))
+    Qg, Rg, Jg, info = P.factor(to_gpu(Z), 15, 4, 1, 1e-14)
+    assert info.rank == 0 and info.status == 0
+    assert not to_np(Qg).any() and not to_np(Rg).any()
+    rng = np.random.Generator(np.random.PCG64(1))
+    B = rng.standard_normal((400, 12))
+    B[17, 3] = np.nan
+    with pytest.raises(P.CqrrptError):
+        P.factor(to_gpu(B), 15, 4, 1, 1e-14)
+    # argument checks (LAPACK-style negative codes)
+    with pytest.raises(P.CqrrptError):
+        P.factor(to_gpu(B[:, :5]), 4, 2, 1, 1e-14)   # d < n
+
+
+def test_factor_deterministic_and_sync_entry(P):
+    say("factor determinism")
+    A = W.spectrum_matrix(9000, 80, W.logspaced_spectrum(80, 1e5), seed=4)
+    Ag = to_gpu(A)
+    f = P.Factorization(9000, 80, 100, 4)
+    f.run(Ag, 3, 1e-14)
+    Q1, R1, J1 = to_np(f.Q).copy(), to_np(f.R).copy(), to_np(f.J).copy()
+    f.run(Ag, 3, 1e-14)
+    assert np.array_equal(Q1, to_np(f.Q)) and np.array_equal(R1, to_np(f.R))
+    assert np.array_equal(J1, to_np(f.J))
+    Q2, R2, J2, rank = P.factor_sync(Ag, 100, 4, 3, 1e-14)
+    assert rank == 80
+    assert np.array_equal(Q1, to_np(Q2)) and np.array_equal(R1, to_np(R2))
