@@ -162,6 +162,21 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n,
                      void* ws, size_t ws_bytes, void* stream,
                      cqrrpt_info_t* info);
 
+/* ------------------------------------------------------------------------
+ * Stage timing (diagnostics)
+ * ------------------------------------------------------------------------
+ * cqrrpt_stage_timing(slots): with slots > 0, every later cqrrpt_factor_ex
+ * call records HIP events on its own stream at the boundaries of its eight
+ * stages (sketch, qrcp, rank_stage1, precondition, gram, cholesky, q_solve,
+ * r_product), using event set (call index mod slots); slots = 0 turns timing
+ * off and frees the events. Process-wide setting, guarded by a mutex.
+ * cqrrpt_stage_times(slot, ms): waits for that slot's last event and writes
+ * the eight stage durations in milliseconds to the HOST array ms[8].
+ * Errors: -1 bad slot count / slot, -2 NULL ms, CQRRPT_EHIP. */
+int cqrrpt_stage_timing(int slots);
+int cqrrpt_stage_times(int slot, double* ms);
+const char* cqrrpt_stage_name(int i);
+
 /* Human-readable name of a return code. */
 const char* cqrrpt_status_string(int code);
 

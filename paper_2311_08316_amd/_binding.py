@@ -55,7 +55,13 @@ _SIGS = {
                                         _vp, _i64, _vp, _i64, _vp, ctypes.c_int,
                                         _vp, _sz, _vp, _vp]),
     "cqrrpt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "cqrrpt_stage_timing": (ctypes.c_int, [ctypes.c_int]),
+    "cqrrpt_stage_times": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    "cqrrpt_stage_name": (ctypes.c_char_p, [ctypes.c_int]),
 }
+
+STAGES = ("sketch", "qrcp", "rank_stage1", "precondition", "gram", "cholesky", "q_solve",
+          "r_product")
 
 
 def lib():
@@ -152,6 +158,18 @@ def qrcp(X):
                            wsb, _stream_handle(X.device))
     _check(rc, "cqrrpt_qrcp")
     return J, R
+
+
+def stage_timing(slots):
+    """Record per-stage HIP events for the next calls (ring of ``slots``)."""
+    _check(lib().cqrrpt_stage_timing(slots), "cqrrpt_stage_timing")
+
+
+def stage_times(slot):
+    """Stage durations (ms) of the call that used event set ``slot``."""
+    buf = (ctypes.c_double * len(STAGES))()
+    _check(lib().cqrrpt_stage_times(slot, buf), "cqrrpt_stage_times")
+    return dict(zip(STAGES, list(buf)))
 
 
 def workspace_bytes(m, n, d, nnz, mode=CQRRPT_FP64):

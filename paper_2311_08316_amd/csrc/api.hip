@@ -63,7 +63,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, int nnz, cqrrpt_mode_t mode)
   L.off_qrcp = o; o += align256(cqh::qrcp_ws_bytes(L.qr));
   L.off_rsk = o; o += align256((size_t)n * n * 8);
   L.off_rn2 = o; o += align256((size_t)n * 8);
-  L.off_bmax = o; o += align256((size_t)((n + 255) / 256) * 8);
+  L.off_bmax = o; o += align256((size_t)((n + 63) / 64) * 8);
   L.off_k = o; o += 256;
   L.off_syrkp = o; o += align256(cqh::syrk_ws_bytes(m, (int)n));
   L.off_g = o; o += align256((size_t)n * n * 8);
@@ -88,6 +88,42 @@ int check_common(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, 
 
 int to_status(hipError_t e) { return e == hipSuccess ? CQRRPT_OK : CQRRPT_EHIP; }
 
+// Optional per-stage timing: a ring of event sets, one set per call.
+constexpr int kStages = 8;
+const char* const kStageNames[kStages] = {"sketch", "qrcp", "rank_stage1", "precondition",
+                                          "gram", "cholesky", "q_solve", "r_product"};
+struct StageTimer {
+  std::mutex mu;
+  int slots = 0;
+  int next = 0;
+  hipEvent_t* ev = nullptr;  // [slots][kStages + 1]
+};
+StageTimer& timer() {
+  static StageTimer t;
+  return t;
+}
+
+// Records the boundary events of one call; a no-op when timing is off.
+struct CallMarks {
+  hipEvent_t* ev = nullptr;
+  hipStream_t s = nullptr;
+  void mark(int i) {
+    if (ev) (void)hipEventRecord(ev[i], s);
+  }
+};
+
+CallMarks begin_marks(hipStream_t s) {
+  CallMarks c;
+  StageTimer& t = timer();
+  std::lock_guard<std::mutex> lock(t.mu);
+  if (t.slots > 0) {
+    c.ev = t.ev + (size_t)t.next * (kStages + 1);
+    c.s = s;
+    t.next = (t.next + 1) % t.slots;
+  }
+  return c;
+}
+
 #define CQ_TRY(expr)                       \
   do {                                     \
     hipError_t _e = (expr);                \
@@ -110,6 +146,48 @@ const char* cqrrpt_status_string(int code) {
     default: return code < 0 ? "invalid argument" : "unknown status";
   }
 }
+
+int cqrrpt_stage_timing(int slots) {
+  StageTimer& t = timer();
+  std::lock_guard<std::mutex> lock(t.mu);
+  if (t.ev) {
+    for (int i = 0; i < t.slots * (kStages + 1); ++i) (void)hipEventDestroy(t.ev[i]);
+    delete[] t.ev;
+    t.ev = nullptr;
+  }
+  t.slots = 0;
+  t.next = 0;
+  if (slots <= 0) return CQRRPT_OK;
+  if (slots > 100000) return -1;
+  t.ev = new hipEvent_t[(size_t)slots * (kStages + 1)];
+  for (int i = 0; i < slots * (kStages + 1); ++i) {
+    if (hipEventCreate(&t.ev[i]) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipEventDestroy(t.ev[j]);
+      delete[] t.ev;
+      t.ev = nullptr;
+      return CQRRPT_EHIP;
+    }
+  }
+  t.slots = slots;
+  return CQRRPT_OK;
+}
+
+int cqrrpt_stage_times(int slot, double* ms) {
+  StageTimer& t = timer();
+  std::lock_guard<std::mutex> lock(t.mu);
+  if (slot < 0 || slot >= t.slots) return -1;
+  if (!ms) return -2;
+  hipEvent_t* ev = t.ev + (size_t)slot * (kStages + 1);
+  if (hipEventSynchronize(ev[kStages]) != hipSuccess) return CQRRPT_EHIP;
+  for (int i = 0; i < kStages; ++i) {
+    float f = 0.f;
+    if (hipEventElapsedTime(&f, ev[i], ev[i + 1]) != hipSuccess) return CQRRPT_EHIP;
+    ms[i] = f;
+  }
+  return CQRRPT_OK;
+}
+
+const char* cqrrpt_stage_name(int i) { return (i >= 0 && i < kStages) ? kStageNames[i] : ""; }
 
 int cqrrpt_saso_sample(int64_t m, int64_t d, int32_t nnz, uint64_t seed, int32_t* rows,
                        int8_t* signs, void* stream) {
@@ -215,27 +293,36 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
   double* G = reinterpret_cast<double*>(base + L.off_g);
   const int ni = (int)n;
 
+  CallMarks mk = begin_marks(s);
   hipLaunchKernelGGL(info_init_kernel, dim3(1), dim3(64), 0, s, info);
   CQ_TRY(hipGetLastError());
+  mk.mark(0);
   // S1-S2: sketch.
   CQ_TRY(cqh::launch_sketch(L.sk, A, lda, m, n, (int)d, nnz, seed, Ahat, d, base + L.off_sketch,
                             info, s));
+  mk.mark(1);
   // S3: QRCP of the sketch -> J, R_sk.
   CQ_TRY(cqh::launch_qrcp(L.qr, Ahat, d, (int)d, ni, J, Rsk, n, base + L.off_qrcp, info, s));
+  mk.mark(2);
   // S4: first-stage rank k_o.
   CQ_TRY(cqh::launch_rank_stage1(Rsk, n, ni, tol, rn2, bmax, ko_dev, info, s));
+  mk.mark(3);
   if (mode == CQRRPT_FP64) {
     // S5: M_pre = A[:, J[:k_o]] R_sk^{-1}, written into Q.
     CQ_TRY(cqh::launch_trsm_f64(A, lda, J, Q, ldq, Rsk, n, m, ko_dev, ni, info, s));
+    mk.mark(4);
     // S6: G = M_pre^T M_pre.
     CQ_TRY(cqh::launch_syrk<double>(Q, ldq, m, ko_dev, ni, Gp, G, n, info, s));
   } else {
     float* M32 = reinterpret_cast<float*>(base + L.off_mpre32);
     CQ_TRY(cqh::launch_trsm_mixed(A, lda, J, M32, m, Rsk, n, m, ko_dev, ni, info, s));
+    mk.mark(4);
     CQ_TRY(cqh::launch_syrk<float>(M32, m, m, ko_dev, ni, Gp, G, n, info, s));
   }
+  mk.mark(5);
   // S7-S8: R_pre = chol(G) in place, second-stage rank k.
   CQ_TRY(cqh::launch_cholesky(G, n, ko_dev, ni, k_dev, base + L.off_chol, info, s));
+  mk.mark(6);
   // S9: Q = M_pre[:, :k] R_pre^{-1}.
   if (mode == CQRRPT_FP64) {
     CQ_TRY(cqh::launch_trsm_f64(Q, ldq, nullptr, Q, ldq, G, n, m, k_dev, ni, info, s));
@@ -243,9 +330,11 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
     float* M32 = reinterpret_cast<float*>(base + L.off_mpre32);
     CQ_TRY(cqh::launch_trsm_f32in(M32, m, Q, ldq, G, n, m, k_dev, ni, info, s));
   }
+  mk.mark(7);
   // S10: R = R_pre R_sk[:k, :]; zero Q past the rank.
   CQ_TRY(cqh::launch_trmm_r(G, n, Rsk, n, R, ldr, ni, k_dev, s));
   CQ_TRY(cqh::launch_zero_cols(Q, ldq, m, ni, k_dev, s));
+  mk.mark(8);
   return CQRRPT_OK;
 }
 

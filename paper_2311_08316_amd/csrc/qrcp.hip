@@ -20,8 +20,9 @@
 //     v = x / (alpha - beta) with v[0] = 1;
 //   * each wave applies I - tau v v^T to one owned column at a time and
 //     recomputes that column's norm over rows i+1..d-1;
-//   * each workgroup publishes its best remaining column (and stages its
-//     rows i+1..d-1), then all meet at one grid barrier.
+//   * each workgroup publishes its best remaining column (norm, index, and
+//     rows i+1..d-1 staged in a global slot), then releases a per-slot step
+//     tag; step i+1 starts by waiting on all G tags (no shared counter).
 // Reductions are fixed-shape wave butterflies, so the result is
 // deterministic.
 #include <limits.h>
@@ -43,13 +44,28 @@ struct QrcpArgs {
   int64_t* J;
   double* R;
   int64_t ldr;
-  double* stage;     // [2][G][d]
-  double* cand_val;  // [2][G]
-  int* cand_col;     // [2][G]
+  double* stage;     // [2][G][d]   candidate column rows, per parity and workgroup
+  double* cand_val;  // [2][G]      candidate norm
+  int* cand_col;     // [2][G]      candidate column (-1: none left)
+  unsigned* tag;     // [2][G]      step + 1 once the slot is published
   double* beta;      // [n]
-  cq::GridBarrier bar;
+  int* abort;
   cqrrpt_info_t* info;
 };
+
+// Spin until *tag == want (acquire). Bounded: on timeout raise *abort.
+CQ_INLINE bool wait_tag(unsigned* tag, unsigned want, int* abort) {
+  unsigned spins = 0;
+  while (__hip_atomic_load(tag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != want) {
+    if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    if (++spins > cq::kSpinLimit) {
+      __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
 
 template <bool kLds>
 __global__ void __launch_bounds__(kThreads) qrcp_kernel(QrcpArgs a) {
@@ -60,8 +76,7 @@ __global__ void __launch_bounds__(kThreads) qrcp_kernel(QrcpArgs a) {
   __shared__ int s_step[kMaxCols];
   __shared__ double s_rv[kWaves];
   __shared__ int s_rc[kWaves];
-  __shared__ double s_alpha, s_beta, s_tau, s_nup;
-  __shared__ int s_p, s_bs;
+  __shared__ int s_bad;
 
   const int G = gridDim.x;
   const int g = blockIdx.x;
@@ -71,8 +86,10 @@ __global__ void __launch_bounds__(kThreads) qrcp_kernel(QrcpArgs a) {
   const int d = a.d;
   const int n = a.n;
   const int ncol = g < n ? (n - 1 - g) / G + 1 : 0;
-  double* xv = smem;                          // pivot column, then the reflector
-  double* cstore = smem + ((d + 1) & ~1);     // owned columns (LDS mode)
+  const int dpad = (d + 1) & ~1;
+  double* xv = smem;                   // pivot column rows i..d-1
+  double* vv = smem + dpad;            // reflector v (v[0] = 1)
+  double* cstore = smem + 2 * dpad;    // owned columns (LDS mode)
 
   auto col = [&](int s) -> double* {
     if (kLds) return cstore + (size_t)s * d;
@@ -89,6 +106,7 @@ __global__ void __launch_bounds__(kThreads) qrcp_kernel(QrcpArgs a) {
     return;
   }
 
+  if (tid == 0) s_bad = 0;
   if (kLds) {
     for (int s = 0; s < ncol; ++s) {
       const double* src = a.X + (int64_t)(g + s * G) * a.ldx;
@@ -109,47 +127,70 @@ __global__ void __launch_bounds__(kThreads) qrcp_kernel(QrcpArgs a) {
   }
   __syncthreads();
 
-  // Publish this workgroup's best remaining column for the step that works
-  // on rows row0..d-1.
-  auto publish = [&](int par, int row0) {
-    if (tid == 0) {
-      double bv = -1.0;
-      int bc = -1, bs = -1;
-      for (int s = 0; s < ncol; ++s) {
-        if (s_alive[s] && s_norm[s] > bv) {
-          bv = s_norm[s];
-          bc = g + s * G;
-          bs = s;
-        }
-      }
-      cq::st_agent(&a.cand_val[par * G + g], bv);
-      cq::st_agent(&a.cand_col[par * G + g], bc);
-      s_bs = bs;
+  // Publish this workgroup's best remaining column for step `step` (rows
+  // row0..d-1), then release the slot's tag. Every wave finds the best slot
+  // itself (larger norm, then smaller slot = smaller column index).
+  auto publish = [&](int step, int row0) {
+    const int par = step & 1;
+    double bv = -1.0;
+    int bs = kMaxCols;
+    if (lane < ncol && s_alive[lane]) {
+      bv = s_norm[lane];
+      bs = lane;
     }
-    __syncthreads();
-    const int bs = s_bs;
-    if (bs >= 0) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ov = __shfl_xor(bv, off, cq::kWave);
+      const int os = __shfl_xor(bs, off, cq::kWave);
+      if (ov > bv || (ov == bv && os < bs)) {
+        bv = ov;
+        bs = os;
+      }
+    }
+    if (bs < kMaxCols) {
       const double* cs = col(bs);
       double* dst = a.stage + ((size_t)par * G + g) * d;
       for (int r = tid; r < d - row0; r += kThreads) cq::st_agent(dst + r, cs[row0 + r]);
     }
+    if (tid == 0) {
+      cq::st_agent(&a.cand_val[par * G + g], bs < kMaxCols ? bv : -1.0);
+      cq::st_agent(&a.cand_col[par * G + g], bs < kMaxCols ? g + bs * G : -1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0)
+      __hip_atomic_store(&a.tag[par * G + g], (unsigned)(step + 1), __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  };
+
+  // Wait until every workgroup published step `step`; returns false on abort.
+  auto gather = [&](int step, double& v, int& c) -> bool {
+    const int par = step & 1;
+    v = -2.0;
+    c = INT_MAX;
+    if (tid < G) {
+      if (!wait_tag(&a.tag[par * G + tid], (unsigned)(step + 1), a.abort)) s_bad = 1;
+      v = cq::ld_agent(&a.cand_val[par * G + tid]);
+      c = cq::ld_agent(&a.cand_col[par * G + tid]);
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return s_bad == 0;
   };
 
   publish(0, 0);
-  if (!cq::grid_sync(a.bar)) {
-    if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
-    return;
-  }
 
   for (int i = 0; i < n; ++i) {
     const int par = i & 1;
     // Global argmax of the published candidates: larger norm, then smaller column.
-    double v = -2.0;
-    int c = INT_MAX;
-    if (tid < G) {
-      v = cq::ld_agent(&a.cand_val[par * G + tid]);
-      c = cq::ld_agent(&a.cand_col[par * G + tid]);
+    double v;
+    int c;
+    if (!gather(i, v, c)) {
+      if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
+      return;
     }
+    // (gather's __syncthreads precedes these LDS writes; the previous step's
+    // readers of s_rv finished before that barrier.)
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
       const double ov = __shfl_xor(v, off, cq::kWave);
@@ -164,53 +205,34 @@ __global__ void __launch_bounds__(kThreads) qrcp_kernel(QrcpArgs a) {
       s_rc[wave] = c;
     }
     __syncthreads();
-    if (tid == 0) {
-      double bv = s_rv[0];
-      int bc = s_rc[0];
-      for (int w = 1; w < kWaves; ++w) {
-        if (s_rv[w] > bv || (s_rv[w] == bv && s_rc[w] < bc)) {
-          bv = s_rv[w];
-          bc = s_rc[w];
-        }
+    double nup = s_rv[0];
+    int p = s_rc[0];
+    for (int w = 1; w < kWaves; ++w) {
+      if (s_rv[w] > nup || (s_rv[w] == nup && s_rc[w] < p)) {
+        nup = s_rv[w];
+        p = s_rc[w];
       }
-      s_p = bc;
-      s_nup = bv;
     }
-    __syncthreads();
-    const int p = s_p;
-    const double nup = s_nup;
     const int owner = p % G;
     const int len = d - i;
     const double* src = a.stage + ((size_t)par * G + owner) * d;
     for (int r = tid; r < len; r += kThreads) xv[r] = cq::ld_agent(src + r);
     __syncthreads();
-    if (tid == 0) {
-      const double alpha = xv[0];
-      double beta = 0.0, tau = 0.0;
-      if (nup != 0.0) {
-        beta = alpha >= 0.0 ? -nup : nup;
-        tau = (beta - alpha) / beta;
-      }
-      s_alpha = alpha;
-      s_beta = beta;
-      s_tau = tau;
+    const double alpha = xv[0];
+    double beta = 0.0, tau = 0.0;
+    if (nup != 0.0) {
+      beta = alpha >= 0.0 ? -nup : nup;
+      tau = (beta - alpha) / beta;
+      const double denom = alpha - beta;
+      for (int r = tid; r < len; r += kThreads) vv[r] = r == 0 ? 1.0 : xv[r] / denom;
     }
-    __syncthreads();
-    const double tau = s_tau;
-    if (tau != 0.0) {
-      const double denom = s_alpha - s_beta;
-      for (int r = 1 + tid; r < len; r += kThreads) xv[r] = xv[r] / denom;
-    }
-    if (tid == 0) {
-      xv[0] = 1.0;
-      if (g == owner) {
-        const int sp = (p - g) / G;
-        s_alive[sp] = 0;
-        s_step[sp] = i;
-        s_bdiag[sp] = s_beta;
-        a.J[i] = p;
-        cq::st_agent(&a.beta[i], s_beta);
-      }
+    if (tid == 0 && g == owner) {
+      const int sp = (p - g) / G;
+      s_alive[sp] = 0;
+      s_step[sp] = i;
+      s_bdiag[sp] = beta;
+      a.J[i] = p;
+      cq::st_agent(&a.beta[i], beta);
     }
     __syncthreads();
 
@@ -219,10 +241,10 @@ __global__ void __launch_bounds__(kThreads) qrcp_kernel(QrcpArgs a) {
       double* cs = col(s);
       if (tau != 0.0) {
         double w = 0.0;
-        for (int r = i + lane; r < d; r += cq::kWave) w += xv[r - i] * cs[r];
+        for (int r = i + lane; r < d; r += cq::kWave) w += vv[r - i] * cs[r];
         w = cq::wave_sum(w);
         const double tw = tau * w;
-        for (int r = i + lane; r < d; r += cq::kWave) cs[r] -= tw * xv[r - i];
+        for (int r = i + lane; r < d; r += cq::kWave) cs[r] -= tw * vv[r - i];
       }
       double nn = 0.0;
       for (int r = i + 1 + lane; r < d; r += cq::kWave) nn += cs[r] * cs[r];
@@ -230,16 +252,16 @@ __global__ void __launch_bounds__(kThreads) qrcp_kernel(QrcpArgs a) {
       if (lane == 0) s_norm[s] = sqrt(nn);
     }
     __syncthreads();
-    if (i == n - 1) break;
-    publish(par ^ 1, i + 1);
-    if (!cq::grid_sync(a.bar)) {
+    publish(i + 1, i + 1);
+  }
+  // The last publish (step n) acts as a final barrier: every beta is out.
+  {
+    double v;
+    int c;
+    if (!gather(n, v, c)) {
       if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
       return;
     }
-  }
-  if (!cq::grid_sync(a.bar)) {
-    if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
-    return;
   }
 
   // Assemble R: owned column c was eliminated at step sc, so it is column sc
@@ -261,8 +283,7 @@ __global__ void __launch_bounds__(kThreads) qrcp_kernel(QrcpArgs a) {
   }
 }
 
-// Small setup kernel: zero the barrier words and reset the status fields a
-// factorization owns.
+// Zero the step tags and the abort word before a cooperative launch.
 __global__ void qrcp_reset_kernel(unsigned* sync_words, int nwords) {
   for (int i = threadIdx.x; i < nwords; i += blockDim.x) sync_words[i] = 0u;
 }
@@ -276,24 +297,28 @@ __global__ void qrcp_reset_kernel(unsigned* sync_words, int nwords) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads)
 rank1_rows_kernel(const double* __restrict__ R, int64_t ldr, int n, double* rn2, double* bmax) {
+  // 64 rows per block; the four waves sum interleaved column ranges, combined
+  // in wave order.
+  __shared__ double s_part[kWaves][64];
   __shared__ double s_max[kWaves];
-  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
   double s = 0.0, mx = 0.0;
   if (i < n) {
-    for (int j = i; j < n; ++j) {
+    for (int j = i + wave; j < n; j += kWaves) {
       const double v = R[i + (int64_t)j * ldr];
       s += v * v;
       mx = fmax(mx, fabs(v));
     }
-    rn2[i] = s;
   }
+  s_part[wave][lane] = s;
   mx = cq::wave_max(mx);
-  if ((threadIdx.x & 63) == 0) s_max[threadIdx.x / 64] = mx;
+  if (lane == 0) s_max[wave] = mx;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double b = s_max[0];
-    for (int w = 1; w < kWaves; ++w) b = fmax(b, s_max[w]);
-    bmax[blockIdx.x] = b;
+  if (wave == 0) {
+    if (i < n) rn2[i] = ((s_part[0][lane] + s_part[1][lane]) + s_part[2][lane]) + s_part[3][lane];
+    if (lane == 0) bmax[blockIdx.x] = fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3]));
   }
 }
 
@@ -326,7 +351,7 @@ rank1_final_kernel(const double* rn2, const double* bmax, int nb, int n, double 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t qrcp_lds_bytes(int d, int cols, bool lds) {
-  size_t b = (size_t)((d + 1) & ~1) * 8;
+  size_t b = (size_t)2 * ((d + 1) & ~1) * 8;
   if (lds) b += (size_t)cols * d * 8;
   return b;
 }
@@ -347,7 +372,9 @@ QrcpPlan plan_qrcp(int d, int n) {
   p.lds_resident = qrcp_lds_bytes(d, cols, true) <= dev.lds_per_block;
   p.lds_bytes = qrcp_lds_bytes(d, cols, p.lds_resident);
   p.stage_bytes = align256((size_t)2 * G * d * 8);
-  p.cand_bytes = align256((size_t)2 * G * 8) + align256((size_t)2 * G * 4);
+  // candidate norms, columns and tags, per parity and workgroup
+  p.cand_bytes = align256((size_t)2 * G * 8) + align256((size_t)2 * G * 4) +
+                 align256((size_t)2 * G * 4);
   p.beta_bytes = align256((size_t)n * 8);
   p.sync_bytes = 256;
   return p;
@@ -359,7 +386,8 @@ size_t qrcp_ws_bytes(const QrcpPlan& p) {
 
 hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, int64_t* J,
                        double* R, int64_t ldr, void* ws, cqrrpt_info_t* info, hipStream_t s) {
-  if (p.cols_per_block > kMaxCols) return hipErrorInvalidValue;
+  if (p.cols_per_block > kMaxCols || p.nblocks > kThreads) return hipErrorInvalidValue;
+  const int G = p.nblocks;
   char* base = static_cast<char*>(ws);
   QrcpArgs a;
   a.X = X;
@@ -370,18 +398,21 @@ hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, 
   a.R = R;
   a.ldr = ldr;
   a.stage = reinterpret_cast<double*>(base);
-  a.cand_val = reinterpret_cast<double*>(base + p.stage_bytes);
-  a.cand_col = reinterpret_cast<int*>(base + p.stage_bytes + align256((size_t)2 * p.nblocks * 8));
+  char* cb = base + p.stage_bytes;
+  a.cand_val = reinterpret_cast<double*>(cb);
+  a.cand_col = reinterpret_cast<int*>(cb + align256((size_t)2 * G * 8));
+  a.tag = reinterpret_cast<unsigned*>(cb + align256((size_t)2 * G * 8) +
+                                      align256((size_t)2 * G * 4));
   a.beta = reinterpret_cast<double*>(base + p.stage_bytes + p.cand_bytes);
-  unsigned* sync = reinterpret_cast<unsigned*>(base + p.stage_bytes + p.cand_bytes + p.beta_bytes);
-  a.bar.count = sync;
-  a.bar.gen = sync + 1;
-  a.bar.abort = reinterpret_cast<int*>(sync + 2);
-  a.bar.nblocks = (unsigned)p.nblocks;
+  a.abort = reinterpret_cast<int*>(base + p.stage_bytes + p.cand_bytes + p.beta_bytes);
   a.info = info;
 
-  hipLaunchKernelGGL(qrcp_reset_kernel, dim3(1), dim3(64), 0, s, sync, 4);
+  // Zero the tags and the abort word before the cooperative launch.
+  hipLaunchKernelGGL(qrcp_reset_kernel, dim3(1), dim3(256), 0, s, a.tag, 2 * G);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(qrcp_reset_kernel, dim3(1), dim3(64), 0, s, (unsigned*)a.abort, 1);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
 
   const void* fn = p.lds_resident ? (const void*)qrcp_kernel<true> : (const void*)qrcp_kernel<false>;
@@ -398,7 +429,7 @@ hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, 
 
 hipError_t launch_rank_stage1(const double* R, int64_t ldr, int n, double tol, double* rn2,
                               double* bmax, int64_t* kdev, cqrrpt_info_t* info, hipStream_t s) {
-  const int nb = (n + kThreads - 1) / kThreads;
+  const int nb = (n + 63) / 64;
   hipLaunchKernelGGL(rank1_rows_kernel, dim3(nb), dim3(kThreads), 0, s, R, ldr, n, rn2, bmax);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

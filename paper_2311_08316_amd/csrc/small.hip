@@ -7,12 +7,16 @@
 //   * zero fill of Q's columns past the rank.
 //
 // The Cholesky factorization is one cooperative launch, right-looking over
-// 64-column blocks with three phases per block separated by grid barriers:
-// factor the diagonal block (one wave, column per lane), solve the block row
-// (one wave per 64-column tile, column per lane), update the trailing upper
-// tiles (one workgroup per tile). G is overwritten by R_pre in place. All
-// reads and writes of G go through device-coherent (agent-scope) accesses
-// because other workgroups produce them within the same launch.
+// 64-column blocks, two phases per block separated by grid barriers:
+//   1. one workgroup factors the diagonal block D (one wave, a column per
+//      lane) and forms D^{-1} (a column per thread, back substitution);
+//   2. every workgroup takes trailing tiles (p, q), p <= q: it forms the
+//      block-row tiles Y_p = D^{-T} G[block, p] and Y_q as small products
+//      with D^{-1}, writes Y_p as R_pre[block, p] when p == q, and applies
+//      G[p, q] -= Y_p^T Y_q.
+// G is overwritten by R_pre in place (upper triangle). Cross-workgroup data
+// goes through global memory ordered by agent-scope release/acquire fences
+// at the barriers.
 #include <math.h>
 
 #include "common.h"
@@ -28,17 +32,47 @@ struct CholArgs {
   int64_t ldg;
   const int64_t* ko;
   int64_t* kout;
-  int* flags;  // flags[0]: failing column (-1 = none) of the current block
+  int* flags;    // flags[0]: failing column (-1 = none) of the current block
+  double* dinv;  // kB x kB inverse of the current diagonal block
+  double* panel; // kB x ldg: block row of R_pre produced by the last phase 2
   cqrrpt_info_t* info;
   cq::GridBarrier bar;
   double cond_max;
 };
 
+CQ_INLINE bool chol_sync(const cq::GridBarrier& b) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  const bool ok = cq::grid_sync(b);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return ok;
+}
+
+// C[4x4 per thread] = A^T B over l < kB for 64 x 64 LDS tiles (A, B stored
+// [l][c] with leading dimension kLd); A may be restricted to l <= row (upper).
+template <bool kUpperA>
+CQ_INLINE void tile_atb(const double* A, const double* B, int ti, int tj, double (&acc)[4][4]) {
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+  const int lmax = kUpperA ? 4 * ti + 4 : kB;
+  for (int l = 0; l < lmax; ++l) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) av[x] = A[l * kLd + 4 * ti + x];
+#pragma unroll
+    for (int y = 0; y < 4; ++y) bv[y] = B[l * kLd + 4 * tj + y];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] += av[x] * bv[y];
+  }
+}
+
 __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
   __shared__ double D[kB * kLd];
-  __shared__ double TA[kB * kLd];
-  __shared__ double TB[kB * kLd];
-  __shared__ double rinv[kB];
+  __shared__ double YA[kB * kLd];
+  __shared__ double YB[kB * kLd];
   __shared__ int s_fail;
 
   const int G = gridDim.x;
@@ -46,6 +80,8 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
+  const int ti = tid >> 4;
+  const int tj = tid & 15;
   int64_t ko = *a.ko;
   if (cq::ld_agent(&a.info->status) != 0) ko = 0;
   const int nblk = (int)((ko + kB - 1) / kB);
@@ -53,19 +89,27 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
   double* Gm = a.G;
   int fail = -1;
 
-  auto ldg_at = [&](int64_t i, int64_t j) -> double { return cq::ld_agent(Gm + i + j * ldg); };
-  auto stg_at = [&](int64_t i, int64_t j, double v) { cq::st_agent(Gm + i + j * ldg, v); };
-
   for (int jb = 0; jb < nblk; ++jb) {
     const int64_t c0 = (int64_t)jb * kB;
-    // Phase 1: factor the diagonal block.
+    // The previous block row of R_pre (columns past its diagonal block) was
+    // staged by phase 2; nobody reads those rows of G any more, so copy it in.
+    if (jb > 0) {
+      const int64_t pr = c0 - kB;
+      const int64_t ncopy = (ko - c0) * kB;
+      for (int64_t e = (int64_t)g * kThreads + tid; e < ncopy; e += (int64_t)G * kThreads) {
+        const int l = (int)(e % kB);
+        const int64_t col = c0 + e / kB;
+        Gm[(pr + l) + col * ldg] = a.panel[l + col * kB];
+      }
+    }
+    // Phase 1: factor the diagonal block and invert it.
     if (g == 0) {
       for (int e = tid; e < kB * kB; e += kThreads) {
         const int i = e & (kB - 1);
         const int j = e >> 6;
         double v;
         if (c0 + i < ko && c0 + j < ko)
-          v = i <= j ? ldg_at(c0 + i, c0 + j) : 0.0;
+          v = i <= j ? Gm[(c0 + i) + (c0 + j) * ldg] : 0.0;
         else
           v = i == j ? 1.0 : 0.0;
         D[i * kLd + j] = v;
@@ -91,14 +135,30 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
         }
       }
       __syncthreads();
+      // Column t of D^{-1} (upper): back substitution D x = e_t.
+      if (tid < kB && s_fail < 0) {
+        const int t = tid;
+        double* x = YA;  // column-major scratch: x[i * kLd + t]
+        for (int i = kB - 1; i >= 0; --i) {
+          double v = 0.0;
+          if (i <= t) {
+            double acc = (i == t) ? 1.0 : 0.0;
+            for (int l = i + 1; l <= t; ++l) acc -= D[i * kLd + l] * x[l * kLd + t];
+            v = acc / D[i * kLd + i];
+          }
+          x[i * kLd + t] = v;
+        }
+      }
+      __syncthreads();
       for (int e = tid; e < kB * kB; e += kThreads) {
         const int i = e & (kB - 1);
         const int j = e >> 6;
-        if (i <= j && c0 + i < ko && c0 + j < ko) stg_at(c0 + i, c0 + j, D[i * kLd + j]);
+        if (i <= j && c0 + i < ko && c0 + j < ko) Gm[(c0 + i) + (c0 + j) * ldg] = D[i * kLd + j];
+        a.dinv[i + j * kB] = YA[i * kLd + j];
       }
       if (tid == 0) cq::st_agent(&a.flags[0], s_fail);
     }
-    if (!cq::grid_sync(a.bar)) {
+    if (!chol_sync(a.bar)) {
       if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
       return;
     }
@@ -107,74 +167,10 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
     const int nrest = nblk - jb - 1;
     if (nrest == 0) break;
 
-    // Phase 2: block row R[block, jc] = D^{-T} G[block, jc]. One workgroup
-    // per 64-column tile, one thread per column, 16-row chunks in LDS (TA).
-    bool have_d = false;
-    for (int tile = g; tile < nrest; tile += G) {
-      if (!have_d) {
-        for (int e = tid; e < kB * kB; e += kThreads) {
-          const int i = e & (kB - 1);
-          const int j = e >> 6;
-          double v;
-          if (c0 + i < ko && c0 + j < ko)
-            v = i <= j ? ldg_at(c0 + i, c0 + j) : 0.0;
-          else
-            v = i == j ? 1.0 : 0.0;
-          D[i * kLd + j] = v;
-        }
-        __syncthreads();
-        if (tid < kB) rinv[tid] = 1.0 / D[tid * kLd + tid];
-        __syncthreads();
-        have_d = true;
-      }
-      const int64_t cbase = (int64_t)(jb + 1 + tile) * kB;
-      for (int e = tid; e < kB * kB; e += kThreads) {
-        const int i = e >> 6;
-        const int cl = e & (kB - 1);
-        const int64_t col = cbase + cl;
-        TA[i * kLd + cl] = (col < ko && c0 + i < ko) ? ldg_at(c0 + i, col) : 0.0;
-      }
-      __syncthreads();
-      if (tid < kB) {
-        for (int c = 0; c < kB / 16; ++c) {
-          double y[16];
-#pragma unroll
-          for (int ii = 0; ii < 16; ++ii) y[ii] = TA[(16 * c + ii) * kLd + tid];
-          for (int i = 0; i < 16 * c; ++i) {
-            const double yi = TA[i * kLd + tid];
-            const double* drow = D + i * kLd + 16 * c;
-#pragma unroll
-            for (int ii = 0; ii < 16; ++ii) y[ii] -= drow[ii] * yi;
-          }
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const double yi = y[i] * rinv[16 * c + i];
-            y[i] = yi;
-            const double* drow = D + (16 * c + i) * kLd + 16 * c;
-#pragma unroll
-            for (int ii = 0; ii < 16; ++ii)
-              if (ii > i) y[ii] -= drow[ii] * yi;
-          }
-#pragma unroll
-          for (int ii = 0; ii < 16; ++ii) TA[(16 * c + ii) * kLd + tid] = y[ii];
-        }
-      }
-      __syncthreads();
-      for (int e = tid; e < kB * kB; e += kThreads) {
-        const int i = e >> 6;
-        const int cl = e & (kB - 1);
-        const int64_t col = cbase + cl;
-        if (col < ko && c0 + i < ko) stg_at(c0 + i, col, TA[i * kLd + cl]);
-      }
-      __syncthreads();
-    }
-    if (!cq::grid_sync(a.bar)) {
-      if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
-      return;
-    }
-
-    // Phase 3: trailing update G[jc1, jc2] -= R[block, jc1]^T R[block, jc2].
+    // Phase 2: trailing tiles (p, q), p <= q, with the block-row tiles formed
+    // on the fly as D^{-T} G[block, p].
     const int ntr = nrest * (nrest + 1) / 2;
+    bool have_dinv = false;
     for (int t = g; t < ntr; t += G) {
       int q = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
       while ((q + 1) * (q + 2) / 2 <= t) ++q;
@@ -182,43 +178,58 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
       const int p = t - q * (q + 1) / 2;  // p <= q
       const int64_t ca = (int64_t)(jb + 1 + p) * kB;
       const int64_t cb = (int64_t)(jb + 1 + q) * kB;
+      const bool same = p == q;
+      if (!have_dinv) {
+        for (int e = tid; e < kB * kB; e += kThreads) {
+          const int i = e & (kB - 1);
+          const int j = e >> 6;
+          D[i * kLd + j] = a.dinv[i + j * kB];
+        }
+        have_dinv = true;
+      }
       for (int e = tid; e < kB * kB; e += kThreads) {
         const int l = e & (kB - 1);
         const int c = e >> 6;
         const bool lv = c0 + l < ko;
-        TA[l * kLd + c] = (lv && ca + c < ko) ? ldg_at(c0 + l, ca + c) : 0.0;
-        TB[l * kLd + c] = (lv && cb + c < ko) ? ldg_at(c0 + l, cb + c) : 0.0;
+        YA[l * kLd + c] = (lv && ca + c < ko) ? Gm[(c0 + l) + (ca + c) * ldg] : 0.0;
+        if (!same) YB[l * kLd + c] = (lv && cb + c < ko) ? Gm[(c0 + l) + (cb + c) * ldg] : 0.0;
       }
       __syncthreads();
-      const int ti = tid >> 4;
-      const int tj = tid & 15;
       double acc[4][4];
+      // Y_p = D^{-T} G[block, p]: (D^{-1})^T is lower, so row i uses l <= i.
+      tile_atb<true>(D, YA, ti, tj, acc);
+      double accb[4][4];
+      if (!same) tile_atb<true>(D, YB, ti, tj, accb);
+      __syncthreads();
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-      for (int l = 0; l < kB; ++l) {
-        double av[4], bv[4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x) av[x] = TA[l * kLd + 4 * ti + x];
-#pragma unroll
-        for (int y = 0; y < 4; ++y) bv[y] = TB[l * kLd + 4 * tj + y];
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] += av[x] * bv[y];
+        for (int y = 0; y < 4; ++y) {
+          YA[(4 * ti + x) * kLd + 4 * tj + y] = acc[x][y];
+          if (!same) YB[(4 * ti + x) * kLd + 4 * tj + y] = accb[x][y];
+        }
+      __syncthreads();
+      if (same) {
+        // Block row of R_pre, staged by the diagonal task of column p (other
+        // tasks of this phase still read G[block, p]).
+        for (int e = tid; e < kB * kB; e += kThreads) {
+          const int l = e & (kB - 1);
+          const int c = e >> 6;
+          if (ca + c < ko) a.panel[l + (ca + c) * kB] = YA[l * kLd + c];
+        }
       }
+      tile_atb<false>(YA, same ? YA : YB, ti, tj, acc);
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y) {
           const int64_t i = ca + 4 * ti + x;
           const int64_t j = cb + 4 * tj + y;
-          if (i <= j && j < ko) stg_at(i, j, ldg_at(i, j) - acc[x][y]);
+          if (i <= j && j < ko) Gm[i + j * ldg] -= acc[x][y];
         }
       __syncthreads();
     }
-    if (!cq::grid_sync(a.bar)) {
+    if (!chol_sync(a.bar)) {
       if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
       return;
     }
@@ -230,7 +241,7 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
     int64_t k = 0;
     double dmax = 0.0, dmin = INFINITY;
     for (int64_t l = 1; l <= kc; ++l) {
-      const double v = fabs(ldg_at(l - 1, l - 1));
+      const double v = fabs(Gm[(l - 1) + (l - 1) * ldg]);
       dmax = fmax(dmax, v);
       dmin = fmin(dmin, v);
       if (dmax / dmin <= a.cond_max) k = l;
@@ -319,8 +330,7 @@ zero_cols_kernel(double* Q, int64_t ldq, int64_t m, int n, const int64_t* kdev) 
 namespace cqh {
 
 size_t chol_ws_bytes(int kmax) {
-  (void)kmax;
-  return 256;
+  return 256 + (size_t)kB * kB * 8 + (size_t)kB * kmax * 8;
 }
 
 hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int kmax,
@@ -336,6 +346,8 @@ hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int km
   a.ko = ko_dev;
   a.kout = k_dev;
   a.flags = reinterpret_cast<int*>(w + 4);
+  a.dinv = reinterpret_cast<double*>(static_cast<char*>(ws) + 256);
+  a.panel = a.dinv + kB * kB;
   a.info = info;
   a.bar.count = w;
   a.bar.gen = w + 1;

@@ -117,6 +117,46 @@ WORKLOADS = {
 }
 
 
+def spectrum_matrix_gpu(m, n, s, seed, noise_std=0.0, device="cuda"):
+    """Device-side version of ``spectrum_matrix`` for large inputs: the same
+    recipe (Haar U, V from positive-diagonal QR of Gaussians, A = U diag(s) V^T
+    plus noise), drawn with torch's seeded device generator. Returns a
+    column-major FP64 torch tensor on ``device``."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+
+    def haar(rows, cols):
+        G = torch.randn((cols, rows), dtype=torch.float64, device=device, generator=gen).t()
+        Q, R = torch.linalg.qr(G)
+        sgn = torch.where(torch.diagonal(R) < 0, -1.0, 1.0).to(torch.float64)
+        return Q * sgn
+
+    U = haar(m, n)
+    V = haar(n, n)
+    sv = torch.as_tensor(np.asarray(s, dtype=np.float64), device=device)
+    A = (U * sv) @ V.t()
+    del U
+    if noise_std:
+        A += noise_std * torch.randn((n, m), dtype=torch.float64, device=device,
+                                     generator=gen).t()
+    return A.t().contiguous().t()
+
+
+def make_workload_gpu(name, seed=0, m=None, device="cuda"):
+    """Named workload built on the device (see ``spectrum_matrix_gpu``)."""
+    w = dict(WORKLOADS[name])
+    if m is not None:
+        w["m"] = m
+    n = w["n"]
+    if w["kind"] == "logspaced":
+        s = logspaced_spectrum(n, w["cond"])
+    else:
+        s = planted_spectrum(n, w["rank"], w["cond"])
+    return spectrum_matrix_gpu(w["m"], n, s, seed, w["noise"], device), w
+
+
 def make_workload(name, seed=0, m=None):
     """Build the input matrix of a named workload (optionally with fewer rows)."""
     w = dict(WORKLOADS[name])

@@ -150,6 +150,8 @@ CASES = [
     ("n1", 500, 1, 2, 1, "log", 1.0, 1e-14),
     ("tiles-and-tail", 20003, 200, 250, 8, "log", 1e8, 1e-14),
     ("nnz1-gamma1", 4000, 64, 64, 1, "log", 1e3, 1e-14),
+    ("wide-16-blocks", 20000, 1024, 1280, 8, "log", 1e8, 1e-14),
+    ("wide-ragged", 12001, 700, 875, 4, "log", 1e6, 1e-14),
 ]
 
 
