@@ -225,6 +225,9 @@ hipError_t launch_sketch(const SketchPlan& p, const double* A, int64_t lda, int6
                          cqrrpt_info_t* info, hipStream_t s);
 
 struct QrcpPlan {
+  bool reg;       // register-resident variant
+  int rpl, cpw;   // its rows per lane and columns per wave
+  int threads;    // its workgroup size
   int nblocks;
   int cols_per_block;
   bool lds_resident;

@@ -283,6 +283,270 @@ __global__ void __launch_bounds__(kThreads) qrcp_kernel(QrcpArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident variant. The cost of one step is dominated by the
+// exchange among workgroups, which grows with their number, so this variant
+// uses few workgroups and keeps the owned columns in VGPRs: wave w of
+// workgroup g (NT threads, W = NT/64 waves) holds slots s = w + W k
+// (k < CPW), i.e. columns g + G s, as RPL rows per lane (row = lane + 64 q).
+// The arithmetic per column is the same as in qrcp_kernel.
+// ---------------------------------------------------------------------------
+template <int NT, int RPL, int CPW>
+__global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
+  constexpr int kRegThreads = NT;
+  constexpr int kRegWaves = NT / cq::kWave;
+  extern __shared__ double smem[];
+  __shared__ double s_rv[kRegWaves];
+  __shared__ int s_rc[kRegWaves];
+  __shared__ int s_bad;
+
+  const int G = gridDim.x;
+  const int g = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & (cq::kWave - 1);
+  const int wave = tid / cq::kWave;
+  const int d = a.d;
+  const int n = a.n;
+  const int dpad = (d + 1) & ~1;
+  double* xv = smem;
+  double* vv = smem + dpad;
+
+  double X[CPW][RPL];
+  bool alive[CPW];
+  int colid[CPW];
+  int step[CPW];
+  double bdiag[CPW];
+  double nrm[CPW];
+
+  if (cq::ld_agent(&a.info->status) != 0) {
+#pragma unroll
+    for (int k = 0; k < CPW; ++k) {
+      const int c = g + G * (wave + kRegWaves * k);
+      if (c < n) {
+        if (lane == 0) a.J[c] = c;
+        for (int r = lane; r < n; r += cq::kWave) a.R[r + (int64_t)c * a.ldr] = 0.0;
+      }
+    }
+    return;
+  }
+  if (tid == 0) s_bad = 0;
+
+#pragma unroll
+  for (int k = 0; k < CPW; ++k) {
+    const int c = g + G * (wave + kRegWaves * k);
+    colid[k] = c;
+    alive[k] = c < n;
+    step[k] = -1;
+    bdiag[k] = 0.0;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int r = lane + cq::kWave * q;
+      const double v = (alive[k] && r < d) ? a.X[r + (int64_t)c * a.ldx] : 0.0;
+      X[k][q] = v;
+      acc += v * v;
+    }
+    nrm[k] = alive[k] ? sqrt(cq::wave_sum(acc)) : -1.0;
+  }
+
+  // Best alive column of this workgroup (larger norm, then smaller index),
+  // its rows row0..d-1 staged, then the slot's tag released.
+  auto publish = [&](int stp, int row0) {
+    const int par = stp & 1;
+    double bv = -1.0;
+    int bc = INT_MAX;
+#pragma unroll
+    for (int k = 0; k < CPW; ++k)
+      if (alive[k] && (nrm[k] > bv || (nrm[k] == bv && colid[k] < bc))) {
+        bv = nrm[k];
+        bc = colid[k];
+      }
+    if (lane == 0) {
+      s_rv[wave] = bv;
+      s_rc[wave] = bc;
+    }
+    __syncthreads();
+    double wv = s_rv[0];
+    int wc = s_rc[0];
+    for (int w = 1; w < kRegWaves; ++w)
+      if (s_rv[w] > wv || (s_rv[w] == wv && s_rc[w] < wc)) {
+        wv = s_rv[w];
+        wc = s_rc[w];
+      }
+    double* dst = a.stage + ((size_t)par * G + g) * d;
+#pragma unroll
+    for (int k = 0; k < CPW; ++k) {
+      if (alive[k] && colid[k] == wc) {
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+          const int r = lane + cq::kWave * q;
+          if (r >= row0 && r < d) cq::st_agent(dst + (r - row0), X[k][q]);
+        }
+      }
+    }
+    if (tid == 0) {
+      cq::st_agent(&a.cand_val[par * G + g], wc == INT_MAX ? -1.0 : wv);
+      cq::st_agent(&a.cand_col[par * G + g], wc == INT_MAX ? -1 : wc);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0)
+      __hip_atomic_store(&a.tag[par * G + g], (unsigned)(stp + 1), __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  };
+
+  auto gather = [&](int stp, double& v, int& c) -> bool {
+    const int par = stp & 1;
+    v = -2.0;
+    c = INT_MAX;
+    if (tid < G) {
+      unsigned spins = 0;
+      unsigned* tg = &a.tag[par * G + tid];
+      while (__hip_atomic_load(tg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
+             (unsigned)(stp + 1)) {
+        if (__hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+            ++spins > cq::kSpinLimit) {
+          __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_bad = 1;
+          break;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      v = cq::ld_agent(&a.cand_val[par * G + tid]);
+      c = cq::ld_agent(&a.cand_col[par * G + tid]);
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return s_bad == 0;
+  };
+
+  publish(0, 0);
+
+  for (int i = 0; i < n; ++i) {
+    const int par = i & 1;
+    double v;
+    int c;
+    if (!gather(i, v, c)) {
+      if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
+      return;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ov = __shfl_xor(v, off, cq::kWave);
+      const int oc = __shfl_xor(c, off, cq::kWave);
+      if (ov > v || (ov == v && oc < c)) {
+        v = ov;
+        c = oc;
+      }
+    }
+    if (lane == 0) {
+      s_rv[wave] = v;
+      s_rc[wave] = c;
+    }
+    __syncthreads();
+    double nup = s_rv[0];
+    int p = s_rc[0];
+    for (int w = 1; w < kRegWaves; ++w)
+      if (s_rv[w] > nup || (s_rv[w] == nup && s_rc[w] < p)) {
+        nup = s_rv[w];
+        p = s_rc[w];
+      }
+    const int owner = p % G;
+    const int len = d - i;
+    const double* src = a.stage + ((size_t)par * G + owner) * d;
+    for (int r = tid; r < len; r += kRegThreads) xv[r] = cq::ld_agent(src + r);
+    __syncthreads();
+    const double alpha = xv[0];
+    double beta = 0.0, tau = 0.0;
+    if (nup != 0.0) {
+      beta = alpha >= 0.0 ? -nup : nup;
+      tau = (beta - alpha) / beta;
+      const double denom = alpha - beta;
+      for (int r = tid; r < len; r += kRegThreads) vv[r] = r == 0 ? 1.0 : xv[r] / denom;
+    }
+    if (g == owner && tid == 0) {
+      a.J[i] = p;
+      cq::st_agent(&a.beta[i], beta);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < CPW; ++k) {
+      if (alive[k] && colid[k] == p) {
+        alive[k] = false;
+        step[k] = i;
+        bdiag[k] = beta;
+      }
+    }
+    // Apply I - tau v v^T to the alive columns: dot products first, then the
+    // update and the new norms; v is streamed from LDS in both passes (the
+    // compiler barrier keeps the second pass from holding the first pass's
+    // loads in registers).
+    if (tau != 0.0) {
+      double w[CPW];
+#pragma unroll
+      for (int k = 0; k < CPW; ++k) w[k] = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int r = lane + cq::kWave * q;
+        const double vq = (r >= i && r < d) ? vv[r - i] : 0.0;
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) w[k] += vq * X[k][q];
+      }
+#pragma unroll
+      for (int k = 0; k < CPW; ++k) w[k] = alive[k] ? tau * cq::wave_sum(w[k]) : 0.0;
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int r = lane + cq::kWave * q;
+        const double vq = (r >= i && r < d) ? vv[r - i] : 0.0;
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) X[k][q] -= w[k] * vq;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < CPW; ++k) {
+      if (!alive[k]) continue;
+      double nn = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int r = lane + cq::kWave * q;
+        if (r > i) nn += X[k][q] * X[k][q];
+      }
+      nrm[k] = sqrt(cq::wave_sum(nn));
+    }
+    publish(i + 1, i + 1);
+  }
+  {
+    double v;
+    int c;
+    if (!gather(n, v, c)) {
+      if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
+      return;
+    }
+  }
+  // Assemble R (column step[k] of R holds owned column k), diag(R) >= 0.
+#pragma unroll
+  for (int k = 0; k < CPW; ++k) {
+    if (colid[k] >= n) continue;
+    const int sc = step[k];
+    double* dst = a.R + (int64_t)sc * a.ldr;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int r = lane + cq::kWave * q;
+      if (r < n) {
+        double val = 0.0;
+        if (r < sc) {
+          const double br = cq::ld_agent(&a.beta[r]);
+          val = br < 0.0 ? -X[k][q] : X[k][q];
+        } else if (r == sc) {
+          val = fabs(bdiag[k]);
+        }
+        dst[r] = val;
+      }
+    }
+  }
+}
+
 // Zero the step tags and the abort word before a cooperative launch.
 __global__ void qrcp_reset_kernel(unsigned* sync_words, int nwords) {
   for (int i = threadIdx.x; i < nwords; i += blockDim.x) sync_words[i] = 0u;
@@ -360,17 +624,47 @@ size_t qrcp_lds_bytes(int d, int cols, bool lds) {
 
 namespace cqh {
 
+// Register variant: rows per lane RPL and columns per wave CPW chosen so a
+// lane's columns fit its VGPR share without spilling: 512-thread workgroups
+// (256 VGPRs per lane) up to RPL = 20, 256-thread workgroups above.
+static const int kRplSet[] = {1, 2, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40};
+
+static int threads_for(int rpl) { return rpl <= 20 ? 512 : 256; }
+static int cpw_for(int rpl) { return rpl == 20 ? 3 : 4; }
+
 QrcpPlan plan_qrcp(int d, int n) {
   const Device& dev = device_info();
   QrcpPlan p{};
-  int G = (n + 3) / 4;
-  if (G > dev.num_cu) G = dev.num_cu;
-  if (G < 1) G = 1;
-  int cols = (n + G - 1) / G;
-  p.nblocks = G;
-  p.cols_per_block = cols;
-  p.lds_resident = qrcp_lds_bytes(d, cols, true) <= dev.lds_per_block;
-  p.lds_bytes = qrcp_lds_bytes(d, cols, p.lds_resident);
+  p.rpl = 0;
+  for (int r : kRplSet)
+    if (64 * r >= d) {
+      p.rpl = r;
+      break;
+    }
+  if (p.rpl > 0) {
+    p.cpw = cpw_for(p.rpl);
+    p.threads = threads_for(p.rpl);
+    const int per_block = (p.threads / 64) * p.cpw;
+    const int G = (n + per_block - 1) / per_block;
+    if (G <= dev.num_cu && G <= p.threads) {
+      p.reg = true;
+      p.nblocks = G;
+      p.cols_per_block = per_block;
+      p.lds_resident = false;
+      p.lds_bytes = (size_t)2 * ((d + 1) & ~1) * 8;
+    }
+  }
+  if (!p.reg) {
+    int G = (n + 3) / 4;
+    if (G > dev.num_cu) G = dev.num_cu;
+    if (G < 1) G = 1;
+    int cols = (n + G - 1) / G;
+    p.nblocks = G;
+    p.cols_per_block = cols;
+    p.lds_resident = qrcp_lds_bytes(d, cols, true) <= dev.lds_per_block;
+    p.lds_bytes = qrcp_lds_bytes(d, cols, p.lds_resident);
+  }
+  const int G = p.nblocks;
   p.stage_bytes = align256((size_t)2 * G * d * 8);
   // candidate norms, columns and tags, per parity and workgroup
   p.cand_bytes = align256((size_t)2 * G * 8) + align256((size_t)2 * G * 4) +
@@ -380,13 +674,23 @@ QrcpPlan plan_qrcp(int d, int n) {
   return p;
 }
 
+static const void* reg_kernel(int rpl) {
+#define CQ_REG(R) \
+  if (rpl == R) return (const void*)qrcp_reg_kernel<(R <= 20 ? 512 : 256), R, (R == 20 ? 3 : 4)>;
+  CQ_REG(1) CQ_REG(2) CQ_REG(4) CQ_REG(6) CQ_REG(8) CQ_REG(10)
+  CQ_REG(12) CQ_REG(16) CQ_REG(20) CQ_REG(24) CQ_REG(32) CQ_REG(40)
+#undef CQ_REG
+  return nullptr;
+}
+
 size_t qrcp_ws_bytes(const QrcpPlan& p) {
   return p.stage_bytes + p.cand_bytes + p.beta_bytes + p.sync_bytes;
 }
 
 hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, int64_t* J,
                        double* R, int64_t ldr, void* ws, cqrrpt_info_t* info, hipStream_t s) {
-  if (p.cols_per_block > kMaxCols || p.nblocks > kThreads) return hipErrorInvalidValue;
+  if (!p.reg && (p.cols_per_block > kMaxCols || p.nblocks > kThreads))
+    return hipErrorInvalidValue;
   const int G = p.nblocks;
   char* base = static_cast<char*>(ws);
   QrcpArgs a;
@@ -415,15 +719,24 @@ hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, 
   e = hipGetLastError();
   if (e != hipSuccess) return e;
 
-  const void* fn = p.lds_resident ? (const void*)qrcp_kernel<true> : (const void*)qrcp_kernel<false>;
+  const void* fn;
+  int threads;
+  if (p.reg) {
+    fn = reg_kernel(p.rpl);
+    threads = p.threads;
+    if (!fn) return hipErrorInvalidValue;
+  } else {
+    fn = p.lds_resident ? (const void*)qrcp_kernel<true> : (const void*)qrcp_kernel<false>;
+    threads = kThreads;
+  }
   e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
   if (e != hipSuccess) return e;
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, p.lds_bytes);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, p.lds_bytes);
   if (e != hipSuccess) return e;
   if ((int64_t)per_cu * device_info().num_cu < p.nblocks) return hipErrorCooperativeLaunchTooLarge;
   void* args[] = {&a};
-  return hipLaunchCooperativeKernel(fn, dim3(p.nblocks), dim3(kThreads), args,
+  return hipLaunchCooperativeKernel(fn, dim3(p.nblocks), dim3(threads), args,
                                     (unsigned)p.lds_bytes, s);
 }
 

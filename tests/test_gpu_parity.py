@@ -122,7 +122,8 @@ def test_sketch_parity(P, m, n, d, nnz):
     assert np.all(np.abs(S1 - So) <= bound + 1e-300)
 
 
-@pytest.mark.parametrize("d,n", [(13, 10), (125, 100), (170, 130), (300, 257), (640, 512)])
+@pytest.mark.parametrize("d,n", [(13, 10), (125, 100), (170, 130), (300, 257), (640, 512),
+                                 (1500, 300), (2000, 150), (2600, 40)])
 def test_qrcp_parity_separated(P, d, n):
     say(f"qrcp d={d} n={n}")
     X = W.column_scaled_well_separated(d, n, seed=d * 7 + n, ratio=1.05)
