@@ -8,8 +8,8 @@
 //
 // The Cholesky factorization is one cooperative launch, right-looking over
 // 64-column blocks, two phases per block separated by grid barriers:
-//   1. one workgroup factors the diagonal block D (one wave, a column per
-//      lane) and forms D^{-1} (a column per thread, back substitution);
+//   1. one wave factors the diagonal block D (a column per lane, in
+//      registers) and forms D^{-1} (a column per lane, back substitution);
 //   2. every workgroup takes trailing tiles (p, q), p <= q: it forms the
 //      block-row tiles Y_p = D^{-T} G[block, p] and Y_q as small products
 //      with D^{-1}, writes Y_p as R_pre[block, p] when p == q, and applies
@@ -39,6 +39,13 @@ struct CholArgs {
   cq::GridBarrier bar;
   double cond_max;
 };
+
+CQ_INLINE double readlane_d(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
 CQ_INLINE bool chol_sync(const cq::GridBarrier& b) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -117,36 +124,45 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
       if (tid == 0) s_fail = -1;
       __syncthreads();
       if (wave == 0) {
+        // Lane c holds column c of D; row j values are broadcast with
+        // v_readlane (lane index known at compile time).
+        double cl[kB];
+#pragma unroll
+        for (int i = 0; i < kB; ++i) cl[i] = D[i * kLd + lane];
+        int fl = -1;
+#pragma unroll
         for (int j = 0; j < kB; ++j) {
-          const double piv = D[j * kLd + j];
-          if (!(piv > 0.0) || !isfinite(piv)) {
-            if (lane == 0) s_fail = (int)(c0 + j);
-            break;
+          if (fl < 0) {
+            const double piv = readlane_d(cl[j], j);
+            if (!(piv > 0.0) || !isfinite(piv)) {
+              fl = j;
+            } else {
+              const double rj = sqrt(piv);
+              cl[j] = lane == j ? rj : (lane > j ? cl[j] / rj : cl[j]);
+#pragma unroll
+              for (int c1 = j + 1; c1 < kB; ++c1) {
+                const double sv = readlane_d(cl[j], c1);
+                cl[c1] -= lane >= c1 ? sv * cl[j] : 0.0;
+              }
+            }
           }
-          const double rj = sqrt(piv);
-          if (lane == j) D[j * kLd + j] = rj;
-          if (lane > j) D[j * kLd + lane] = D[j * kLd + lane] / rj;
-          __builtin_amdgcn_wave_barrier();
-          if (lane > j) {
-            const double rjl = D[j * kLd + lane];
-            for (int c1 = j + 1; c1 <= lane; ++c1) D[c1 * kLd + lane] -= D[j * kLd + c1] * rjl;
-          }
-          __builtin_amdgcn_wave_barrier();
         }
-      }
-      __syncthreads();
-      // Column t of D^{-1} (upper): back substitution D x = e_t.
-      if (tid < kB && s_fail < 0) {
-        const int t = tid;
-        double* x = YA;  // column-major scratch: x[i * kLd + t]
-        for (int i = kB - 1; i >= 0; --i) {
-          double v = 0.0;
-          if (i <= t) {
-            double acc = (i == t) ? 1.0 : 0.0;
-            for (int l = i + 1; l <= t; ++l) acc -= D[i * kLd + l] * x[l * kLd + t];
-            v = acc / D[i * kLd + i];
+#pragma unroll
+        for (int i = 0; i < kB; ++i) D[i * kLd + lane] = cl[i];
+        if (lane == 0 && fl >= 0) s_fail = (int)(c0 + fl);
+        if (fl < 0) {
+          // Column `lane` of D^{-1} by back substitution (zero below the
+          // diagonal follows from the zero start values).
+          double w[kB];
+#pragma unroll
+          for (int i = kB - 1; i >= 0; --i) {
+            double acc = lane == i ? 1.0 : 0.0;
+#pragma unroll
+            for (int l = i + 1; l < kB; ++l) acc -= D[i * kLd + l] * w[l];
+            w[i] = acc / D[i * kLd + i];
           }
-          x[i * kLd + t] = v;
+#pragma unroll
+          for (int i = 0; i < kB; ++i) YA[i * kLd + lane] = w[i];
         }
       }
       __syncthreads();
@@ -356,7 +372,14 @@ hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int km
   int per_cu = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)chol_kernel, kThreads, 0);
   if (e != hipSuccess) return e;
-  int nblocks = device_info().num_cu;
+  // Few workgroups: the barrier cost grows with their number; enough for
+  // about four trailing tiles each in the first block step.
+  const int nb = (kmax + kB - 1) / kB;
+  const int first_tasks = (nb - 1) * nb / 2;
+  int nblocks = (first_tasks + 3) / 4;
+  if (nblocks < 16) nblocks = 16;
+  if (nblocks > 64) nblocks = 64;
+  if (nblocks > device_info().num_cu) nblocks = device_info().num_cu;
   if (per_cu < 1) return hipErrorCooperativeLaunchTooLarge;
   a.bar.nblocks = (unsigned)nblocks;
   void* args[] = {&a};

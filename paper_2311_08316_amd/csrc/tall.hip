@@ -20,10 +20,11 @@
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;     // SYRK
+constexpr int kTThreads = 512;    // triangular solve: 8 waves, 2 per SIMD
 constexpr int kRT = 128;   // rows per workgroup
 constexpr int kNB = 64;    // column block
-constexpr int kKB = 16;    // K per staging step
+constexpr int kKB = 32;    // K per staging step
 constexpr int kTsLd = kRT + 1;
 constexpr int kRdLd = kNB + 1;
 
@@ -45,9 +46,11 @@ template <typename TC> CQ_INLINE int acc_row(int lq, int r);
 template <> CQ_INLINE int acc_row<double>(int lq, int r) { return lq + 4 * r; }
 template <> CQ_INLINE int acc_row<float>(int lq, int r) { return 4 * lq + r; }
 
-// TB: type of B, TX: type of X, TC: arithmetic type.
+// TB: type of B, TX: type of X, TC: arithmetic type. Wave w computes the
+// 32 x 32 sub-block (rows 32 (w / 2), columns 32 (w % 2)) of the 128 x 64
+// output block with 2 x 2 MFMA tiles.
 template <typename TB, typename TX, typename TC>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kTThreads)
 trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X, int64_t ldx,
             const double* __restrict__ R, int64_t ldr, int64_t m, const int64_t* kdev,
             const cqrrpt_info_t* info) {
@@ -64,32 +67,34 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
+  const int wr = wave >> 1;
+  const int wc = wave & 1;
   const int l16 = lane & 15;
   const int lq = lane >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * kRT;
-  const int64_t wrow = row0 + 32 * wave;   // this wave's 32 rows
+  const int64_t wrow = row0 + 32 * wr;
   const int nblk = (int)((k + kNB - 1) / kNB);
 
   for (int jb = 0; jb < nblk; ++jb) {
     const int64_t c0 = (int64_t)jb * kNB;
     const int K = (int)c0;
-    acc_t acc[2][4];
+    acc_t acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+      for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
     if (K > 0) {
-      // Register prefetch of the A fragments and of this thread's share of
-      // the next R staging tile; R tiles are double-buffered in LDS.
-      TC af[2][4], an[2][4];
+      // Register prefetch of the next step's A fragments and R share; the R
+      // staging tiles are double-buffered in LDS.
+      TC af[2][kKB / 4], an[2][kKB / 4];
       TC ra[4];
-      auto load_a = [&](TC (&dst)[2][4], int kk) {
+      auto load_a = [&](TC (&dst)[2][kKB / 4], int kk) {
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
           const int64_t r = wrow + 16 * a + l16;
 #pragma unroll
-          for (int s = 0; s < 4; ++s) {
+          for (int s = 0; s < kKB / 4; ++s) {
             const int64_t kc = kk + 4 * s + lq;
             dst[a][s] = r < m ? (TC)X[r + kc * ldx] : (TC)0;
           }
@@ -98,9 +103,9 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
       auto load_r = [&](int kk) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int e = tid + kThreads * q;
+          const int e = tid + kTThreads * q;
           const int kr = e & (kKB - 1);
-          const int cc = e >> 4;
+          const int cc = e / kKB;
           const int64_t col = c0 + cc;
           ra[q] = col < k ? (TC)R[(kk + kr) + col * ldr] : (TC)0;
         }
@@ -108,9 +113,9 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
       auto store_r = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int e = tid + kThreads * q;
+          const int e = tid + kTThreads * q;
           const int kr = e & (kKB - 1);
-          const int cc = e >> 4;
+          const int cc = e / kKB;
           Rt[buf * kKB * kNB + kr * kNB + cc] = ra[q];
         }
       };
@@ -125,16 +130,16 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
           load_a(an, kk + kKB);
           load_r(kk + kKB);
         }
-        const TC* rb = Rt + buf * kKB * kNB;
+        const TC* rb = Rt + buf * kKB * kNB + 32 * wc;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          TC bf[4];
+        for (int s = 0; s < kKB / 4; ++s) {
+          TC bf[2];
 #pragma unroll
-          for (int b = 0; b < 4; ++b) bf[b] = rb[(4 * s + lq) * kNB + 16 * b + l16];
+          for (int b = 0; b < 2; ++b) bf[b] = rb[(4 * s + lq) * kNB + 16 * b + l16];
 #pragma unroll
           for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = mfma(af[a][s], bf[b], acc[a][b]);
+            for (int b = 0; b < 2; ++b) acc[a][b] = mfma(af[a][s], bf[b], acc[a][b]);
         }
         if (more) store_r(buf ^ 1);
         __syncthreads();
@@ -142,15 +147,15 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
 #pragma unroll
           for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int s = 0; s < 4; ++s) af[a][s] = an[a][s];
+            for (int s = 0; s < kKB / 4; ++s) af[a][s] = an[a][s];
         }
       }
     }
 
     // T = B[rows, gather(block)] - acc, into LDS (column-major, padded).
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int cl = 16 * b + l16;
+    for (int b = 0; b < 2; ++b) {
+      const int cl = 32 * wc + 16 * b + l16;
       const int64_t col = c0 + cl;
       const bool cvalid = col < k;
       const int64_t gcol = cvalid ? (gather ? gather[col] : col) : 0;
@@ -158,7 +163,7 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
       for (int a = 0; a < 2; ++a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int rl = 32 * wave + 16 * a + acc_row<TC>(lq, r);
+          const int rl = 32 * wr + 16 * a + acc_row<TC>(lq, r);
           const int64_t row = row0 + rl;
           TC bv = (TC)0;
           if (cvalid && row < m) bv = (TC)B[row + gcol * ldb];
@@ -167,7 +172,7 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
       }
     }
     // Diagonal block of R (identity past k) and reciprocals of its diagonal.
-    for (int e = tid; e < kNB * kNB; e += kThreads) {
+    for (int e = tid; e < kNB * kNB; e += kTThreads) {
       const int i = e & (kNB - 1);
       const int j = e >> 6;
       TC v;
@@ -351,7 +356,7 @@ hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX*
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int64_t grid = (m + kRT - 1) / kRT;
-  hipLaunchKernelGGL((trsm_kernel<TB, TX, TC>), dim3((unsigned)grid), dim3(kThreads), lds, s, B,
+  hipLaunchKernelGGL((trsm_kernel<TB, TX, TC>), dim3((unsigned)grid), dim3(kTThreads), lds, s, B,
                      ldb, gather, X, ldx, R, ldr, m, kdev, info);
   return hipGetLastError();
 }
