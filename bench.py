@@ -55,6 +55,14 @@ def parse():
                     help="skip the planted-rank and mixed-precision runs")
     ap.add_argument("--cpu-rows", type=int, default=16384,
                     help="rows of the bounded sample the CPU oracle factors")
+    ap.add_argument("--gaussian-input", action="store_true",
+                    help="iid Gaussian input of the workload's shape (full rank; for "
+                         "counter runs, where the QR-based generator is slow)")
+    ap.add_argument("--no-quality", action="store_true",
+                    help="skip the orthogonality/reconstruction evaluation")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (three times), the "
+                         "reference kernel for scaling HBM byte counters")
     return ap.parse_args()
 
 
@@ -71,7 +79,8 @@ def quality(torch, A, f, k):
     return orth, recon
 
 
-def run_mode(P, torch, A, w, mode, tol, seed, steps, warmup, want_stages=True):
+def run_mode(P, torch, A, w, mode, tol, seed, steps, warmup, want_stages=True,
+             want_quality=True):
     m, n, d, nnz = w["m"], w["n"], w["d"], w["nnz"]
     f = P.Factorization(m, n, d, nnz, mode)
     for _ in range(warmup):
@@ -105,7 +114,7 @@ def run_mode(P, torch, A, w, mode, tol, seed, steps, warmup, want_stages=True):
         stages_all = None
     info = f.info()
     k = int(info.rank)
-    orth, recon = quality(torch, A, f, k)
+    orth, recon = quality(torch, A, f, k) if want_quality else (None, None)
     ms = total_ms / steps
     return dict(f=f, ms=ms, wall_s=wall, p50=float(np.percentile(per, 50)),
                 p99=float(np.percentile(per, 99)), min=float(per.min()), rank=k,
@@ -199,14 +208,22 @@ def main():
         sys.exit(2)
     P.lib()
     t0 = time.perf_counter()
-    A, w = W.make_workload_gpu(args.workload, seed=args.seed)
+    if args.gaussian_input:
+        w = dict(W.WORKLOADS[args.workload])
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(args.seed)
+        A = torch.randn((w["n"], w["m"]), dtype=torch.float64, device="cuda",
+                        generator=gen).t()
+    else:
+        A, w = W.make_workload_gpu(args.workload, seed=args.seed)
     torch.cuda.synchronize()
     log(f"generated {args.workload} in {time.perf_counter() - t0:.1f} s")
     m, n, d, nnz, tol = w["m"], w["n"], w["d"], w["nnz"], w["tol"]
 
-    main_res = run_mode(P, torch, A, w, P.CQRRPT_FP64, tol, args.seed, args.steps, args.warmup)
+    main_res = run_mode(P, torch, A, w, P.CQRRPT_FP64, tol, args.seed, args.steps, args.warmup,
+                        want_quality=not args.no_quality)
     log(f"fp64 tol={tol}: {main_res['ms']:.3f} ms/step, rank {main_res['rank']}, "
-        f"orth {main_res['orth']:.2e}, recon {main_res['recon']:.2e}, "
+        f"orth {main_res['orth']}, recon {main_res['recon']}, "
         f"stages {json.dumps({k: round(v, 3) for k, v in main_res['stages'].items()})}")
     roof = roofline(main_res, w)
     log(f"roofline: {roof}")
@@ -231,6 +248,16 @@ def main():
         except P.CqrrptError as exc:
             extra["mixed"] = {"error": str(exc)}
 
+    if args.copy_calib:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x copy of 1 GiB (reads 1 GiB, writes 1 GiB each)")
+        del src, dst
+
     cpu = None
     if not args.no_cpu_baseline:
         rows = min(args.cpu_rows, m)
@@ -251,7 +278,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic",
+        "data": "synthetic-gaussian" if args.gaussian_input else "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "d": d, "nnz": nnz, "tol": tol,
                    "seed": args.seed, "mode": "fp64"},
         "p50_ms": main_res["p50"],

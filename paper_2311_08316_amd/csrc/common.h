@@ -118,6 +118,76 @@ CQ_INLINE double wave_max(double v) {
   return v;
 }
 
+// Lane permutations by DPP (no LDS round trip). Controls used: quad_perm
+// [1,0,3,2] = 0xB1, quad_perm [2,3,0,1] = 0x4E, row_half_mirror = 0x141
+// (lane i of each 8 takes lane 7-i), row_mirror = 0x140 (lane i of each 16
+// takes lane 15-i). Every lane has a valid source under these controls.
+template <int kCtrl>
+CQ_INLINE int dpp_move(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, kCtrl, 0xF, 0xF, false);
+}
+template <int kCtrl>
+CQ_INLINE double dpp_move(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)dpp_move<kCtrl>((int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)dpp_move<kCtrl>((int)(uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+CQ_INLINE double readlane_d(double x, int l) {
+  const uint64_t v = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes (all active), the same bits in every lane: within
+// each row of 16 lanes, pairs, quads, halves and rows are added to their
+// mirror partner (a + b and b + a round alike, so the lanes agree), then the
+// four row sums are combined in a fixed order.
+CQ_INLINE double wave_sum_dpp(double v) {
+  v += dpp_move<0xB1>(v);
+  v += dpp_move<0x4E>(v);
+  v += dpp_move<0x141>(v);
+  v += dpp_move<0x140>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// Larger value wins, ties to the smaller index: a total order on distinct
+// (value, index) pairs, so the winner does not depend on the pairing order.
+CQ_INLINE bool beats(double ov, int oc, double v, int c) {
+  return ov > v || (ov == v && oc < c);
+}
+template <int kCtrl>
+CQ_INLINE void argmax_step(double& v, int& c) {
+  const double ov = dpp_move<kCtrl>(v);
+  const int oc = dpp_move<kCtrl>(c);
+  if (beats(ov, oc, v, c)) {
+    v = ov;
+    c = oc;
+  }
+}
+// Wave-wide argmax (all lanes active); every lane ends with the winner.
+CQ_INLINE void wave_argmax_dpp(double& v, int& c) {
+  argmax_step<0xB1>(v, c);
+  argmax_step<0x4E>(v, c);
+  argmax_step<0x141>(v, c);
+  argmax_step<0x140>(v, c);
+  double bv = readlane_d(v, 0);
+  int bc = __builtin_amdgcn_readlane(c, 0);
+#pragma unroll
+  for (int l = 16; l < 64; l += 16) {
+    const double ov = readlane_d(v, l);
+    const int oc = __builtin_amdgcn_readlane(c, l);
+    if (beats(ov, oc, bv, bc)) {
+      bv = ov;
+      bc = oc;
+    }
+  }
+  v = bv;
+  c = bc;
+}
+
 // ---------------------------------------------------------------------------
 // Grid barrier for cooperative launches. Arrival counter plus a generation
 // word, both in device memory; agent-scope release/acquire orders every
@@ -188,6 +258,26 @@ CQ_INLINE void st_agent(int* p, int x) {
   __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Flagged words for exchanges without fences: the high 32 bits carry the
+// step a word belongs to, the low 32 bits data. A 64-bit access is single-copy
+// atomic, so a reader that sees the expected step in a word also sees that
+// word's data; no release/acquire pair is needed.
+CQ_INLINE void put_flagged(uint64_t* p, uint32_t data, uint32_t flag) {
+  __hip_atomic_store(p, ((uint64_t)flag << 32) | data, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+CQ_INLINE uint64_t get_flagged(const uint64_t* p) {
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+CQ_INLINE uint32_t flag_of(uint64_t w) { return (uint32_t)(w >> 32); }
+CQ_INLINE double join_halves(uint64_t lo, uint64_t hi) {
+  return __longlong_as_double((long long)((hi << 32) | (lo & 0xffffffffull)));
+}
+CQ_INLINE uint32_t lo_half(double x) { return (uint32_t)(uint64_t)__double_as_longlong(x); }
+CQ_INLINE uint32_t hi_half(double x) {
+  return (uint32_t)((uint64_t)__double_as_longlong(x) >> 32);
+}
+
 // Device-side status word helpers (cqrrpt_info_t lives in device memory).
 CQ_INLINE void set_status(cqrrpt_info_t* info, int code) {
   __hip_atomic_store(&info->status, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -209,6 +299,7 @@ hipError_t launch_saso_sample(int64_t m, int d, int nnz, uint64_t seed, int32_t*
                               int8_t* signs, hipStream_t s);
 
 struct SketchPlan {
+  int reg_t;    // targets per thread of the register variant (0: LDS variant)
   int ts;       // source rows per sub-chunk
   int nsub;     // number of sub-chunks
   int nc;       // columns per workgroup

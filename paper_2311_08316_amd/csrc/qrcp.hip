@@ -21,12 +21,16 @@
 //   * each wave applies I - tau v v^T to one owned column at a time and
 //     recomputes that column's norm over rows i+1..d-1;
 //   * each workgroup publishes its best remaining column (norm, index, and
-//     rows i+1..d-1 staged in a global slot), then releases a per-slot step
-//     tag; step i+1 starts by waiting on all G tags (no shared counter).
-// Reductions are fixed-shape wave butterflies, so the result is
-// deterministic.
+//     rows i+1..d-1 staged in a global slot); step i+1 starts by waiting for
+//     all G slots (no shared counter).
+// Two variants: a general one (columns in LDS or in place in X, step tags
+// released after the slot is written) and a register-resident one for the
+// usual sketch sizes (columns in VGPRs, slots of flagged words, no fences).
+// Reductions have a fixed shape, so the result is deterministic.
 #include <limits.h>
 #include <math.h>
+
+#include <algorithm>
 
 #include "common.h"
 
@@ -49,6 +53,8 @@ struct QrcpArgs {
   int* cand_col;     // [2][G]      candidate column (-1: none left)
   unsigned* tag;     // [2][G]      step + 1 once the slot is published
   double* beta;      // [n]
+  uint64_t* fstage;  // register variant: [2][G][2d] flagged words
+  uint64_t* fcand;   // register variant: [2][G][4] flagged words
   int* abort;
   cqrrpt_info_t* info;
 };
@@ -285,19 +291,42 @@ __global__ void __launch_bounds__(kThreads) qrcp_kernel(QrcpArgs a) {
 
 // ---------------------------------------------------------------------------
 // Register-resident variant. The cost of one step is dominated by the
-// exchange among workgroups, which grows with their number, so this variant
-// uses few workgroups and keeps the owned columns in VGPRs: wave w of
-// workgroup g (NT threads, W = NT/64 waves) holds slots s = w + W k
-// (k < CPW), i.e. columns g + G s, as RPL rows per lane (row = lane + 64 q).
-// The arithmetic per column is the same as in qrcp_kernel.
+// exchange among workgroups, so this variant uses few workgroups and keeps
+// the owned columns in VGPRs: wave w of workgroup g (NT threads, W = NT/64
+// waves) holds slots s = w + W k (k < CPW), i.e. columns g + G s, as RPL rows
+// per lane (row = lane + 64 q).
+//
+// The exchange uses flagged 64-bit words (data in the low half, step in the
+// high half), so no fence or separate tag sits on the critical path:
+//   * cand[par][g]  = {lo(norm), hi(norm), column}, each word tagged step+1;
+//   * stage[par][g] = rows row0..d-1 of that column, two words per double.
+// A reader polls the words it needs until every one carries the expected
+// step. Slot reuse is safe with two parities: a workgroup rewrites parity p
+// at step s + 2 only after it has seen every workgroup's step s + 1
+// candidate, and each workgroup publishes that only after it has finished
+// reading step s.
+//
+// Per step, wave 0 gathers the G candidates and takes the argmax; every
+// thread then fetches its share of the winner's staged rows, forms the
+// reflector (each workgroup computes the same beta and tau from the same
+// data) and writes v to LDS; each wave copies v into registers once, applies
+// I - tau v v^T to its alive columns and recomputes their norms. The sign of
+// every beta is kept in LDS for the final assembly of R, so no workgroup
+// reads another's results after the last step.
 // ---------------------------------------------------------------------------
+constexpr int kRegMaxG = 256;
+
 template <int NT, int RPL, int CPW>
 __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
-  constexpr int kRegThreads = NT;
-  constexpr int kRegWaves = NT / cq::kWave;
+  constexpr int W = NT / cq::kWave;
+  constexpr int KR = (cq::kWave * RPL + NT - 1) / NT;  // staged rows per thread
+  constexpr int KS = kRegMaxG / cq::kWave;             // candidate slots per lane
+  constexpr bool kHoldV = RPL * (CPW + 1) <= 40;       // v fits beside the columns
   extern __shared__ double smem[];
-  __shared__ double s_rv[kRegWaves];
-  __shared__ int s_rc[kRegWaves];
+  __shared__ double s_rv[W];
+  __shared__ int s_rc[W];
+  __shared__ double s_nup;
+  __shared__ int s_p;
   __shared__ int s_bad;
 
   const int G = gridDim.x;
@@ -307,9 +336,10 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
   const int wave = tid / cq::kWave;
   const int d = a.d;
   const int n = a.n;
-  const int dpad = (d + 1) & ~1;
-  double* xv = smem;
-  double* vv = smem + dpad;
+  // v by absolute row (64 RPL entries): zero above the current step and
+  // below row d, so the passes over a lane's rows need no masks.
+  double* vv = smem;
+  unsigned char* bneg = reinterpret_cast<unsigned char*>(smem + cq::kWave * RPL);  // [n]
 
   double X[CPW][RPL];
   bool alive[CPW];
@@ -321,7 +351,7 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
   if (cq::ld_agent(&a.info->status) != 0) {
 #pragma unroll
     for (int k = 0; k < CPW; ++k) {
-      const int c = g + G * (wave + kRegWaves * k);
+      const int c = g + G * (wave + W * k);
       if (c < n) {
         if (lane == 0) a.J[c] = c;
         for (int r = lane; r < n; r += cq::kWave) a.R[r + (int64_t)c * a.ldr] = 0.0;
@@ -330,10 +360,11 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
     return;
   }
   if (tid == 0) s_bad = 0;
+  for (int r = tid; r < cq::kWave * RPL; r += NT) vv[r] = 0.0;
 
 #pragma unroll
   for (int k = 0; k < CPW; ++k) {
-    const int c = g + G * (wave + kRegWaves * k);
+    const int c = g + G * (wave + W * k);
     colid[k] = c;
     alive[k] = c < n;
     step[k] = -1;
@@ -346,18 +377,19 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
       X[k][q] = v;
       acc += v * v;
     }
-    nrm[k] = alive[k] ? sqrt(cq::wave_sum(acc)) : -1.0;
+    nrm[k] = cq::wave_sum_dpp(acc);
+    nrm[k] = alive[k] ? sqrt(nrm[k]) : -1.0;
   }
 
-  // Best alive column of this workgroup (larger norm, then smaller index),
-  // its rows row0..d-1 staged, then the slot's tag released.
+  // Best alive column of this workgroup (larger norm, then smaller index):
+  // its owner wave stages rows row0..d-1, thread 0 writes the candidate.
   auto publish = [&](int stp, int row0) {
-    const int par = stp & 1;
+    const uint32_t flag = (uint32_t)stp + 1u;
     double bv = -1.0;
     int bc = INT_MAX;
 #pragma unroll
     for (int k = 0; k < CPW; ++k)
-      if (alive[k] && (nrm[k] > bv || (nrm[k] == bv && colid[k] < bc))) {
+      if (alive[k] && cq::beats(nrm[k], colid[k], bv, bc)) {
         bv = nrm[k];
         bc = colid[k];
       }
@@ -368,105 +400,159 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
     __syncthreads();
     double wv = s_rv[0];
     int wc = s_rc[0];
-    for (int w = 1; w < kRegWaves; ++w)
-      if (s_rv[w] > wv || (s_rv[w] == wv && s_rc[w] < wc)) {
+    for (int w = 1; w < W; ++w)
+      if (cq::beats(s_rv[w], s_rc[w], wv, wc)) {
         wv = s_rv[w];
         wc = s_rc[w];
       }
-    double* dst = a.stage + ((size_t)par * G + g) * d;
+    // Row lane + 64 q is at or below row0 exactly when q > q0.
+    const int q0 = (row0 - 1 - lane) >> 6;
+    uint64_t* dst = a.fstage + ((size_t)(stp & 1) * G + g) * 2 * (size_t)d +
+                    2 * (int64_t)(lane - row0);
 #pragma unroll
     for (int k = 0; k < CPW; ++k) {
       if (alive[k] && colid[k] == wc) {
 #pragma unroll
         for (int q = 0; q < RPL; ++q) {
-          const int r = lane + cq::kWave * q;
-          if (r >= row0 && r < d) cq::st_agent(dst + (r - row0), X[k][q]);
+          if (q > q0 && lane + cq::kWave * q < d) {
+            cq::put_flagged(dst + 2 * cq::kWave * q, cq::lo_half(X[k][q]), flag);
+            cq::put_flagged(dst + 2 * cq::kWave * q + 1, cq::hi_half(X[k][q]), flag);
+          }
         }
       }
     }
     if (tid == 0) {
-      cq::st_agent(&a.cand_val[par * G + g], wc == INT_MAX ? -1.0 : wv);
-      cq::st_agent(&a.cand_col[par * G + g], wc == INT_MAX ? -1 : wc);
+      uint64_t* cd = a.fcand + ((size_t)(stp & 1) * G + g) * 4;
+      const double cv = wc == INT_MAX ? -1.0 : wv;
+      cq::put_flagged(cd, cq::lo_half(cv), flag);
+      cq::put_flagged(cd + 1, cq::hi_half(cv), flag);
+      cq::put_flagged(cd + 2, (uint32_t)(wc == INT_MAX ? -1 : wc), flag);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (tid == 0)
-      __hip_atomic_store(&a.tag[par * G + g], (unsigned)(stp + 1), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
   };
 
-  auto gather = [&](int stp, double& v, int& c) -> bool {
-    const int par = stp & 1;
-    v = -2.0;
-    c = INT_MAX;
-    if (tid < G) {
-      unsigned spins = 0;
-      unsigned* tg = &a.tag[par * G + tid];
-      while (__hip_atomic_load(tg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
-             (unsigned)(stp + 1)) {
-        if (__hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
-            ++spins > cq::kSpinLimit) {
-          __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          s_bad = 1;
-          break;
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      v = cq::ld_agent(&a.cand_val[par * G + tid]);
-      c = cq::ld_agent(&a.cand_col[par * G + tid]);
+  // Bounded poll: true once every flag matches; raises *abort on timeout or
+  // when another workgroup raised it.
+  auto timed_out = [&](unsigned& spins) -> bool {
+    ++spins;
+    if ((spins & 63u) == 0u &&
+        __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return true;
+    if (spins > cq::kSpinLimit) {
+      __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return true;
     }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return s_bad == 0;
+    return false;
   };
 
   publish(0, 0);
 
   for (int i = 0; i < n; ++i) {
     const int par = i & 1;
-    double v;
-    int c;
-    if (!gather(i, v, c)) {
-      if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
-      return;
-    }
+    const uint32_t flag = (uint32_t)i + 1u;
+    // Wave 0: the G candidates of step i and their argmax.
+    if (wave == 0) {
+      double bv = -2.0;
+      int bc = INT_MAX;
+      bool bad = false;
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ov = __shfl_xor(v, off, cq::kWave);
-      const int oc = __shfl_xor(c, off, cq::kWave);
-      if (ov > v || (ov == v && oc < c)) {
-        v = ov;
-        c = oc;
+      for (int s = 0; s < KS; ++s) {
+        const int slot = lane + cq::kWave * s;
+        if (slot < G) {
+          const uint64_t* cd = a.fcand + ((size_t)par * G + slot) * 4;
+          uint64_t w0 = cq::get_flagged(cd), w1 = cq::get_flagged(cd + 1),
+                   w2 = cq::get_flagged(cd + 2);
+          unsigned spins = 0;
+          while (cq::flag_of(w0) != flag || cq::flag_of(w1) != flag ||
+                 cq::flag_of(w2) != flag) {
+            if (timed_out(spins)) {
+              bad = true;
+              break;
+            }
+            w0 = cq::get_flagged(cd);
+            w1 = cq::get_flagged(cd + 1);
+            w2 = cq::get_flagged(cd + 2);
+          }
+          const double v = cq::join_halves(w0, w1);
+          const int c = (int)(uint32_t)w2;
+          if (!bad && cq::beats(v, c, bv, bc)) {
+            bv = v;
+            bc = c;
+          }
+        }
       }
-    }
-    if (lane == 0) {
-      s_rv[wave] = v;
-      s_rc[wave] = c;
+      cq::wave_argmax_dpp(bv, bc);
+      if (bad) s_bad = 1;
+      if (lane == 0) {
+        s_nup = bv;
+        s_p = bc;
+      }
     }
     __syncthreads();
-    double nup = s_rv[0];
-    int p = s_rc[0];
-    for (int w = 1; w < kRegWaves; ++w)
-      if (s_rv[w] > nup || (s_rv[w] == nup && s_rc[w] < p)) {
-        nup = s_rv[w];
-        p = s_rc[w];
-      }
-    const int owner = p % G;
+    // A timed-out exchange leaves garbage but no early exit: every later poll
+    // ends within 64 spins once *abort is up, and the status reports it.
+    const double nup = s_nup;
+    const int p = s_p;
+    const bool valid = p >= 0 && p < n;  // false only after a timeout
+    const int owner = valid ? p % G : 0;
     const int len = d - i;
-    const double* src = a.stage + ((size_t)par * G + owner) * d;
-    for (int r = tid; r < len; r += kRegThreads) xv[r] = cq::ld_agent(src + r);
-    __syncthreads();
-    const double alpha = xv[0];
-    double beta = 0.0, tau = 0.0;
+    // The winner's rows i..d-1: row i (alpha) in every thread, then this
+    // thread's share; v = x / (alpha - beta), v[0] = 1.
+    const uint64_t* src = a.fstage + ((size_t)par * G + owner) * 2 * (size_t)d;
+    uint64_t al = cq::get_flagged(src), ah = cq::get_flagged(src + 1);
+    uint64_t lo[KR], hi[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int rr = tid + NT * k;
+      lo[k] = hi[k] = (uint64_t)flag << 32;
+      if (rr < len) {
+        lo[k] = cq::get_flagged(src + 2 * rr);
+        hi[k] = cq::get_flagged(src + 2 * rr + 1);
+      }
+    }
+    {
+      bool bad = false;
+      unsigned spins = 0;
+      while (true) {
+        bool ready = cq::flag_of(al) == flag && cq::flag_of(ah) == flag;
+#pragma unroll
+        for (int k = 0; k < KR; ++k)
+          ready = ready && cq::flag_of(lo[k]) == flag && cq::flag_of(hi[k]) == flag;
+        if (ready) break;
+        if (timed_out(spins)) {
+          bad = true;
+          break;
+        }
+        if (cq::flag_of(al) != flag) al = cq::get_flagged(src);
+        if (cq::flag_of(ah) != flag) ah = cq::get_flagged(src + 1);
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+          const int rr = tid + NT * k;
+          if (cq::flag_of(lo[k]) != flag) lo[k] = cq::get_flagged(src + 2 * rr);
+          if (cq::flag_of(hi[k]) != flag) hi[k] = cq::get_flagged(src + 2 * rr + 1);
+        }
+      }
+      if (bad) s_bad = 1;
+    }
+    const double alpha = cq::join_halves(al, ah);
+    double beta = 0.0, tau = 0.0, denom = 1.0;
     if (nup != 0.0) {
       beta = alpha >= 0.0 ? -nup : nup;
       tau = (beta - alpha) / beta;
-      const double denom = alpha - beta;
-      for (int r = tid; r < len; r += kRegThreads) vv[r] = r == 0 ? 1.0 : xv[r] / denom;
+      denom = alpha - beta;
     }
-    if (g == owner && tid == 0) {
-      a.J[i] = p;
-      cq::st_agent(&a.beta[i], beta);
+    // tau = 0 (nothing left below row i): v = 0 leaves every column as is.
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int rr = tid + NT * k;
+      if (rr < len)
+        vv[i + rr] = tau == 0.0 ? 0.0
+                     : rr == 0  ? 1.0
+                                : cq::join_halves(lo[k], hi[k]) / denom;
+    }
+    if (tid == 0) {
+      if (i > 0) vv[i - 1] = 0.0;
+      bneg[i] = beta < 0.0 ? 1 : 0;
+      if (g == owner && valid) a.J[i] = p;
     }
     __syncthreads();
 #pragma unroll
@@ -477,52 +563,50 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
         bdiag[k] = beta;
       }
     }
-    // Apply I - tau v v^T to the alive columns: dot products first, then the
-    // update and the new norms; v is streamed from LDS in both passes (the
-    // compiler barrier keeps the second pass from holding the first pass's
-    // loads in registers).
-    if (tau != 0.0) {
+    // Apply I - tau v v^T to the alive columns, then recompute their norms
+    // over rows i+1..d-1 (row lane + 64 q is below row i exactly when q > qi).
+    {
       double w[CPW];
 #pragma unroll
       for (int k = 0; k < CPW; ++k) w[k] = 0.0;
 #pragma unroll
       for (int q = 0; q < RPL; ++q) {
-        const int r = lane + cq::kWave * q;
-        const double vq = (r >= i && r < d) ? vv[r - i] : 0.0;
+        const double vq = vv[lane + cq::kWave * q];
 #pragma unroll
         for (int k = 0; k < CPW; ++k) w[k] += vq * X[k][q];
       }
 #pragma unroll
-      for (int k = 0; k < CPW; ++k) w[k] = alive[k] ? tau * cq::wave_sum(w[k]) : 0.0;
-      asm volatile("" ::: "memory");
+      for (int k = 0; k < CPW; ++k) w[k] = cq::wave_sum_dpp(w[k]);
+#pragma unroll
+      for (int k = 0; k < CPW; ++k) w[k] = alive[k] ? tau * w[k] : 0.0;
+      // Wide columns: read v from LDS again rather than holding it in VGPRs
+      // next to the columns (the compiler barrier stops it from keeping the
+      // first pass's loads live).
+      if (!kHoldV) asm volatile("" ::: "memory");
+      const int qi = (i - lane) >> 6;
+      double nn[CPW];
+#pragma unroll
+      for (int k = 0; k < CPW; ++k) nn[k] = 0.0;
 #pragma unroll
       for (int q = 0; q < RPL; ++q) {
-        const int r = lane + cq::kWave * q;
-        const double vq = (r >= i && r < d) ? vv[r - i] : 0.0;
+        const double vq = vv[lane + cq::kWave * q];
 #pragma unroll
-        for (int k = 0; k < CPW; ++k) X[k][q] -= w[k] * vq;
+        for (int k = 0; k < CPW; ++k) {
+          X[k][q] -= w[k] * vq;
+          nn[k] += q > qi ? X[k][q] * X[k][q] : 0.0;
+        }
       }
-    }
 #pragma unroll
-    for (int k = 0; k < CPW; ++k) {
-      if (!alive[k]) continue;
-      double nn = 0.0;
+      for (int k = 0; k < CPW; ++k) nrm[k] = cq::wave_sum_dpp(nn[k]);
 #pragma unroll
-      for (int q = 0; q < RPL; ++q) {
-        const int r = lane + cq::kWave * q;
-        if (r > i) nn += X[k][q] * X[k][q];
-      }
-      nrm[k] = sqrt(cq::wave_sum(nn));
+      for (int k = 0; k < CPW; ++k) nrm[k] = alive[k] ? sqrt(nrm[k]) : -1.0;
     }
     publish(i + 1, i + 1);
   }
-  {
-    double v;
-    int c;
-    if (!gather(n, v, c)) {
-      if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
-      return;
-    }
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
+    return;
   }
   // Assemble R (column step[k] of R holds owned column k), diag(R) >= 0.
 #pragma unroll
@@ -536,8 +620,7 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
       if (r < n) {
         double val = 0.0;
         if (r < sc) {
-          const double br = cq::ld_agent(&a.beta[r]);
-          val = br < 0.0 ? -X[k][q] : X[k][q];
+          val = bneg[r] ? -X[k][q] : X[k][q];
         } else if (r == sc) {
           val = fabs(bdiag[k]);
         }
@@ -547,9 +630,12 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
   }
 }
 
-// Zero the step tags and the abort word before a cooperative launch.
-__global__ void qrcp_reset_kernel(unsigned* sync_words, int nwords) {
-  for (int i = threadIdx.x; i < nwords; i += blockDim.x) sync_words[i] = 0u;
+// Zero the exchange words (flags included) and the abort word before a
+// cooperative launch.
+__global__ void qrcp_reset_kernel(uint64_t* words, size_t nwords) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nwords;
+       i += (size_t)gridDim.x * blockDim.x)
+    words[i] = 0ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -630,7 +716,7 @@ namespace cqh {
 static const int kRplSet[] = {1, 2, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40};
 
 static int threads_for(int rpl) { return rpl <= 20 ? 512 : 256; }
-static int cpw_for(int rpl) { return rpl == 20 ? 3 : 4; }
+static int cpw_for(int rpl) { return rpl == 20 ? 3 : rpl >= 32 ? 2 : 4; }
 
 QrcpPlan plan_qrcp(int d, int n) {
   const Device& dev = device_info();
@@ -646,12 +732,12 @@ QrcpPlan plan_qrcp(int d, int n) {
     p.threads = threads_for(p.rpl);
     const int per_block = (p.threads / 64) * p.cpw;
     const int G = (n + per_block - 1) / per_block;
-    if (G <= dev.num_cu && G <= p.threads) {
+    if (G <= dev.num_cu && G <= kRegMaxG) {
       p.reg = true;
       p.nblocks = G;
       p.cols_per_block = per_block;
       p.lds_resident = false;
-      p.lds_bytes = (size_t)2 * ((d + 1) & ~1) * 8;
+      p.lds_bytes = (size_t)64 * p.rpl * 8 + (((size_t)n + 7) & ~(size_t)7);
     }
   }
   if (!p.reg) {
@@ -665,10 +751,16 @@ QrcpPlan plan_qrcp(int d, int n) {
     p.lds_bytes = qrcp_lds_bytes(d, cols, p.lds_resident);
   }
   const int G = p.nblocks;
-  p.stage_bytes = align256((size_t)2 * G * d * 8);
-  // candidate norms, columns and tags, per parity and workgroup
-  p.cand_bytes = align256((size_t)2 * G * 8) + align256((size_t)2 * G * 4) +
-                 align256((size_t)2 * G * 4);
+  if (p.reg) {
+    // flagged words: two per staged double, four per candidate
+    p.stage_bytes = align256((size_t)2 * G * 2 * d * 8);
+    p.cand_bytes = align256((size_t)2 * G * 4 * 8);
+  } else {
+    p.stage_bytes = align256((size_t)2 * G * d * 8);
+    // candidate norms, columns and tags, per parity and workgroup
+    p.cand_bytes = align256((size_t)2 * G * 8) + align256((size_t)2 * G * 4) +
+                   align256((size_t)2 * G * 4);
+  }
   p.beta_bytes = align256((size_t)n * 8);
   p.sync_bytes = 256;
   return p;
@@ -676,7 +768,8 @@ QrcpPlan plan_qrcp(int d, int n) {
 
 static const void* reg_kernel(int rpl) {
 #define CQ_REG(R) \
-  if (rpl == R) return (const void*)qrcp_reg_kernel<(R <= 20 ? 512 : 256), R, (R == 20 ? 3 : 4)>;
+  if (rpl == R)                                                                   \
+    return (const void*)qrcp_reg_kernel<(R <= 20 ? 512 : 256), R, (R == 20 ? 3 : R >= 32 ? 2 : 4)>;
   CQ_REG(1) CQ_REG(2) CQ_REG(4) CQ_REG(6) CQ_REG(8) CQ_REG(10)
   CQ_REG(12) CQ_REG(16) CQ_REG(20) CQ_REG(24) CQ_REG(32) CQ_REG(40)
 #undef CQ_REG
@@ -708,14 +801,22 @@ hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, 
   a.tag = reinterpret_cast<unsigned*>(cb + align256((size_t)2 * G * 8) +
                                       align256((size_t)2 * G * 4));
   a.beta = reinterpret_cast<double*>(base + p.stage_bytes + p.cand_bytes);
+  a.fstage = reinterpret_cast<uint64_t*>(base);
+  a.fcand = reinterpret_cast<uint64_t*>(base + p.stage_bytes);
   a.abort = reinterpret_cast<int*>(base + p.stage_bytes + p.cand_bytes + p.beta_bytes);
   a.info = info;
 
-  // Zero the tags and the abort word before the cooperative launch.
-  hipLaunchKernelGGL(qrcp_reset_kernel, dim3(1), dim3(256), 0, s, a.tag, 2 * G);
+  // Zero the exchange words (all flagged words, or the tags) and the abort
+  // word before the cooperative launch.
+  uint64_t* zero_at = p.reg ? a.fstage : reinterpret_cast<uint64_t*>(a.tag);
+  const size_t zero_words =
+      p.reg ? (p.stage_bytes + p.cand_bytes) / 8 : align256((size_t)2 * G * 4) / 8;
+  const int zero_blocks = (int)std::min<size_t>(1024, (zero_words + 255) / 256);
+  hipLaunchKernelGGL(qrcp_reset_kernel, dim3(zero_blocks), dim3(256), 0, s, zero_at, zero_words);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(qrcp_reset_kernel, dim3(1), dim3(64), 0, s, (unsigned*)a.abort, 1);
+  hipLaunchKernelGGL(qrcp_reset_kernel, dim3(1), dim3(64), 0, s,
+                     reinterpret_cast<uint64_t*>(a.abort), (size_t)1);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
 

@@ -211,6 +211,134 @@ saso_partial_kernel(const double* __restrict__ A, int64_t lda, int64_t m, int64_
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-accumulator variant of the partial sketch. Thread t owns targets
+// r = t + 256 i (i < T) for all NC columns of the block, held in registers.
+// Per sub-chunk it walks its T segments as one sequence (so lanes with short
+// segments do not wait at every target boundary), reading whole staged rows
+// of A (NC contiguous doubles) from LDS. Within a target the order of the
+// additions is ascending source row; across sub-chunks it is sub-chunk order.
+// ---------------------------------------------------------------------------
+template <int T, int NC>
+__global__ void __launch_bounds__(kThreads)
+saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, int64_t n, int d,
+                        int nnz, int ts, int subs_per_chunk, int nsub,
+                        const int32_t* __restrict__ seg, const uint16_t* __restrict__ list,
+                        double* __restrict__ part, int64_t part_ld, int64_t part_stride,
+                        double scale, double* __restrict__ Ahat, int64_t ldah, int direct,
+                        cqrrpt_info_t* info) {
+  extern __shared__ double smem[];
+  double* tile = smem;                                                   // ts * NC
+  int* sseg = reinterpret_cast<int*>(tile + (size_t)ts * NC);           // d + 1
+  uint16_t* slst = reinterpret_cast<uint16_t*>(sseg + ((d + 1 + 3) & ~3));  // ts * nnz
+
+  const int tid = threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * NC;
+  const int ncols = (int)((n - c0) < NC ? (n - c0) : NC);
+  const int q = blockIdx.y;
+
+  double acc[T][NC];
+#pragma unroll
+  for (int i = 0; i < T; ++i)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[i][c] = 0.0;
+
+  const int sb0 = q * subs_per_chunk;
+  const int sb1 = min(nsub, sb0 + subs_per_chunk);
+  for (int sb = sb0; sb < sb1; ++sb) {
+    const int64_t j0 = (int64_t)sb * ts;
+    const int rows_here = (int)((m - j0) < ts ? (m - j0) : ts);
+    __syncthreads();
+    for (int e = tid; e < ts * NC; e += kThreads) {
+      const int c = e / ts;
+      const int jl = e - c * ts;
+      double v = 0.0;
+      if (jl < rows_here && c < ncols) v = A[(j0 + jl) + (c0 + c) * lda];
+      tile[jl * NC + c] = v;
+    }
+    const int32_t* segb = seg + (int64_t)sb * (d + 1);
+    for (int r = tid; r <= d; r += kThreads) sseg[r] = segb[r];
+    const uint16_t* lb = list + (int64_t)sb * ts * nnz;
+    const int nent = rows_here * nnz;
+    for (int e = tid; e < nent; e += kThreads) slst[e] = lb[e];
+    __syncthreads();
+
+    // This thread's segments, walked as one sequence.
+    int bounds[T + 1];
+    int total = 0;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+      const int r = tid + kThreads * i;
+      bounds[i] = r < d ? sseg[r] : 0;
+      const int len = r < d ? sseg[r + 1] - sseg[r] : 0;
+      total += len;
+    }
+    int cur = 0;                       // index of the current target
+    int e = bounds[0];
+    int left = (tid < d) ? sseg[tid + 1] - sseg[tid] : 0;  // entries left in it
+    double s[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s[c] = 0.0;
+    for (int it = 0; it < total; ++it) {
+      while (left == 0) {
+        // Flush the finished target and move to the next one.
+#pragma unroll
+        for (int i = 0; i < T; ++i)
+          if (i == cur) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[i][c] += s[c];
+          }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) s[c] = 0.0;
+        ++cur;
+        int nb = 0, nl = 0;
+#pragma unroll
+        for (int i = 0; i < T; ++i)
+          if (i == cur) {
+            const int r = tid + kThreads * i;
+            nb = r < d ? sseg[r] : 0;
+            nl = r < d ? sseg[r + 1] - sseg[r] : 0;
+          }
+        e = nb;
+        left = nl;
+      }
+      const unsigned v = slst[e];
+      const double* row = tile + (v >> 1) * NC;
+      if (v & 1u) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) s[c] -= row[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) s[c] += row[c];
+      }
+      ++e;
+      --left;
+    }
+#pragma unroll
+    for (int i = 0; i < T; ++i)
+      if (i == cur) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[i][c] += s[c];
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < T; ++i) {
+    const int r = tid + kThreads * i;
+    if (r >= d) continue;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if (c >= ncols) continue;
+      if (direct) {
+        const double o = acc[i][c] * scale;
+        if (!isfinite(o)) cq::set_status(info, CQRRPT_ENONFINITE);
+        Ahat[r + (c0 + c) * ldah] = o;
+      } else {
+        part[q * part_stride + r + (c0 + c) * part_ld] = acc[i][c];
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kThreads)
 saso_reduce_kernel(const double* __restrict__ part, int64_t part_ld, int64_t part_stride,
                    int nchunk, int d, int64_t n, double scale, double* __restrict__ Ahat,
@@ -236,6 +364,28 @@ size_t index_lds_bytes(int d, int nnz, int ts) {
   return (size_t)((d + 1 + 3) & ~3) * 4 + (size_t)3 * ts * nnz * 2;
 }
 
+size_t partial_reg_lds_bytes(int d, int nnz, int ts, int nc) {
+  return (size_t)ts * nc * 8 + (size_t)((d + 1 + 3) & ~3) * 4 + (size_t)ts * nnz * 2;
+}
+
+// Targets per thread (rounded up to an instantiated value) for d rows.
+int reg_targets(int d) {
+  static const int kT[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
+  const int need = (d + kThreads - 1) / kThreads;
+  for (int t : kT)
+    if (t >= need) return t;
+  return 0;
+}
+
+const void* reg_partial_kernel(int T, int NC) {
+#define CQ_SK(TT, CC) \
+  if (T == TT && NC == CC) return (const void*)saso_partial_reg_kernel<TT, CC>;
+  CQ_SK(1, 8) CQ_SK(2, 8) CQ_SK(3, 8) CQ_SK(4, 8) CQ_SK(5, 8) CQ_SK(6, 8) CQ_SK(8, 8)
+  CQ_SK(10, 8) CQ_SK(12, 4) CQ_SK(16, 4)
+#undef CQ_SK
+  return nullptr;
+}
+
 size_t partial_lds_bytes(int d, int nnz, int ts, int nc) {
   return (size_t)d * nc * 8 + (size_t)ts * (nc + 1) * 8 + (size_t)((d + 1 + 3) & ~3) * 4 +
          (size_t)ts * nnz * 2;
@@ -259,15 +409,22 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int d, int nnz) {
   p.ts = sub_rows(nnz);
   p.nsub = (int)((m + p.ts - 1) / p.ts);
   const size_t budget = dev.lds_per_block;
-  int nc = 16;
-  while (nc > 1 && partial_lds_bytes(d, nnz, p.ts, nc) > budget) nc >>= 1;
-  while (nc > 1 && nc / 2 >= n) nc >>= 1;
+  p.reg_t = reg_targets(d);
+  int nc;
+  if (p.reg_t > 0) {
+    nc = p.reg_t <= 10 ? 8 : 4;
+    p.lds_bytes = partial_reg_lds_bytes(d, nnz, p.ts, nc);
+  } else {
+    nc = 16;
+    while (nc > 1 && partial_lds_bytes(d, nnz, p.ts, nc) > budget) nc >>= 1;
+    while (nc > 1 && nc / 2 >= n) nc >>= 1;
+    p.lds_bytes = partial_lds_bytes(d, nnz, p.ts, nc);
+  }
   p.nc = nc;
-  p.lds_bytes = partial_lds_bytes(d, nnz, p.ts, nc);
   const int64_t ncb = (n + nc - 1) / nc;
-  // Enough workgroups to cover the chip about twice; each chunk keeps at
-  // least 8 sub-chunks so the partial sums stay small next to A.
-  int64_t want = (2 * dev.num_cu + ncb - 1) / ncb;
+  // Enough workgroups to cover the chip about three times; each chunk keeps
+  // at least 8 sub-chunks so the partial sums stay small next to A.
+  int64_t want = (3 * dev.num_cu + ncb - 1) / ncb;
   int64_t maxchunks = p.nsub / 8;
   if (maxchunks < 1) maxchunks = 1;
   if (want > maxchunks) want = maxchunks;
@@ -307,16 +464,29 @@ hipError_t launch_sketch(const SketchPlan& p, const double* A, int64_t lda, int6
   e = hipGetLastError();
   if (e != hipSuccess) return e;
 
-  e = hipFuncSetAttribute((const void*)saso_partial_kernel,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
-  if (e != hipSuccess) return e;
   const int64_t ncb = (n + p.nc - 1) / p.nc;
   const int direct = p.nchunk == 1;
-  hipLaunchKernelGGL(saso_partial_kernel, dim3((unsigned)ncb, p.nchunk), dim3(kThreads),
-                     p.lds_bytes, s, A, lda, m, n, d, nnz, p.ts, p.nc, p.subs_per_chunk, p.nsub,
-                     seg, list, part, (int64_t)d, (int64_t)d * n, scale, Ahat, ldah, direct,
-                     info);
-  e = hipGetLastError();
+  if (p.reg_t > 0) {
+    const void* fn = reg_partial_kernel(p.reg_t, p.nc);
+    if (!fn) return hipErrorInvalidValue;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
+    if (e != hipSuccess) return e;
+    int64_t part_ld = d, part_stride = (int64_t)d * n;
+    void* args[] = {(void*)&A, (void*)&lda, (void*)&m, (void*)&n, (void*)&d, (void*)&nnz,
+                    (void*)&p.ts, (void*)&p.subs_per_chunk, (void*)&p.nsub, (void*)&seg,
+                    (void*)&list, (void*)&part, (void*)&part_ld, (void*)&part_stride,
+                    (void*)&scale, (void*)&Ahat, (void*)&ldah, (void*)&direct, (void*)&info};
+    e = hipLaunchKernel(fn, dim3((unsigned)ncb, p.nchunk), dim3(kThreads), args, p.lds_bytes, s);
+  } else {
+    e = hipFuncSetAttribute((const void*)saso_partial_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(saso_partial_kernel, dim3((unsigned)ncb, p.nchunk), dim3(kThreads),
+                       p.lds_bytes, s, A, lda, m, n, d, nnz, p.ts, p.nc, p.subs_per_chunk,
+                       p.nsub, seg, list, part, (int64_t)d, (int64_t)d * n, scale, Ahat, ldah,
+                       direct, info);
+    e = hipGetLastError();
+  }
   if (e != hipSuccess || direct) return e;
   const int64_t total = (int64_t)d * n;
   int64_t grid = (total + kThreads - 1) / kThreads;

@@ -40,13 +40,6 @@ struct CholArgs {
   double cond_max;
 };
 
-CQ_INLINE double readlane_d(double x, int l) {
-  const long long v = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), l);
-  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
 CQ_INLINE bool chol_sync(const cq::GridBarrier& b) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   const bool ok = cq::grid_sync(b);
@@ -133,7 +126,7 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
 #pragma unroll
         for (int j = 0; j < kB; ++j) {
           if (fl < 0) {
-            const double piv = readlane_d(cl[j], j);
+            const double piv = cq::readlane_d(cl[j], j);
             if (!(piv > 0.0) || !isfinite(piv)) {
               fl = j;
             } else {
@@ -141,7 +134,7 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
               cl[j] = lane == j ? rj : (lane > j ? cl[j] / rj : cl[j]);
 #pragma unroll
               for (int c1 = j + 1; c1 < kB; ++c1) {
-                const double sv = readlane_d(cl[j], c1);
+                const double sv = cq::readlane_d(cl[j], c1);
                 cl[c1] -= lane >= c1 ? sv * cl[j] : 0.0;
               }
             }

@@ -46,9 +46,23 @@ template <typename TC> CQ_INLINE int acc_row(int lq, int r);
 template <> CQ_INLINE int acc_row<double>(int lq, int r) { return lq + 4 * r; }
 template <> CQ_INLINE int acc_row<float>(int lq, int r) { return 4 * lq + r; }
 
+// LDS layout of the triangular solve (in units of TC):
+//   [0, kStage)          staging: 2 x (A tile kKB x kRT, R tile kKB x kNB),
+//                        aliased by Ts (kNB x kTsLd) after the GEMM phase
+//   [kStage, +kRdSz)     diagonal block of R
+//   [.., +kNB)           reciprocals of its diagonal
+constexpr int kAtSz = kKB * kRT;
+constexpr int kRtSz = kKB * kNB;
+constexpr int kStage = 2 * (kAtSz + kRtSz) > kNB * kTsLd ? 2 * (kAtSz + kRtSz) : kNB * kTsLd;
+constexpr int kRdSz = kNB * kRdLd;
+
 // TB: type of B, TX: type of X, TC: arithmetic type. Wave w computes the
 // 32 x 32 sub-block (rows 32 (w / 2), columns 32 (w % 2)) of the 128 x 64
-// output block with 2 x 2 MFMA tiles.
+// output block with 2 x 2 MFMA tiles. Each K step stages the X tile
+// (kRT x kKB) and the R tile (kKB x kNB) through LDS, double-buffered, with
+// the next step's global loads in flight during the current step's MFMAs.
+// The block's B values and diagonal R block are loaded into registers
+// before the GEMM phase, so their latency overlaps it.
 template <typename TB, typename TX, typename TC>
 __global__ void __launch_bounds__(kTThreads)
 trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X, int64_t ldx,
@@ -56,10 +70,10 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
             const cqrrpt_info_t* info) {
   typedef typename MfmaAcc<TC>::type acc_t;
   extern __shared__ unsigned char smem_raw[];
-  TC* Ts = reinterpret_cast<TC*>(smem_raw);          // [kNB][kTsLd], aliased by Rt
-  TC* Rt = Ts;                                        // [2][kKB][kNB]
-  TC* Rd = Ts + kNB * kTsLd;                          // [kNB][kRdLd]
-  TC* rinv = Rd + kNB * kRdLd;                        // [kNB]
+  TC* stage = reinterpret_cast<TC*>(smem_raw);
+  TC* Ts = stage;
+  TC* Rd = stage + kStage;
+  TC* rinv = Rd + kRdSz;
 
   if (info->status != 0) return;
   const int64_t k = *kdev;
@@ -72,87 +86,17 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
   const int l16 = lane & 15;
   const int lq = lane >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * kRT;
-  const int64_t wrow = row0 + 32 * wr;
   const int nblk = (int)((k + kNB - 1) / kNB);
+  constexpr int kALoads = kAtSz / kTThreads;  // 8
+  constexpr int kRLoads = kRtSz / kTThreads;  // 4
+  constexpr int kDLoads = kNB * kNB / kTThreads;  // 8
 
   for (int jb = 0; jb < nblk; ++jb) {
     const int64_t c0 = (int64_t)jb * kNB;
     const int K = (int)c0;
-    acc_t acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
-    if (K > 0) {
-      // Register prefetch of the next step's A fragments and R share; the R
-      // staging tiles are double-buffered in LDS.
-      TC af[2][kKB / 4], an[2][kKB / 4];
-      TC ra[4];
-      auto load_a = [&](TC (&dst)[2][kKB / 4], int kk) {
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const int64_t r = wrow + 16 * a + l16;
-#pragma unroll
-          for (int s = 0; s < kKB / 4; ++s) {
-            const int64_t kc = kk + 4 * s + lq;
-            dst[a][s] = r < m ? (TC)X[r + kc * ldx] : (TC)0;
-          }
-        }
-      };
-      auto load_r = [&](int kk) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int e = tid + kTThreads * q;
-          const int kr = e & (kKB - 1);
-          const int cc = e / kKB;
-          const int64_t col = c0 + cc;
-          ra[q] = col < k ? (TC)R[(kk + kr) + col * ldr] : (TC)0;
-        }
-      };
-      auto store_r = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int e = tid + kTThreads * q;
-          const int kr = e & (kKB - 1);
-          const int cc = e / kKB;
-          Rt[buf * kKB * kNB + kr * kNB + cc] = ra[q];
-        }
-      };
-      load_a(af, 0);
-      load_r(0);
-      store_r(0);
-      __syncthreads();
-      for (int kk = 0; kk < K; kk += kKB) {
-        const int buf = (kk / kKB) & 1;
-        const bool more = kk + kKB < K;
-        if (more) {
-          load_a(an, kk + kKB);
-          load_r(kk + kKB);
-        }
-        const TC* rb = Rt + buf * kKB * kNB + 32 * wc;
-#pragma unroll
-        for (int s = 0; s < kKB / 4; ++s) {
-          TC bf[2];
-#pragma unroll
-          for (int b = 0; b < 2; ++b) bf[b] = rb[(4 * s + lq) * kNB + 16 * b + l16];
-#pragma unroll
-          for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = mfma(af[a][s], bf[b], acc[a][b]);
-        }
-        if (more) store_r(buf ^ 1);
-        __syncthreads();
-        if (more) {
-#pragma unroll
-          for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int s = 0; s < kKB / 4; ++s) af[a][s] = an[a][s];
-        }
-      }
-    }
-
-    // T = B[rows, gather(block)] - acc, into LDS (column-major, padded).
+    // Prefetch this block's B values (accumulator layout) and diagonal R.
+    TC breg[2][2][4];
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int cl = 32 * wc + 16 * b + l16;
@@ -160,19 +104,17 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
       const bool cvalid = col < k;
       const int64_t gcol = cvalid ? (gather ? gather[col] : col) : 0;
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int rl = 32 * wr + 16 * a + acc_row<TC>(lq, r);
-          const int64_t row = row0 + rl;
-          TC bv = (TC)0;
-          if (cvalid && row < m) bv = (TC)B[row + gcol * ldb];
-          Ts[cl * kTsLd + rl] = bv - acc[a][b][r];
+          const int64_t row = row0 + 32 * wr + 16 * a + acc_row<TC>(lq, r);
+          breg[a][b][r] = (cvalid && row < m) ? (TC)B[row + gcol * ldb] : (TC)0;
         }
-      }
     }
-    // Diagonal block of R (identity past k) and reciprocals of its diagonal.
-    for (int e = tid; e < kNB * kNB; e += kTThreads) {
+    TC dreg[kDLoads];
+#pragma unroll
+    for (int q = 0; q < kDLoads; ++q) {
+      const int e = tid + kTThreads * q;
       const int i = e & (kNB - 1);
       const int j = e >> 6;
       TC v;
@@ -180,7 +122,92 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
         v = i <= j ? (TC)R[(c0 + i) + (c0 + j) * ldr] : (TC)0;
       else
         v = i == j ? (TC)1 : (TC)0;
-      Rd[i * kRdLd + j] = v;
+      dreg[q] = v;
+    }
+
+    acc_t acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+    if (K > 0) {
+      TC areg[kALoads], rreg[kRLoads];
+      auto load = [&](int kk) {
+#pragma unroll
+        for (int q = 0; q < kALoads; ++q) {
+          const int e = tid + kTThreads * q;
+          const int rr = e & (kRT - 1);
+          const int kc = e >> 7;
+          const int64_t row = row0 + rr;
+          areg[q] = row < m ? (TC)X[row + (int64_t)(kk + kc) * ldx] : (TC)0;
+        }
+#pragma unroll
+        for (int q = 0; q < kRLoads; ++q) {
+          const int e = tid + kTThreads * q;
+          const int kr = e & (kKB - 1);
+          const int cc = e / kKB;
+          const int64_t col = c0 + cc;
+          rreg[q] = col < k ? (TC)R[(kk + kr) + col * ldr] : (TC)0;
+        }
+      };
+      auto store = [&](int buf) {
+        TC* At = stage + buf * (kAtSz + kRtSz);
+        TC* Rt = At + kAtSz;
+#pragma unroll
+        for (int q = 0; q < kALoads; ++q) {
+          const int e = tid + kTThreads * q;
+          At[(e >> 7) * kRT + (e & (kRT - 1))] = areg[q];
+        }
+#pragma unroll
+        for (int q = 0; q < kRLoads; ++q) {
+          const int e = tid + kTThreads * q;
+          Rt[(e & (kKB - 1)) * kNB + e / kKB] = rreg[q];
+        }
+      };
+      load(0);
+      store(0);
+      __syncthreads();
+      for (int kk = 0; kk < K; kk += kKB) {
+        const int buf = (kk / kKB) & 1;
+        const bool more = kk + kKB < K;
+        if (more) load(kk + kKB);
+        const TC* At = stage + buf * (kAtSz + kRtSz);
+        const TC* Rt = At + kAtSz;
+#pragma unroll
+        for (int s = 0; s < kKB / 4; ++s) {
+          TC af[2], bf[2];
+#pragma unroll
+          for (int a = 0; a < 2; ++a) af[a] = At[(4 * s + lq) * kRT + 32 * wr + 16 * a + l16];
+#pragma unroll
+          for (int b = 0; b < 2; ++b) bf[b] = Rt[(4 * s + lq) * kNB + 32 * wc + 16 * b + l16];
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = mfma(af[a], bf[b], acc[a][b]);
+        }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+      }
+    }
+
+    // Diagonal block, reciprocals, and T = B - acc (Ts aliases the staging
+    // buffers, free after the GEMM phase's last barrier).
+#pragma unroll
+    for (int q = 0; q < kDLoads; ++q) {
+      const int e = tid + kTThreads * q;
+      Rd[(e & (kNB - 1)) * kRdLd + (e >> 6)] = dreg[q];
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int cl = 32 * wc + 16 * b + l16;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rl = 32 * wr + 16 * a + acc_row<TC>(lq, r);
+          Ts[cl * kTsLd + rl] = breg[a][b][r] - acc[a][b][r];
+        }
     }
     __syncthreads();
     if (tid < kNB) rinv[tid] = (TC)1 / Rd[tid * kRdLd + tid];
@@ -351,7 +378,7 @@ template <typename TB, typename TX, typename TC>
 hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX* X, int64_t ldx,
                             const double* R, int64_t ldr, int64_t m, const int64_t* kdev,
                             const cqrrpt_info_t* info, hipStream_t s) {
-  const size_t lds = ((size_t)kNB * kTsLd + (size_t)kNB * kRdLd + kNB) * sizeof(TC);
+  const size_t lds = ((size_t)kStage + kRdSz + kNB) * sizeof(TC);
   const void* fn = (const void*)trsm_kernel<TB, TX, TC>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
