@@ -4,16 +4,10 @@
 //   * Q-factor      Q = M_pre R_pre^{-1}                   (same kernel, in place),
 //   * Gram          G = M_pre^T M_pre                       (split-K, fixed-order sum).
 //
-// Triangular solve X R = B (R upper, non-unit), left-looking per row tile.
-// A workgroup owns kRT rows and walks the column blocks of width kNB:
-//   acc = X[rows, :c0] R[:c0, block]          (MFMA 16x16x4, K grows with c0)
-//   T   = B[rows, gather(block)] - acc
-//   X[rows, block] = T R[block, block]^{-1}   (row-wise substitution, exact
-//                                              division by the diagonal via
-//                                              its reciprocal)
 // Every row is solved by the same column-oriented substitution a textbook
-// TRSM performs, so each row keeps its backward stability; no explicit inverse
-// of R is formed.
+// TRSM performs (inside 16-column tiles; the rest are matrix products of
+// already solved columns), so each row keeps its backward stability; no
+// explicit inverse of R is formed.
 #include <math.h>
 
 #include "common.h"
@@ -21,13 +15,6 @@
 namespace {
 
 constexpr int kThreads = 256;     // SYRK
-constexpr int kTThreads = 512;    // triangular solve: 8 waves, 2 per SIMD
-constexpr int kRT = 128;   // rows per workgroup
-constexpr int kNB = 64;    // column block
-constexpr int kKB = 32;    // K per staging step
-constexpr int kTsLd = kRT + 1;
-constexpr int kRdLd = kNB + 1;
-
 template <typename T> struct MfmaAcc;
 template <> struct MfmaAcc<double> { typedef d4_t type; };
 template <> struct MfmaAcc<float> { typedef f4_t type; };
@@ -46,206 +33,262 @@ template <typename TC> CQ_INLINE int acc_row(int lq, int r);
 template <> CQ_INLINE int acc_row<double>(int lq, int r) { return lq + 4 * r; }
 template <> CQ_INLINE int acc_row<float>(int lq, int r) { return 4 * lq + r; }
 
-// LDS layout of the triangular solve (in units of TC):
-//   [0, kStage)          staging: 2 x (A tile kKB x kRT, R tile kKB x kNB),
-//                        aliased by Ts (kNB x kTsLd) after the GEMM phase
-//   [kStage, +kRdSz)     diagonal block of R
-//   [.., +kNB)           reciprocals of its diagonal
-constexpr int kAtSz = kKB * kRT;
-constexpr int kRtSz = kKB * kNB;
-constexpr int kStage = 2 * (kAtSz + kRtSz) > kNB * kTsLd ? 2 * (kAtSz + kRtSz) : kNB * kTsLd;
-constexpr int kRdSz = kNB * kRdLd;
+// Triangular solve X R = B (R upper, non-unit), left-looking per row block.
+// A workgroup of kTThreads owns kRT rows and walks column panels of width
+// kPW:
+//   acc = X[rows, :c0] R[:c0, panel]                 (MFMA)
+// then solves the panel's diagonal block 16 columns at a time:
+//   T_t = B[rows, gather(tile t)] - acc[:, tile t]
+//   X_t = T_t R_tt^{-1}                              (row-wise substitution)
+//   acc[:, tiles > t] += X_t R[tile t, tiles > t]    (MFMA)
+// Wide panels keep the re-reads of the already solved columns (the K operand
+// of the product) at m n^2 / (2 kPW) values in total.
+constexpr int kTThreads = 256;  // 4 waves; two workgroups per CU
+constexpr int kRT = 128;        // rows per workgroup
+constexpr int kPW = 128;        // panel width
+constexpr int kKB = 16;         // K per staging step
+constexpr int kSLd = 144;       // LDS row pitch: 128 + 16 keeps lane groups on distinct banks
 
-// TB: type of B, TX: type of X, TC: arithmetic type. Wave w computes the
-// 32 x 32 sub-block (rows 32 (w / 2), columns 32 (w % 2)) of the 128 x 64
-// output block with 2 x 2 MFMA tiles. Each K step stages the X tile
-// (kRT x kKB) and the R tile (kKB x kNB) through LDS, double-buffered, with
-// the next step's global loads in flight during the current step's MFMAs.
-// The block's B values and diagonal R block are loaded into registers
-// before the GEMM phase, so their latency overlaps it.
+// LDS (units of TC): staging 2 x (X tile kKB x kRT, R tile kKB x kPW), each
+// row padded to kSLd; during the diagonal phase the same space holds the
+// tile of B (then T_t, then X_t; 16 x kRT, column-major), the R strip
+// (16 x kPW) and the accumulator tile (16 x kRT).
+constexpr int kTileSz = kKB * kSLd;
+constexpr int kStageSz = 4 * kTileSz;
+constexpr int kTrsmLds = kStageSz;
+// After the TC area: the panel's gathered column indices (int32).
+constexpr size_t kTrsmLdsBytes(size_t tc_bytes) { return kTrsmLds * tc_bytes + kPW * 4; }
+
+// R[i, j] through a 32-bit element offset (the launcher checks that every
+// offset of the k x k block fits).
+CQ_INLINE double r_at(const double* R, uint32_t ldr, int i, int j) {
+  return R[(uint32_t)i + (uint32_t)j * ldr];
+}
+
+template <typename TC>
+CQ_INLINE TC r_entry(const double* R, uint32_t ldr, int i, int j, int k) {
+  // R[i, j] of the upper triangle; outside the leading k x k block the
+  // identity, so padded columns solve to zero.
+  const int ic = i < k ? i : k - 1, jc = j < k ? j : k - 1;
+  const TC v = (TC)r_at(R, ldr, ic, jc);
+  if (i < k && j < k) return i <= j ? v : (TC)0;
+  return i == j ? (TC)1 : (TC)0;
+}
+
+// TB: type of B, TX: type of X, TC: arithmetic type. Wave w holds the
+// 64 x 64 sub-block (rows 64 (w % 2), panel columns 64 (w / 2)) of the
+// 128 x 128 panel as 4 x 4 MFMA tiles.
 template <typename TB, typename TX, typename TC>
-__global__ void __launch_bounds__(kTThreads)
+__global__ void __launch_bounds__(kTThreads, 2)
 trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X, int64_t ldx,
             const double* __restrict__ R, int64_t ldr, int64_t m, const int64_t* kdev,
             const cqrrpt_info_t* info) {
   typedef typename MfmaAcc<TC>::type acc_t;
   extern __shared__ unsigned char smem_raw[];
-  TC* stage = reinterpret_cast<TC*>(smem_raw);
-  TC* Ts = stage;
-  TC* Rd = stage + kStage;
-  TC* rinv = Rd + kRdSz;
+  TC* lds = reinterpret_cast<TC*>(smem_raw);
+  TC* Tt = lds;                // diagonal phase: B tile / T_t / X_t, [16][kSLd]
+  TC* Rs = lds + kTileSz;      // diagonal phase: R strip, [16][kSLd]
+  TC* Ta = lds + 2 * kTileSz;  // diagonal phase: accumulator tile, [16][kSLd]
+  int* gcols = reinterpret_cast<int*>(lds + kTrsmLds);  // [kPW]
 
   if (info->status != 0) return;
-  const int64_t k = *kdev;
+  const int k = (int)*kdev;
   if (k <= 0) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = wave >> 1;
-  const int wc = wave & 1;
+  const int wr = wave & 1;
+  const int wc = wave >> 1;
   const int l16 = lane & 15;
   const int lq = lane >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * kRT;
-  const int nblk = (int)((k + kNB - 1) / kNB);
-  constexpr int kALoads = kAtSz / kTThreads;  // 8
-  constexpr int kRLoads = kRtSz / kTThreads;  // 4
-  constexpr int kDLoads = kNB * kNB / kTThreads;  // 8
+  constexpr int kLoads = kKB * kRT / kTThreads;  // 8 per operand and step
+  // Element e = tid + 256 q of a 16 x 128 tile: (e & 127, e >> 7) =
+  // (tid & 127, tid / 128 + 2 q) in column-major K tiles, and
+  // (e & 15, e >> 4) = (tid & 15, tid / 16 + 16 q) in row-major R tiles.
+  const int ra = tid & (kRT - 1), ca = tid >> 7;
+  const int rb = tid & 15, cb = tid >> 4;
+  // Rows past m read row m-1 (in bounds); their results are never stored.
+  const int64_t rowa = row0 + ra < m ? row0 + ra : m - 1;
+  const uint32_t ldr32 = (uint32_t)ldr;
 
-  for (int jb = 0; jb < nblk; ++jb) {
-    const int64_t c0 = (int64_t)jb * kNB;
-    const int K = (int)c0;
-
-    // Prefetch this block's B values (accumulator layout) and diagonal R.
-    TC breg[2][2][4];
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int cl = 32 * wc + 16 * b + l16;
-      const int64_t col = c0 + cl;
-      const bool cvalid = col < k;
-      const int64_t gcol = cvalid ? (gather ? gather[col] : col) : 0;
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t row = row0 + 32 * wr + 16 * a + acc_row<TC>(lq, r);
-          breg[a][b][r] = (cvalid && row < m) ? (TC)B[row + gcol * ldb] : (TC)0;
-        }
+  for (int c0 = 0; c0 < k; c0 += kPW) {
+    // Keep the panel offset opaque so address arithmetic is not turned into
+    // loop-carried 64-bit pointers.
+    int c0o = c0;
+    asm volatile("" : "+s"(c0o));
+    const int nt = ((k - c0o < kPW ? k - c0o : kPW) + 15) / 16;
+    // Gathered column of each panel column (clamped past k; those values
+    // are zeroed on load). The previous panel's readers are done: its last
+    // tile step ended after a barrier that follows every load_tile call.
+    if (tid < kPW) {
+      const int col = c0o + tid < k ? c0o + tid : k - 1;
+      gcols[tid] = gather ? (int)gather[col] : col;
     }
-    TC dreg[kDLoads];
+    __syncthreads();
+    // Tile t's B values (column-major 16 x kRT, coalesced) and R strip,
+    // one tile ahead of use.
+    TC breg[kLoads], sreg[kLoads];
+    auto load_tile = [&](int t) {
 #pragma unroll
-    for (int q = 0; q < kDLoads; ++q) {
-      const int e = tid + kTThreads * q;
-      const int i = e & (kNB - 1);
-      const int j = e >> 6;
-      TC v;
-      if (c0 + i < k && c0 + j < k)
-        v = i <= j ? (TC)R[(c0 + i) + (c0 + j) * ldr] : (TC)0;
-      else
-        v = i == j ? (TC)1 : (TC)0;
-      dreg[q] = v;
-    }
+      for (int q = 0; q < kLoads; ++q) {
+        const int cl = 16 * t + ca + 2 * q;
+        const TC v = (TC)B[rowa + (int64_t)gcols[cl] * ldb];
+        breg[q] = c0o + cl < k ? v : (TC)0;
+      }
+#pragma unroll
+      for (int q = 0; q < kLoads; ++q)
+        sreg[q] = r_entry<TC>(R, ldr32, c0o + 16 * t + rb, c0o + cb + 16 * q, k);
+    };
+    load_tile(0);
+    acc_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
-    acc_t acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-
-    if (K > 0) {
-      TC areg[kALoads], rreg[kRLoads];
+    if (c0o > 0) {
+      TC areg[kLoads], rreg[kLoads];
       auto load = [&](int kk) {
+        const TX* xs = X + rowa + (int64_t)(kk + ca) * ldx;
 #pragma unroll
-        for (int q = 0; q < kALoads; ++q) {
-          const int e = tid + kTThreads * q;
-          const int rr = e & (kRT - 1);
-          const int kc = e >> 7;
-          const int64_t row = row0 + rr;
-          areg[q] = row < m ? (TC)X[row + (int64_t)(kk + kc) * ldx] : (TC)0;
-        }
+        for (int q = 0; q < kLoads; ++q) areg[q] = (TC)xs[(int64_t)(2 * q) * ldx];
+        // R rows kk.. < c0 <= column: strictly above the diagonal.
 #pragma unroll
-        for (int q = 0; q < kRLoads; ++q) {
-          const int e = tid + kTThreads * q;
-          const int kr = e & (kKB - 1);
-          const int cc = e / kKB;
-          const int64_t col = c0 + cc;
-          rreg[q] = col < k ? (TC)R[(kk + kr) + col * ldr] : (TC)0;
+        for (int q = 0; q < kLoads; ++q) {
+          const int col = c0o + cb + 16 * q;
+          const int colc = col < k ? col : k - 1;
+          const TC v = (TC)r_at(R, ldr32, kk + rb, colc);
+          rreg[q] = col < k ? v : (TC)0;
         }
       };
       auto store = [&](int buf) {
-        TC* At = stage + buf * (kAtSz + kRtSz);
-        TC* Rt = At + kAtSz;
+        TC* At = lds + buf * 2 * kTileSz;
+        TC* Rt = At + kTileSz;
 #pragma unroll
-        for (int q = 0; q < kALoads; ++q) {
-          const int e = tid + kTThreads * q;
-          At[(e >> 7) * kRT + (e & (kRT - 1))] = areg[q];
-        }
+        for (int q = 0; q < kLoads; ++q) At[(ca + 2 * q) * kSLd + ra] = areg[q];
 #pragma unroll
-        for (int q = 0; q < kRLoads; ++q) {
-          const int e = tid + kTThreads * q;
-          Rt[(e & (kKB - 1)) * kNB + e / kKB] = rreg[q];
-        }
+        for (int q = 0; q < kLoads; ++q) Rt[rb * kSLd + cb + 16 * q] = rreg[q];
       };
       load(0);
+      __syncthreads();  // the previous panel's diagonal phase is done with LDS
       store(0);
       __syncthreads();
-      for (int kk = 0; kk < K; kk += kKB) {
-        const int buf = (kk / kKB) & 1;
-        const bool more = kk + kKB < K;
-        if (more) load(kk + kKB);
-        const TC* At = stage + buf * (kAtSz + kRtSz);
-        const TC* Rt = At + kAtSz;
+      for (int kk = 0; kk < c0o; kk += kKB) {
+        int kko = kk;
+        asm volatile("" : "+s"(kko));
+        const int buf = (kko / kKB) & 1;
+        const bool more = kko + kKB < c0o;
+        if (more) load(kko + kKB);
+        const TC* At = lds + buf * 2 * kTileSz;
+        const TC* Rt = At + kTileSz;
 #pragma unroll
         for (int s = 0; s < kKB / 4; ++s) {
-          TC af[2], bf[2];
+          TC af[4], bf[4];
 #pragma unroll
-          for (int a = 0; a < 2; ++a) af[a] = At[(4 * s + lq) * kRT + 32 * wr + 16 * a + l16];
+          for (int a = 0; a < 4; ++a) af[a] = At[(4 * s + lq) * kSLd + 64 * wr + 16 * a + l16];
 #pragma unroll
-          for (int b = 0; b < 2; ++b) bf[b] = Rt[(4 * s + lq) * kNB + 32 * wc + 16 * b + l16];
+          for (int b = 0; b < 4; ++b) bf[b] = Rt[(4 * s + lq) * kSLd + 64 * wc + 16 * b + l16];
 #pragma unroll
-          for (int a = 0; a < 2; ++a)
+          for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = mfma(af[a], bf[b], acc[a][b]);
+            for (int b = 0; b < 4; ++b) acc[a][b] = mfma(af[a], bf[b], acc[a][b]);
         }
         if (more) store(buf ^ 1);
         __syncthreads();
       }
     }
 
-    // Diagonal block, reciprocals, and T = B - acc (Ts aliases the staging
-    // buffers, free after the GEMM phase's last barrier).
+    // Diagonal block, one 16-column tile at a time.
+    for (int t = 0; t < nt; ++t) {
+      int to = t;
+      asm volatile("" : "+s"(to));
+      __syncthreads();  // LDS free: GEMM staging or the previous tile's update
+      // The strip's diagonal entries of tile t hold 1 / R_jj (the update
+      // below masks that tile's columns).
 #pragma unroll
-    for (int q = 0; q < kDLoads; ++q) {
-      const int e = tid + kTThreads * q;
-      Rd[(e & (kNB - 1)) * kRdLd + (e >> 6)] = dreg[q];
-    }
+      for (int q = 0; q < kLoads; ++q) {
+        const bool diag = cb + 16 * q == 16 * to + rb;
+        Rs[rb * kSLd + cb + 16 * q] = diag ? (TC)1 / sreg[q] : sreg[q];
+        Tt[(ca + 2 * q) * kSLd + ra] = breg[q];
+      }
+      if (wc == (to >> 2)) {
+        // Column tile t & 3 of this wave's accumulators (selects, no
+        // branches on the accumulators).
+        const int bt = to & 3;
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int cl = 32 * wc + 16 * b + l16;
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+          for (int r = 0; r < 4; ++r) {
+            TC v = acc[a][0][r];
+            v = bt == 1 ? acc[a][1][r] : v;
+            v = bt == 2 ? acc[a][2][r] : v;
+            v = bt == 3 ? acc[a][3][r] : v;
+            Ta[l16 * kSLd + 64 * wr + 16 * a + acc_row<TC>(lq, r)] = v;
+          }
+      }
+      if (to + 1 < nt) load_tile(to + 1);
+      __syncthreads();
+      if (tid < kRT) {
+        // Row tid of the tile: x_j = (T_j - sum_{l<j} x_l R_lj) / R_jj,
+        // applied column by column (right-looking inside the 16 columns).
+        TC x[16];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int rl = 32 * wr + 16 * a + acc_row<TC>(lq, r);
-          Ts[cl * kTsLd + rl] = breg[a][b][r] - acc[a][b][r];
-        }
-    }
-    __syncthreads();
-    if (tid < kNB) rinv[tid] = (TC)1 / Rd[tid * kRdLd + tid];
-    __syncthreads();
-
-    if (tid < kRT) {
-      // Row tid of the block: left-looking over 16-column chunks, so only a
-      // 16-entry register array is live; solved entries go back to Ts.
-      for (int c = 0; c < kNB / 16; ++c) {
-        TC t[16];
-#pragma unroll
-        for (int jj = 0; jj < 16; ++jj) t[jj] = Ts[(16 * c + jj) * kTsLd + tid];
-        for (int i = 0; i < 16 * c; ++i) {
-          const TC x = Ts[i * kTsLd + tid];
-          const TC* rrow = Rd + i * kRdLd + 16 * c;
-#pragma unroll
-          for (int jj = 0; jj < 16; ++jj) t[jj] -= x * rrow[jj];
-        }
+        for (int j = 0; j < 16; ++j) x[j] = Tt[j * kSLd + tid] - Ta[j * kSLd + tid];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-          const TC x = t[j] * rinv[16 * c + j];
-          t[j] = x;
-          const TC* rrow = Rd + (16 * c + j) * kRdLd + 16 * c;
+          const TC* rrow = Rs + j * kSLd + 16 * to;
+          x[j] *= rrow[j];
 #pragma unroll
-          for (int jj = 0; jj < 16; ++jj)
-            if (jj > j) t[jj] -= x * rrow[jj];
+          for (int jj = j + 1; jj < 16; ++jj) x[jj] -= x[j] * rrow[jj];
         }
 #pragma unroll
-        for (int jj = 0; jj < 16; ++jj) Ts[(16 * c + jj) * kTsLd + tid] = t[jj];
+        for (int j = 0; j < 16; ++j) Tt[j * kSLd + tid] = x[j];
       }
-      const int64_t row = row0 + tid;
-      if (row < m) {
-        const int nv = (int)((k - c0) < kNB ? (k - c0) : kNB);
-        for (int j = 0; j < nv; ++j) X[row + (c0 + j) * ldx] = (TX)Ts[j * kTsLd + tid];
+      __syncthreads();
+      // X_t to memory.
+      if (row0 + ra < m) {
+        TX* xs = X + row0 + ra + (int64_t)(c0o + 16 * to + ca) * ldx;
+#pragma unroll
+        for (int q = 0; q < kLoads; ++q)
+          if (c0o + 16 * to + ca + 2 * q < k) xs[(int64_t)(2 * q) * ldx] = (TX)Tt[(ca + 2 * q) * kSLd + ra];
+      }
+      // acc[:, tiles > t] += X_t R[tile t, tiles > t]. A wave with such a
+      // tile runs all four (done tiles take a zero R operand), which keeps
+      // the accumulators in place.
+      if (4 * wc + 3 > to) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          TC af[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) af[a] = Tt[(4 * s + lq) * kSLd + 64 * wr + 16 * a + l16];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const TC rv = Rs[(4 * s + lq) * kSLd + 64 * wc + 16 * b + l16];
+            const TC bf = 4 * wc + b > to ? rv : (TC)0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[a][b] = mfma(af[a], bf, acc[a][b]);
+          }
+        }
       }
     }
-    __syncthreads();
   }
+}
+
+template <typename TB, typename TX, typename TC>
+hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX* X, int64_t ldx,
+                            const double* R, int64_t ldr, int64_t m, const int64_t* kdev,
+                            const cqrrpt_info_t* info, hipStream_t s) {
+  const size_t lds = kTrsmLdsBytes(sizeof(TC));
+  // R is addressed with 32-bit element offsets.
+  if (ldr <= 0 || (uint64_t)ldr * 8192u > 0xffffffffull) return hipErrorInvalidValue;
+  const void* fn = (const void*)trsm_kernel<TB, TX, TC>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int64_t grid = (m + kRT - 1) / kRT;
+  hipLaunchKernelGGL((trsm_kernel<TB, TX, TC>), dim3((unsigned)grid), dim3(kTThreads), lds, s, B,
+                     ldb, gather, X, ldx, R, ldr, m, kdev, info);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -372,20 +415,6 @@ syrk_reduce_kernel(const double* __restrict__ P, int nsplit, int kmax, const int
     for (int q = 0; q < nsplit; ++q) s += P[q * stride + e];
     G[i + j * ldg] = s;
   }
-}
-
-template <typename TB, typename TX, typename TC>
-hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX* X, int64_t ldx,
-                            const double* R, int64_t ldr, int64_t m, const int64_t* kdev,
-                            const cqrrpt_info_t* info, hipStream_t s) {
-  const size_t lds = ((size_t)kStage + kRdSz + kNB) * sizeof(TC);
-  const void* fn = (const void*)trsm_kernel<TB, TX, TC>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  const int64_t grid = (m + kRT - 1) / kRT;
-  hipLaunchKernelGGL((trsm_kernel<TB, TX, TC>), dim3((unsigned)grid), dim3(kTThreads), lds, s, B,
-                     ldb, gather, X, ldx, R, ldr, m, kdev, info);
-  return hipGetLastError();
 }
 
 }  // namespace
