@@ -236,17 +236,28 @@ def main():
             "gflops_2mn2": pr["gflops"], "ms_per_step": pr["ms"], "p50_ms": pr["p50"],
             "p99_ms": pr["p99"], "rank": pr["rank"], "orth": pr["orth"], "recon": pr["recon"]}
         log(f"planted-rank run: {extra['planted_rank_tol1e-9']}")
+        # Mixed precision is measured on its own workload (1048576 x 512,
+        # cond 1e10, full rank) next to FP64 on the same matrix.
         try:
-            mx = run_mode(P, torch, A, w, P.CQRRPT_MIXED, tol, args.seed, steps2, 1)
-            extra["mixed"] = {
-                "gflops_2mn2": mx["gflops"], "ms_per_step": mx["ms"], "p50_ms": mx["p50"],
-                "p99_ms": mx["p99"], "rank": mx["rank"], "orth": mx["orth"],
-                "recon": mx["recon"], "cholqr2_passes": mx["passes"],
-                "speedup_vs_fp64": main_res["ms"] / mx["ms"],
-                "stages_ms": mx["stages"]}
-            log(f"mixed run: {extra['mixed']}")
+            del pr
+            A3, w3 = W.make_workload_gpu("mixed_1048576x512_cond1e10", seed=args.seed)
+            torch.cuda.synchronize()
+            runs = {}
+            for name, mode in (("fp64", P.CQRRPT_FP64), ("mixed", P.CQRRPT_MIXED)):
+                r = run_mode(P, torch, A3, w3, mode, w3["tol"], args.seed, steps2, 1)
+                runs[name] = {
+                    "gflops_2mn2": r["gflops"], "ms_per_step": r["ms"], "p50_ms": r["p50"],
+                    "p99_ms": r["p99"], "rank": r["rank"], "orth": r["orth"],
+                    "recon": r["recon"], "cholqr2_passes": r["passes"],
+                    "stages_ms": r["stages"]}
+                del r
+            runs["mixed"]["speedup_vs_fp64"] = (runs["fp64"]["ms_per_step"] /
+                                                runs["mixed"]["ms_per_step"])
+            extra["mixed_vs_fp64_1048576x512_cond1e10"] = runs
+            log(f"mixed vs fp64 (1048576x512): {runs}")
+            del A3
         except P.CqrrptError as exc:
-            extra["mixed"] = {"error": str(exc)}
+            extra["mixed_vs_fp64_1048576x512_cond1e10"] = {"error": str(exc)}
 
     if args.copy_calib:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)

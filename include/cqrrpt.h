@@ -50,8 +50,13 @@ extern "C" {
  *   CQRRPT_MIXED: the preconditioning solve M_pre = A[:,J] R_sk^{-1} runs on
  *                 FP32 matrix cores and stores M_pre in FP32; the Gram, the
  *                 Q solve, the sketch QRCP, Cholesky and R = R_pre R_sk stay
- *                 FP64; one extra CholeskyQR pass (Sec. 1.2, "CholeskyQR2")
- *                 runs when the estimated orthogonality loss exceeds 1e-13. */
+ *                 FP64; one extra CholeskyQR pass (Sec. 1.2, "CholeskyQR2":
+ *                 G2 = Q^T Q, R2 = chol(G2), Q <- Q R2^{-1}, R <- R2 R) runs
+ *                 when max |Q^T Q - I| exceeds 1e-13 and G2 has a full
+ *                 Cholesky factor; the decision is taken on the device.
+ *                 The second-stage rank bound on the diagonal of R_pre is
+ *                 1e6 instead of 10 in this mode (the FP32 solve leaves
+ *                 cond(M_pre) near u_fp32 cond(A); the re-pass handles it). */
 typedef enum { CQRRPT_FP64 = 0, CQRRPT_MIXED = 1 } cqrrpt_mode_t;
 
 /* Per-call diagnostics, written to DEVICE memory by cqrrpt_factor_ex and
@@ -166,12 +171,13 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n,
  * Stage timing (diagnostics)
  * ------------------------------------------------------------------------
  * cqrrpt_stage_timing(slots): with slots > 0, every later cqrrpt_factor_ex
- * call records HIP events on its own stream at the boundaries of its eight
+ * call records HIP events on its own stream at the boundaries of its nine
  * stages (sketch, qrcp, rank_stage1, precondition, gram, cholesky, q_solve,
- * r_product), using event set (call index mod slots); slots = 0 turns timing
- * off and frees the events. Process-wide setting, guarded by a mutex.
+ * r_product, cholqr2 -- the last is empty in FP64 mode), using event set
+ * (call index mod slots); slots = 0 turns timing off and frees the events.
+ * Process-wide setting, guarded by a mutex.
  * cqrrpt_stage_times(slot, ms): waits for that slot's last event and writes
- * the eight stage durations in milliseconds to the HOST array ms[8].
+ * the nine stage durations in milliseconds to the HOST array ms[9].
  * Errors: -1 bad slot count / slot, -2 NULL ms, CQRRPT_EHIP. */
 int cqrrpt_stage_timing(int slots);
 int cqrrpt_stage_times(int slot, double* ms);

@@ -61,7 +61,7 @@ _SIGS = {
 }
 
 STAGES = ("sketch", "qrcp", "rank_stage1", "precondition", "gram", "cholesky", "q_solve",
-          "r_product")
+          "r_product", "cholqr2")
 
 
 def lib():

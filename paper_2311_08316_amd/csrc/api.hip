@@ -89,9 +89,21 @@ int check_common(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, 
 int to_status(hipError_t e) { return e == hipSuccess ? CQRRPT_OK : CQRRPT_EHIP; }
 
 // Optional per-stage timing: a ring of event sets, one set per call.
-constexpr int kStages = 8;
-const char* const kStageNames[kStages] = {"sketch", "qrcp", "rank_stage1", "precondition",
-                                          "gram", "cholesky", "q_solve", "r_product"};
+constexpr int kStages = 9;
+const char* const kStageNames[kStages] = {"sketch",   "qrcp",    "rank_stage1",
+                                          "precondition", "gram", "cholesky",
+                                          "q_solve",  "r_product", "cholqr2"};
+
+// Mixed mode re-runs CholeskyQR on Q when max |Q^T Q - I| exceeds this.
+constexpr double kCholQR2Threshold = 1e-13;
+// Second-stage bound on max|diag R_pre| / min|diag R_pre| (Sec. 3.3): the
+// paper's sqrt(100) for a single FP64 CholeskyQR pass. With an FP32
+// preconditioning solve, cond(M_pre) is about u_fp32 cond(A) even when the
+// sketch resolves A, and the CholeskyQR2 re-pass restores orthogonality
+// whenever the first pass leaves u_fp64 cond(M_pre)^2 well below one, so
+// mixed mode accepts up to 1e6.
+constexpr double kStage2CondFp64 = 10.0;
+constexpr double kStage2CondMixed = 1e6;
 struct StageTimer {
   std::mutex mu;
   int slots = 0;
@@ -321,7 +333,8 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
   }
   mk.mark(5);
   // S7-S8: R_pre = chol(G) in place, second-stage rank k.
-  CQ_TRY(cqh::launch_cholesky(G, n, ko_dev, ni, k_dev, base + L.off_chol, info, s));
+  CQ_TRY(cqh::launch_cholesky(G, n, ko_dev, ni, k_dev, base + L.off_chol, info, s,
+                              mode == CQRRPT_MIXED ? kStage2CondMixed : kStage2CondFp64));
   mk.mark(6);
   // S9: Q = M_pre[:, :k] R_pre^{-1}.
   if (mode == CQRRPT_FP64) {
@@ -335,6 +348,23 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
   CQ_TRY(cqh::launch_trmm_r(G, n, Rsk, n, R, ldr, ni, k_dev, s));
   CQ_TRY(cqh::launch_zero_cols(Q, ldq, m, ni, k_dev, s));
   mk.mark(8);
+  if (mode == CQRRPT_MIXED) {
+    // S11: adaptive CholeskyQR2 pass, decided on the device. G2 = Q^T Q
+    // (FP64) replaces R_pre in G, R's old value goes to the R_sk buffer
+    // (both are dead after S10).
+    int* pass = reinterpret_cast<int*>(kv + 3);
+    int* apply = pass + 1;
+    int64_t* k2_dev = kv + 2;
+    CQ_TRY(cqh::launch_syrk<double>(Q, ldq, m, k_dev, ni, Gp, G, n, info, s));
+    unsigned long long* mx = reinterpret_cast<unsigned long long*>(kv + 4);
+    CQ_TRY(cqh::launch_orth_check(G, n, k_dev, ni, kCholQR2Threshold, pass, mx, info, s));
+    CQ_TRY(cqh::launch_cholesky(G, n, k_dev, ni, k2_dev, base + L.off_chol, info, s, INFINITY,
+                                false, pass));
+    CQ_TRY(cqh::launch_cholqr2_commit(pass, k_dev, k2_dev, apply, R, ldr, Rsk, n, ni, info, s));
+    CQ_TRY(cqh::launch_trsm_f64(Q, ldq, nullptr, Q, ldq, G, n, m, k_dev, ni, info, s, apply));
+    CQ_TRY(cqh::launch_trmm_r(G, n, Rsk, n, R, ldr, ni, k_dev, s, apply));
+  }
+  mk.mark(9);
   return CQRRPT_OK;
 }
 

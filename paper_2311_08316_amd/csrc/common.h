@@ -334,10 +334,11 @@ hipError_t launch_rank_stage1(const double* R, int64_t ldr, int n, double tol, d
                               double* bmax, int64_t* kdev, cqrrpt_info_t* info, hipStream_t s);
 
 // X[:, :k] = B[:, gather[:k]] * R[:k, :k]^{-1}  (right, upper, non-unit).
+// enable (device int, optional): the launch does nothing when *enable == 0.
 hipError_t launch_trsm_f64(const double* B, int64_t ldb, const int64_t* gather, double* X,
                            int64_t ldx, const double* R, int64_t ldr, int64_t m,
                            const int64_t* kdev, int kmax, const cqrrpt_info_t* info,
-                           hipStream_t s);
+                           hipStream_t s, const int* enable = nullptr);
 hipError_t launch_trsm_mixed(const double* B, int64_t ldb, const int64_t* gather, float* X,
                              int64_t ldx, const double* R, int64_t ldr, int64_t m,
                              const int64_t* kdev, int kmax, const cqrrpt_info_t* info,
@@ -354,11 +355,25 @@ hipError_t launch_syrk(const T* X, int64_t ldx, int64_t m, const int64_t* kdev, 
                        hipStream_t s);
 
 size_t chol_ws_bytes(int kmax);
+// cond_max: second-stage bound on max|diag| / min|diag| (infinity: none);
+// record: write rank and failing column into info.
 hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int kmax,
-                           int64_t* k_dev, void* ws, cqrrpt_info_t* info, hipStream_t s);
+                           int64_t* k_dev, void* ws, cqrrpt_info_t* info, hipStream_t s,
+                           double cond_max = 10.0, bool record = true,
+                           const int* enable = nullptr);
 
 hipError_t launch_trmm_r(const double* Rpre, int64_t ldp, const double* Rsk, int64_t ldk,
-                         double* R, int64_t ldr, int n, const int64_t* kdev, hipStream_t s);
+                         double* R, int64_t ldr, int n, const int64_t* kdev, hipStream_t s,
+                         const int* enable = nullptr);
+// CholeskyQR2 re-pass helpers: *pass = (max |G2 - I| > threshold); then
+// *apply = *pass and chol(G2) kept all k columns, and R is copied to Rcopy
+// when the pass applies.
+hipError_t launch_orth_check(const double* G2, int64_t ldg, const int64_t* kdev, int n,
+                             double threshold, int* pass, unsigned long long* mx,
+                             cqrrpt_info_t* info, hipStream_t s);
+hipError_t launch_cholqr2_commit(const int* pass, const int64_t* k_dev, const int64_t* k2_dev,
+                                 int* apply, const double* R, int64_t ldr, double* Rcopy,
+                                 int64_t ldc, int n, cqrrpt_info_t* info, hipStream_t s);
 hipError_t launch_zero_cols(double* Q, int64_t ldq, int64_t m, int n, const int64_t* kdev,
                             hipStream_t s);
 

@@ -24,6 +24,7 @@
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
 constexpr int kB = 64;
 constexpr int kLd = kB + 1;
 
@@ -38,6 +39,8 @@ struct CholArgs {
   cqrrpt_info_t* info;
   cq::GridBarrier bar;
   double cond_max;
+  const int* enable;  // optional: nothing happens when *enable == 0
+  bool record;        // write rank and failing column into info
 };
 
 CQ_INLINE bool chol_sync(const cq::GridBarrier& b) {
@@ -82,6 +85,7 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
   const int wave = tid >> 6;
   const int ti = tid >> 4;
   const int tj = tid & 15;
+  if (a.enable && *a.enable == 0) return;
   int64_t ko = *a.ko;
   if (cq::ld_agent(&a.info->status) != 0) ko = 0;
   const int nblk = (int)((ko + kB - 1) / kB);
@@ -257,8 +261,10 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
       else break;
     }
     a.kout[0] = k;
-    a.info->rank = k;
-    a.info->chol_fail_col = fail >= 0 ? fail : -1;
+    if (a.record) {
+      a.info->rank = k;
+      a.info->chol_fail_col = fail >= 0 ? fail : -1;
+    }
   }
 }
 
@@ -272,9 +278,10 @@ __global__ void chol_reset_kernel(unsigned* w, int nw) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads)
 trmm_kernel(const double* __restrict__ P, int64_t ldp, const double* __restrict__ S, int64_t lds,
-            double* __restrict__ R, int64_t ldr, int n, const int64_t* kdev) {
+            double* __restrict__ R, int64_t ldr, int n, const int64_t* kdev, const int* enable) {
   __shared__ double PA[32 * kLd];
   __shared__ double SB[32 * kLd];
+  if (enable && *enable == 0) return;
   const int64_t k = *kdev;
   const int64_t i0 = (int64_t)blockIdx.x * kB;
   const int64_t j0 = (int64_t)blockIdx.y * kB;
@@ -324,6 +331,68 @@ trmm_kernel(const double* __restrict__ P, int64_t ldp, const double* __restrict_
     }
 }
 
+// ---------------------------------------------------------------------------
+// CholeskyQR2 re-pass (mixed mode): orthogonality estimate of Q from its Gram
+// G2 = Q^T Q, max |G2 - I| over the leading k x k upper triangle, and the
+// decision to run the pass (estimate above the threshold). The pass applies
+// only if G2 then has a full Cholesky factor.
+// ---------------------------------------------------------------------------
+__global__ void orth_reset_kernel(unsigned long long* mx) {
+  if (threadIdx.x == 0) mx[0] = 0ull;
+}
+
+// One workgroup per column j < k: max |G2[i, j] - delta_ij| over i <= j,
+// folded into *mx as the bit pattern of a non-negative double (ordered like
+// the value, NaN above every number), so the result does not depend on the
+// order of the atomics.
+__global__ void __launch_bounds__(kThreads)
+orth_column_kernel(const double* __restrict__ G2, int64_t ldg, const int64_t* kdev,
+                   unsigned long long* mx) {
+  __shared__ double s_max[kWaves];
+  const int64_t j = blockIdx.x;
+  if (j >= *kdev) return;
+  double v = 0.0;
+  for (int64_t i = threadIdx.x; i <= j; i += kThreads) {
+    const double e = fabs(G2[i + j * ldg] - (i == j ? 1.0 : 0.0));
+    v = (e > v || e != e) ? e : v;
+  }
+  v = cq::wave_max(v);
+  if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int w = 0; w < kWaves; ++w) m = (s_max[w] > m || s_max[w] != s_max[w]) ? s_max[w] : m;
+    atomicMax(mx, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+__global__ void orth_decide_kernel(const unsigned long long* mx, const int64_t* kdev,
+                                   double threshold, int* pass, cqrrpt_info_t* info) {
+  if (threadIdx.x == 0) {
+    const double m = __longlong_as_double((long long)mx[0]);
+    info->orth_est = m;
+    // NaN fails the comparison: no pass on a non-finite Gram.
+    pass[0] = (info->status == 0 && *kdev > 0 && m > threshold) ? 1 : 0;
+  }
+}
+
+__global__ void cholqr2_commit_kernel(const int* pass, const int64_t* k_dev,
+                                      const int64_t* k2_dev, int* apply, cqrrpt_info_t* info) {
+  if (threadIdx.x == 0) {
+    const int a = (pass[0] != 0 && k2_dev[0] == k_dev[0]) ? 1 : 0;
+    apply[0] = a;
+    info->cholqr2_passes = a;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+copy_square_kernel(const double* __restrict__ src, int64_t lds, double* __restrict__ dst,
+                   int64_t ldd, int n, const int* enable) {
+  if (enable && *enable == 0) return;
+  const int64_t j = blockIdx.x;
+  for (int i = threadIdx.x; i < n; i += kThreads) dst[i + j * ldd] = src[i + j * lds];
+}
+
 __global__ void __launch_bounds__(kThreads)
 zero_cols_kernel(double* Q, int64_t ldq, int64_t m, int n, const int64_t* kdev) {
   const int64_t c = blockIdx.y;
@@ -343,7 +412,8 @@ size_t chol_ws_bytes(int kmax) {
 }
 
 hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int kmax,
-                           int64_t* k_dev, void* ws, cqrrpt_info_t* info, hipStream_t s) {
+                           int64_t* k_dev, void* ws, cqrrpt_info_t* info, hipStream_t s,
+                           double cond_max, bool record, const int* enable) {
   (void)kmax;
   unsigned* w = static_cast<unsigned*>(ws);
   hipLaunchKernelGGL(chol_reset_kernel, dim3(1), dim3(64), 0, s, w, 8);
@@ -361,7 +431,9 @@ hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int km
   a.bar.count = w;
   a.bar.gen = w + 1;
   a.bar.abort = reinterpret_cast<int*>(w + 2);
-  a.cond_max = 10.0;
+  a.cond_max = cond_max;
+  a.record = record;
+  a.enable = enable;
   int per_cu = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)chol_kernel, kThreads, 0);
   if (e != hipSuccess) return e;
@@ -381,10 +453,37 @@ hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int km
 }
 
 hipError_t launch_trmm_r(const double* Rpre, int64_t ldp, const double* Rsk, int64_t ldk,
-                         double* R, int64_t ldr, int n, const int64_t* kdev, hipStream_t s) {
+                         double* R, int64_t ldr, int n, const int64_t* kdev, hipStream_t s,
+                         const int* enable) {
   const int nt = (n + kB - 1) / kB;
   hipLaunchKernelGGL(trmm_kernel, dim3(nt, nt), dim3(kThreads), 0, s, Rpre, ldp, Rsk, ldk, R, ldr,
-                     n, kdev);
+                     n, kdev, enable);
+  return hipGetLastError();
+}
+
+hipError_t launch_orth_check(const double* G2, int64_t ldg, const int64_t* kdev, int n,
+                             double threshold, int* pass, unsigned long long* mx,
+                             cqrrpt_info_t* info, hipStream_t s) {
+  hipLaunchKernelGGL(orth_reset_kernel, dim3(1), dim3(64), 0, s, mx);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(orth_column_kernel, dim3(n), dim3(kThreads), 0, s, G2, ldg, kdev, mx);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(orth_decide_kernel, dim3(1), dim3(64), 0, s, mx, kdev, threshold, pass,
+                     info);
+  return hipGetLastError();
+}
+
+hipError_t launch_cholqr2_commit(const int* pass, const int64_t* k_dev, const int64_t* k2_dev,
+                                 int* apply, const double* R, int64_t ldr, double* Rcopy,
+                                 int64_t ldc, int n, cqrrpt_info_t* info, hipStream_t s) {
+  hipLaunchKernelGGL(cholqr2_commit_kernel, dim3(1), dim3(64), 0, s, pass, k_dev, k2_dev, apply,
+                     info);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(copy_square_kernel, dim3(n), dim3(kThreads), 0, s, R, ldr, Rcopy, ldc, n,
+                     apply);
   return hipGetLastError();
 }
 

@@ -82,7 +82,7 @@ template <typename TB, typename TX, typename TC>
 __global__ void __launch_bounds__(kTThreads, 2)
 trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X, int64_t ldx,
             const double* __restrict__ R, int64_t ldr, int64_t m, const int64_t* kdev,
-            const cqrrpt_info_t* info) {
+            const cqrrpt_info_t* info, const int* enable) {
   typedef typename MfmaAcc<TC>::type acc_t;
   extern __shared__ unsigned char smem_raw[];
   TC* lds = reinterpret_cast<TC*>(smem_raw);
@@ -91,7 +91,7 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
   TC* Ta = lds + 2 * kTileSz;  // diagonal phase: accumulator tile, [16][kSLd]
   int* gcols = reinterpret_cast<int*>(lds + kTrsmLds);  // [kPW]
 
-  if (info->status != 0) return;
+  if (info->status != 0 || (enable && *enable == 0)) return;
   const int k = (int)*kdev;
   if (k <= 0) return;
   const int tid = threadIdx.x;
@@ -278,7 +278,7 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
 template <typename TB, typename TX, typename TC>
 hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX* X, int64_t ldx,
                             const double* R, int64_t ldr, int64_t m, const int64_t* kdev,
-                            const cqrrpt_info_t* info, hipStream_t s) {
+                            const cqrrpt_info_t* info, const int* enable, hipStream_t s) {
   const size_t lds = kTrsmLdsBytes(sizeof(TC));
   // R is addressed with 32-bit element offsets.
   if (ldr <= 0 || (uint64_t)ldr * 8192u > 0xffffffffull) return hipErrorInvalidValue;
@@ -287,7 +287,7 @@ hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX*
   if (e != hipSuccess) return e;
   const int64_t grid = (m + kRT - 1) / kRT;
   hipLaunchKernelGGL((trsm_kernel<TB, TX, TC>), dim3((unsigned)grid), dim3(kTThreads), lds, s, B,
-                     ldb, gather, X, ldx, R, ldr, m, kdev, info);
+                     ldb, gather, X, ldx, R, ldr, m, kdev, info, enable);
   return hipGetLastError();
 }
 
@@ -424,9 +424,10 @@ namespace cqh {
 hipError_t launch_trsm_f64(const double* B, int64_t ldb, const int64_t* gather, double* X,
                            int64_t ldx, const double* R, int64_t ldr, int64_t m,
                            const int64_t* kdev, int kmax, const cqrrpt_info_t* info,
-                           hipStream_t s) {
+                           hipStream_t s, const int* enable) {
   (void)kmax;
-  return launch_trsm_impl<double, double, double>(B, ldb, gather, X, ldx, R, ldr, m, kdev, info, s);
+  return launch_trsm_impl<double, double, double>(B, ldb, gather, X, ldx, R, ldr, m, kdev, info,
+                                                  enable, s);
 }
 
 hipError_t launch_trsm_mixed(const double* B, int64_t ldb, const int64_t* gather, float* X,
@@ -434,14 +435,16 @@ hipError_t launch_trsm_mixed(const double* B, int64_t ldb, const int64_t* gather
                              const int64_t* kdev, int kmax, const cqrrpt_info_t* info,
                              hipStream_t s) {
   (void)kmax;
-  return launch_trsm_impl<double, float, float>(B, ldb, gather, X, ldx, R, ldr, m, kdev, info, s);
+  return launch_trsm_impl<double, float, float>(B, ldb, gather, X, ldx, R, ldr, m, kdev, info,
+                                                nullptr, s);
 }
 
 hipError_t launch_trsm_f32in(const float* B, int64_t ldb, double* X, int64_t ldx,
                              const double* R, int64_t ldr, int64_t m, const int64_t* kdev,
                              int kmax, const cqrrpt_info_t* info, hipStream_t s) {
   (void)kmax;
-  return launch_trsm_impl<float, double, double>(B, ldb, nullptr, X, ldx, R, ldr, m, kdev, info, s);
+  return launch_trsm_impl<float, double, double>(B, ldb, nullptr, X, ldx, R, ldr, m, kdev, info,
+                                                 nullptr, s);
 }
 
 int syrk_splits(int64_t m, int kmax) {

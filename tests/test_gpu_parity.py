@@ -222,3 +222,38 @@ def test_factor_deterministic_and_sync_entry(P):
     Q2, R2, J2, rank = P.factor_sync(Ag, 100, 4, 3, 1e-14)
     assert rank == 80
     assert np.array_equal(Q1, to_np(Q2)) and np.array_equal(R1, to_np(R2))
+
+
+# ---------------------------------------------------------------------------
+# Mixed precision (FP32 preconditioning solve, FP64 elsewhere) with the
+# adaptive CholeskyQR2 re-pass. Pivots and the first-stage rank come from the
+# FP64 sketch QRCP in both modes, so they must equal the oracle's; Q must
+# reach the FP64 orthogonality bar after the pass; the reconstruction is
+# FP32-level by the stability analysis of the preconditioned method and is
+# stated against a loose bound, not matched.
+
+@pytest.mark.parametrize("cond,expect_pass", [(1e2, 0), (1e10, 1)])
+def test_mixed_cholqr2(P, cond, expect_pass):
+    m, n, d, nnz = 40000, 256, 320, 8
+    say(f"mixed m={m} n={n} cond={cond:.0e}")
+    A = W.spectrum_matrix(m, n, W.logspaced_spectrum(n, cond), seed=11)
+    orc = O.cqrrpt(A, d, nnz, seed=2, tol=1e-14)
+    Qg, Rg, Jg, info = P.factor(to_gpu(A), d, nnz, 2, 1e-14, mode=P.CQRRPT_MIXED)
+    Qn, Rn, Jn = to_np(Qg), to_np(Rg), to_np(Jg)
+    k = orc["rank"]
+    assert k == n and info.rank == k and info.rank_stage1 == orc["rank_stage1"]
+    assert np.array_equal(Jn, orc["J"])
+    assert info.cholqr2_passes == expect_pass, (info.cholqr2_passes, info.orth_est)
+    recon, orth = metrics(A, Qn, Rn, Jn, k)
+    dR = np.linalg.norm(Rn - orc["R"]) / np.linalg.norm(orc["R"])
+    say(f"  passes {info.cholqr2_passes} orth_est {info.orth_est:.2e} orth {orth:.2e} "
+        f"recon {recon:.2e} dR {dR:.2e}")
+    assert orth <= 1e-12
+    assert recon <= 1e-5 and dR <= 1e-4
+    assert np.array_equal(Rn, np.triu(Rn)) and np.all(np.diag(Rn) > 0)
+
+
+def test_fp64_mode_runs_no_repass(P):
+    A = W.spectrum_matrix(5000, 64, W.logspaced_spectrum(64, 1e8), seed=12)
+    _, _, _, info = P.factor(to_gpu(A), 80, 4, 3, 1e-14)
+    assert info.cholqr2_passes == 0 and info.orth_est == 0.0
