@@ -60,6 +60,8 @@ def parse():
                          "counter runs, where the QR-based generator is slow)")
     ap.add_argument("--no-quality", action="store_true",
                     help="skip the orthogonality/reconstruction evaluation")
+    ap.add_argument("--serving-requests", type=int, default=64,
+                    help="requests in the serving-stream run (0 skips it)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (three times), the "
                          "reference kernel for scaling HBM byte counters")
@@ -191,6 +193,57 @@ def cpu_baseline(A_host_sample, w, seed, tol):
             "seconds": t, "rank": int(out["rank"])}
 
 
+def serving_run(P, torch, W, count, mode, seed, slots=4, budget_gib=64.0):
+    """Serving stream (Poisson arrivals at the recipe's rate): each request's
+    matrix is generated on the device at its arrival time and submitted to a
+    server; latency is completion minus submission (host steady clock, the
+    server's own timestamps), throughput is requests and 2mn^2 flops over
+    the span from the first submission to the last completion."""
+    stream = W.serving_stream(count, seed=seed)
+    srv = P.Server(int(budget_gib * 2 ** 30), slots=slots, mode=mode)
+    live, done = [], []
+
+    def collect(block):
+        keep = []
+        for tk, r in live:
+            if block or srv.poll(tk):
+                if block:
+                    while not srv.poll(tk):
+                        time.sleep(1e-4)
+                ts, ta, td = srv.times(tk)
+                _, _, _, info = srv.result(tk)
+                done.append((ts, ta, td, r, int(info.rank)))
+            else:
+                keep.append((tk, r))
+        live[:] = keep
+
+    t0 = time.perf_counter()
+    for r in stream:
+        wait = r["t"] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        A = W.serving_matrix_gpu(r["m"], r["n"], r["seed"])
+        live.append((srv.submit(A, r["d"], r["nnz"], r["seed"], r["tol"]), r))
+        del A
+        collect(False)
+    srv.drain()
+    collect(True)
+    srv.close()
+    lat = np.array([td - ts for ts, ta, td, r, k in done])
+    queue = np.array([ta - ts for ts, ta, td, r, k in done])
+    span_s = (max(d[2] for d in done) - min(d[0] for d in done)) * 1e-3
+    flops = sum(2.0 * r["m"] * r["n"] ** 2 for *_, r, k in done)
+    full_rank = sum(1 for *_, r, k in done if k == r["n"])
+    return {"requests": len(done), "slots": slots,
+            "offered_rate_req_s": W.SERVING["rate_per_s"],
+            "p50_latency_ms": float(np.percentile(lat, 50)),
+            "p99_latency_ms": float(np.percentile(lat, 99)),
+            "mean_queue_ms": float(queue.mean()),
+            "throughput_req_s": len(done) / span_s,
+            "gflops_2mn2": flops / span_s / 1e9, "span_s": span_s,
+            "full_rank_results": full_rank}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -258,6 +311,13 @@ def main():
             del A3
         except P.CqrrptError as exc:
             extra["mixed_vs_fp64_1048576x512_cond1e10"] = {"error": str(exc)}
+
+    if not args.no_extra_runs and args.serving_requests > 0:
+        srv_res = {}
+        for name, mode in (("fp64", P.CQRRPT_FP64), ("mixed", P.CQRRPT_MIXED)):
+            srv_res[name] = serving_run(P, torch, W, args.serving_requests, mode, args.seed)
+            log(f"serving ({name}): {srv_res[name]}")
+        extra["serving_stream"] = srv_res
 
     if args.copy_calib:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)

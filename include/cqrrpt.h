@@ -183,6 +183,49 @@ int cqrrpt_stage_timing(int slots);
 int cqrrpt_stage_times(int slot, double* ms);
 const char* cqrrpt_stage_name(int i);
 
+/* ------------------------------------------------------------------------
+ * Serving (derived from the serving goal; not in the paper)
+ * ------------------------------------------------------------------------
+ * A server admits factorization requests of any shape as they arrive and
+ * runs them concurrently on the current device:
+ *   cqrrpt_server_create(budget, max_slots, mode): allocates one device
+ *     arena of `budget` bytes (all request workspaces are carved from it)
+ *     and max_slots streams; NULL on bad arguments or HIP failure.
+ *   cqrrpt_server_submit(...): queues one request with cqrrpt_factor_ex's
+ *     arguments (device pointers, caller-owned; A must already hold its
+ *     values: the server's streams do not wait on the caller's streams;
+ *     info is a DEVICE cqrrpt_info_t). Returns at once with *ticket.
+ *     Requests are admitted in arrival order when a slot is free and the
+ *     arena fits their workspace (cqrrpt_workspace_bytes). Errors:
+ *     CQRRPT_EBUDGET if the workspace exceeds the budget, -5 if the shape is
+ *     out of range, -2 NULL buffer, -17 NULL ticket, -1 NULL/closing server.
+ *   cqrrpt_server_poll(ticket, *done): *done = 1 once the request's work is
+ *     complete on the device (its Q, R, J, info may then be read); returns
+ *     the request's status (cqrrpt_factor_ex's code) once done, -2 unknown
+ *     ticket.
+ *   cqrrpt_server_ticket_times(ticket, ms[3]): host steady-clock times (ms)
+ *     of submission, admission and observed completion.
+ *   cqrrpt_server_release(ticket): forgets a finished ticket (-3 if not
+ *     finished).
+ *   cqrrpt_server_drain(): blocks until every submitted request is done;
+ *     returns the first non-zero request status, if any.
+ *   cqrrpt_server_destroy(): drains, then frees the arena and streams.
+ * A request's results are the same bits whether it runs alone or among
+ * others. Any thread may submit and poll. */
+typedef struct cqrrpt_server cqrrpt_server_t;
+cqrrpt_server_t* cqrrpt_server_create(size_t hbm_budget_bytes, int32_t max_slots,
+                                      cqrrpt_mode_t mode);
+int cqrrpt_server_submit(cqrrpt_server_t* server, const double* A, int64_t lda,
+                         int64_t m, int64_t n, int64_t d, int32_t nnz,
+                         uint64_t seed, double tol, double* Q, int64_t ldq,
+                         double* R, int64_t ldr, int64_t* J,
+                         cqrrpt_info_t* info, uint64_t* ticket);
+int cqrrpt_server_poll(cqrrpt_server_t* server, uint64_t ticket, int32_t* done);
+int cqrrpt_server_ticket_times(cqrrpt_server_t* server, uint64_t ticket, double* ms3);
+int cqrrpt_server_release(cqrrpt_server_t* server, uint64_t ticket);
+int cqrrpt_server_drain(cqrrpt_server_t* server);
+void cqrrpt_server_destroy(cqrrpt_server_t* server);
+
 /* Human-readable name of a return code. */
 const char* cqrrpt_status_string(int code);
 

@@ -58,6 +58,15 @@ _SIGS = {
     "cqrrpt_stage_timing": (ctypes.c_int, [ctypes.c_int]),
     "cqrrpt_stage_times": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     "cqrrpt_stage_name": (ctypes.c_char_p, [ctypes.c_int]),
+    "cqrrpt_server_create": (_vp, [_sz, _i32, ctypes.c_int]),
+    "cqrrpt_server_submit": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i64, _i64, _i32, _u64, _dbl,
+                                            _vp, _i64, _vp, _i64, _vp, _vp,
+                                            ctypes.POINTER(_u64)]),
+    "cqrrpt_server_poll": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(_i32)]),
+    "cqrrpt_server_ticket_times": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(_dbl)]),
+    "cqrrpt_server_release": (ctypes.c_int, [_vp, _u64]),
+    "cqrrpt_server_drain": (ctypes.c_int, [_vp]),
+    "cqrrpt_server_destroy": (None, [_vp]),
 }
 
 STAGES = ("sketch", "qrcp", "rank_stage1", "precondition", "gram", "cholesky", "q_solve",
@@ -236,3 +245,73 @@ def factor_sync(A, d, nnz, seed, tol):
                              R.data_ptr(), n, J.data_ptr(), ctypes.byref(rank))
     _check(rc, "cqrrpt_factor")
     return Q, R, J, rank.value
+
+
+class Server:
+    """Serving form (``cqrrpt_server_*``): requests are submitted as they
+    arrive, admitted by the library in arrival order as a slot and device
+    memory free up, and run concurrently. ``submit`` allocates the request's
+    outputs and returns a ticket; ``result`` returns them once done."""
+
+    def __init__(self, budget_bytes, slots=4, mode=CQRRPT_FP64, device=None):
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        self.mode = mode
+        self._h = lib().cqrrpt_server_create(int(budget_bytes), int(slots), int(mode))
+        if not self._h:
+            raise CqrrptError("cqrrpt_server_create failed")
+        self._out = {}
+
+    def submit(self, A, d, nnz, seed, tol):
+        """Queue one factorization of A (the caller's pending writes to A are
+        completed first). Returns the ticket."""
+        A = colmajor(A)
+        m, n = A.shape
+        Q = empty_colmajor(m, n, A.device)
+        R = empty_colmajor(n, n, A.device)
+        J = torch.empty(n, dtype=torch.int64, device=A.device)
+        info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
+        torch.cuda.current_stream(A.device).synchronize()
+        t = ctypes.c_uint64(0)
+        rc = lib().cqrrpt_server_submit(self._h, A.data_ptr(), _ld(A), m, n, d, nnz, seed, tol,
+                                        Q.data_ptr(), m, R.data_ptr(), n, J.data_ptr(),
+                                        info.data_ptr(), ctypes.byref(t))
+        _check(rc, "cqrrpt_server_submit")
+        self._out[t.value] = (A, Q, R, J, info)
+        return t.value
+
+    def poll(self, ticket):
+        done = ctypes.c_int32(0)
+        rc = lib().cqrrpt_server_poll(self._h, ticket, ctypes.byref(done))
+        if done.value:
+            _check(rc, "server request")
+        elif rc < 0:
+            _check(rc, "cqrrpt_server_poll")
+        return bool(done.value)
+
+    def times(self, ticket):
+        """(submit, admit, done) host times in ms."""
+        buf = (ctypes.c_double * 3)()
+        _check(lib().cqrrpt_server_ticket_times(self._h, ticket, buf), "ticket_times")
+        return tuple(buf)
+
+    def result(self, ticket):
+        """(Q, R, J, info) of a finished request; forgets the ticket."""
+        if not self.poll(ticket):
+            raise CqrrptError("request not finished")
+        _, Q, R, J, info = self._out.pop(ticket)
+        lib().cqrrpt_server_release(self._h, ticket)
+        return Q, R, J, CqrrptInfo.from_buffer_copy(bytes(info.cpu().numpy().tobytes()))
+
+    def drain(self):
+        _check(lib().cqrrpt_server_drain(self._h), "cqrrpt_server_drain")
+
+    def close(self):
+        if self._h:
+            lib().cqrrpt_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -169,3 +169,47 @@ def make_workload(name, seed=0, m=None):
         s = planted_spectrum(n, w["rank"], w["cond"])
     A = spectrum_matrix(mm, n, s, seed, w["noise"])
     return A, w
+
+
+# ---------------------------------------------------------------------------
+# Serving stream: requests arrive as a Poisson process; each is an iid
+# Gaussian matrix with log-uniform column scales, log-uniform height and a
+# width drawn from a fixed set; d = ceil(1.25 n), nnz = 4, tol = 1e-14.
+# ---------------------------------------------------------------------------
+SERVING = dict(rate_per_s=200.0, m_range=(20_000, 500_000), n_set=(64, 128, 256, 512, 1024),
+               col_scale_range=(1e-4, 1.0), nnz=4, tol=1e-14)
+
+
+def serving_stream(count, seed=0, rate_per_s=None, m_range=None, n_set=None):
+    """Arrival times (s, cumulative exponential gaps) and shapes of ``count``
+    requests: list of dicts with t, m, n, d, nnz, tol and the request's own
+    matrix/sketch seed (index + 1)."""
+    rate = SERVING["rate_per_s"] if rate_per_s is None else rate_per_s
+    lo, hi = SERVING["m_range"] if m_range is None else m_range
+    widths = SERVING["n_set"] if n_set is None else n_set
+    rng = _rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    ms = np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), size=count))).astype(np.int64)
+    ns = rng.choice(np.asarray(widths, dtype=np.int64), size=count)
+    out = []
+    for i in range(count):
+        n = int(ns[i])
+        m = max(int(ms[i]), math.ceil(1.25 * n))
+        out.append(dict(t=float(t[i]), m=m, n=n, d=math.ceil(1.25 * n), nnz=SERVING["nnz"],
+                        tol=SERVING["tol"], seed=i + 1))
+    return out
+
+
+def serving_matrix_gpu(m, n, seed, device="cuda"):
+    """Device-side serving request: iid N(0,1) times log-uniform column
+    scales from ``SERVING['col_scale_range']``, column-major FP64."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    lo, hi = SERVING["col_scale_range"]
+    A = torch.randn((n, m), dtype=torch.float64, device=device, generator=gen)
+    c = torch.exp(torch.empty(n, dtype=torch.float64, device=device).uniform_(
+        math.log(lo), math.log(hi), generator=gen))
+    A *= c[:, None]
+    return A.t()

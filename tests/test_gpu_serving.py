@@ -1,0 +1,92 @@
+"""GPU tests of the serving form (cqrrpt_server_* through the C ABI): many
+requests of uneven shape submitted at once to a server with few slots and a
+tight memory budget; every result must equal, bit for bit, the same request
+factorized alone, and a small request is checked against the oracle."""
+
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import cqrrpt_oracle as O
+from paper_2311_08316_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    import paper_2311_08316_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+SHAPES = [(20000, 64), (45000, 128), (30000, 256), (9000, 100), (60000, 512), (12000, 1024),
+          (25000, 64), (16000, 300)]
+
+
+def _solo(P, A, d, nnz, seed, tol, mode):
+    Q, R, J, info = P.factor(A, d, nnz, seed, tol, mode=mode)
+    torch.cuda.synchronize()
+    return Q.cpu().numpy(), R.cpu().numpy(), J.cpu().numpy(), info.rank
+
+
+@pytest.mark.parametrize("mode_name", ["fp64", "mixed"])
+def test_server_mix_equals_solo(P, mode_name):
+    mode = P.CQRRPT_FP64 if mode_name == "fp64" else P.CQRRPT_MIXED
+    reqs = []
+    for i, (m, n) in enumerate(SHAPES):
+        A = W.serving_matrix_gpu(m, n, seed=100 + i)
+        reqs.append((A, m, n, -(-5 * n // 4), 4, 7 + i, 1e-14))
+    biggest = max(P.workspace_bytes(m, n, d, nnz, mode) for _, m, n, d, nnz, _, _ in reqs)
+    # Room for about two of the largest workspaces: admission has to wait.
+    srv = P.Server(int(2.2 * biggest), slots=3, mode=mode)
+    say(f"server {mode_name}: {len(reqs)} requests, budget {2.2 * biggest / 2**20:.0f} MiB")
+    tickets = [srv.submit(A, d, nnz, seed, tol) for A, m, n, d, nnz, seed, tol in reqs]
+    srv.drain()
+    for t, (A, m, n, d, nnz, seed, tol) in zip(tickets, reqs):
+        ts, ta, td = srv.times(t)
+        assert ts <= ta <= td
+        Q, R, J, info = srv.result(t)
+        Qs, Rs, Js, ks = _solo(P, A, d, nnz, seed, tol, mode)
+        assert info.rank == ks
+        assert np.array_equal(J.cpu().numpy(), Js)
+        assert np.array_equal(R.cpu().numpy(), Rs)
+        assert np.array_equal(Q.cpu().numpy(), Qs)
+        say(f"  {m}x{n}: rank {info.rank}, same bits alone and in the mix")
+    srv.close()
+
+
+def test_server_request_matches_oracle(P):
+    m, n = 8000, 64
+    A = W.gaussian_matrix(m, n, seed=5, col_scale_range=(1e-4, 1.0))
+    Ag = torch.from_numpy(A).to("cuda").t().contiguous().t()
+    srv = P.Server(1 << 30, slots=2)
+    t = srv.submit(Ag, 80, 4, 3, 1e-14)
+    srv.drain()
+    Q, R, J, info = srv.result(t)
+    srv.close()
+    orc = O.cqrrpt(A, 80, 4, seed=3, tol=1e-14)
+    assert info.rank == orc["rank"] == n
+    assert np.array_equal(J.cpu().numpy(), orc["J"])
+    dR = np.linalg.norm(R.cpu().numpy() - orc["R"]) / np.linalg.norm(orc["R"])
+    assert dR <= 1e-12
+
+
+def test_server_budget_and_argument_errors(P):
+    srv = P.Server(1 << 20, slots=1)  # 1 MiB: too small for this request
+    A = W.serving_matrix_gpu(20000, 128, seed=1)
+    with pytest.raises(P.CqrrptError):
+        srv.submit(A, 160, 4, 1, 1e-14)
+    with pytest.raises(P.CqrrptError):
+        srv.submit(A, 100, 4, 1, 1e-14)  # d < n
+    srv.close()

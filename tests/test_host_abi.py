@@ -1,0 +1,110 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function that include/cqrrpt.h declares, and its host logic (argument
+checks, workspace sizing, status strings, server creation without a device)
+behaves as documented. No compute call is made here."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cqrrpt.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set()
+    for m in re.finditer(r"\b([A-Za-z_][A-Za-z0-9_ \*]*?)\b(cqrrpt_[a-z0-9_]+)\s*\(", text):
+        names.add(m.group(2))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2311_08316_amd import build_lib
+    if not os.path.exists(build_lib.LIB):
+        build_lib.build()
+    from paper_2311_08316_amd import _binding
+    return _binding.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("cqrrpt_saso_sample", "cqrrpt_sketch", "cqrrpt_qrcp", "cqrrpt_factor",
+                 "cqrrpt_factor_ex", "cqrrpt_workspace_bytes", "cqrrpt_server_create",
+                 "cqrrpt_server_submit", "cqrrpt_server_poll", "cqrrpt_server_drain",
+                 "cqrrpt_server_destroy"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings(L):
+    f = L.cqrrpt_status_string
+    f.restype = ctypes.c_char_p
+    for code in range(0, 7):
+        assert f(code)
+    assert f(-3)
+
+
+def test_workspace_bytes_argument_ranges(L):
+    ws = L.cqrrpt_workspace_bytes
+    assert ws(10000, 100, 125, 4, 0) > 0
+    assert ws(10000, 100, 125, 4, 1) > ws(10000, 100, 125, 4, 0)  # FP32 M_pre
+    assert ws(100, 200, 250, 4, 0) == 0      # n > m
+    assert ws(10000, 100, 99, 4, 0) == 0     # d < n
+    assert ws(10000, 100, 125, 0, 0) == 0    # nnz < 1
+    assert ws(10000, 100, 125, 33, 0) == 0   # nnz above the build limit
+    assert ws(100000, 9000, 9000, 4, 0) == 0  # n above the build limit
+
+
+def test_factor_ex_rejects_bad_arguments_before_any_device_work(L):
+    f = L.cqrrpt_factor_ex
+    i64, i32, u64, dbl, vp, sz = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
+                                  ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t)
+    f.argtypes = [vp, i64, i64, i64, i64, i32, u64, dbl, vp, i64, vp, i64, vp, ctypes.c_int,
+                  vp, sz, vp, vp]
+    p = vp(16)  # never dereferenced: every case fails an argument check first
+    base = dict(A=p, lda=100, m=100, n=10, d=12, nnz=4, seed=0, tol=1e-14, Q=p, ldq=100, R=p,
+                ldr=10, J=p, mode=0, ws=p, wsb=1 << 30, s=None, info=p)
+
+    def call(**kw):
+        a = dict(base, **kw)
+        return f(a["A"], a["lda"], a["m"], a["n"], a["d"], a["nnz"], a["seed"], a["tol"], a["Q"],
+                 a["ldq"], a["R"], a["ldr"], a["J"], a["mode"], a["ws"], a["wsb"], a["s"],
+                 a["info"])
+
+    assert call(A=None) == -1
+    assert call(lda=99) == -2
+    assert call(m=0) == -3
+    assert call(n=0) == -4
+    assert call(n=101) == -4
+    assert call(d=9) == -5
+    assert call(d=101) == -5
+    assert call(nnz=0) == -6
+    assert call(tol=float("nan")) == -8
+    assert call(tol=-1.0) == -8
+    assert call(Q=None) == -9
+    assert call(ldq=99) == -10
+    assert call(R=None) == -11
+    assert call(ldr=9) == -12
+    assert call(J=None) == -13
+    assert call(mode=7) == -14
+    assert call(ws=None) == -15
+    assert call(info=None) == -18
+    assert call(wsb=16) == 4  # CQRRPT_EWORKSPACE
+
+
+def test_server_rejects_bad_arguments(L):
+    create = L.cqrrpt_server_create
+    create.restype = ctypes.c_void_p
+    create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int]
+    assert not create(0, 4, 0)
+    assert not create(1 << 20, 0, 0)
+    assert not create(1 << 20, 4, 9)
