@@ -65,13 +65,12 @@ CQ_INLINE double r_at(const double* R, uint32_t ldr, int i, int j) {
   return R[(uint32_t)i + (uint32_t)j * ldr];
 }
 
+// R[i, j] of the upper triangle, from a raw value v loaded at the clamped
+// position; outside the leading k x k block the identity, so padded columns
+// solve to zero.
 template <typename TC>
-CQ_INLINE TC r_entry(const double* R, uint32_t ldr, int i, int j, int k) {
-  // R[i, j] of the upper triangle; outside the leading k x k block the
-  // identity, so padded columns solve to zero.
-  const int ic = i < k ? i : k - 1, jc = j < k ? j : k - 1;
-  const TC v = (TC)r_at(R, ldr, ic, jc);
-  if (i < k && j < k) return i <= j ? v : (TC)0;
+CQ_INLINE TC r_entry(double v, int i, int j, int k) {
+  if (i < k && j < k) return i <= j ? (TC)v : (TC)0;
   return i == j ? (TC)1 : (TC)0;
 }
 
@@ -127,18 +126,19 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
     }
     __syncthreads();
     // Tile t's B values (column-major 16 x kRT, coalesced) and R strip,
-    // one tile ahead of use.
-    TC breg[kLoads], sreg[kLoads];
+    // one tile ahead of use, kept in their storage types until stored (a
+    // conversion or mask at load time would wait for the load).
+    TB breg[kLoads];
+    double sreg[kLoads];
     auto load_tile = [&](int t) {
 #pragma unroll
-      for (int q = 0; q < kLoads; ++q) {
-        const int cl = 16 * t + ca + 2 * q;
-        const TC v = (TC)B[rowa + (int64_t)gcols[cl] * ldb];
-        breg[q] = c0o + cl < k ? v : (TC)0;
-      }
+      for (int q = 0; q < kLoads; ++q) breg[q] = B[rowa + (int64_t)gcols[16 * t + ca + 2 * q] * ldb];
+      const int ri = c0o + 16 * t + rb;
 #pragma unroll
-      for (int q = 0; q < kLoads; ++q)
-        sreg[q] = r_entry<TC>(R, ldr32, c0o + 16 * t + rb, c0o + cb + 16 * q, k);
+      for (int q = 0; q < kLoads; ++q) {
+        const int cj = c0o + cb + 16 * q;
+        sreg[q] = r_at(R, ldr32, ri < k ? ri : k - 1, cj < k ? cj : k - 1);
+      }
     };
     load_tile(0);
     acc_t acc[4][4];
@@ -148,27 +148,27 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
       for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
     if (c0o > 0) {
-      TC areg[kLoads], rreg[kLoads];
+      TX areg[kLoads];
+      double rreg[kLoads];
       auto load = [&](int kk) {
         const TX* xs = X + rowa + (int64_t)(kk + ca) * ldx;
 #pragma unroll
-        for (int q = 0; q < kLoads; ++q) areg[q] = (TC)xs[(int64_t)(2 * q) * ldx];
+        for (int q = 0; q < kLoads; ++q) areg[q] = xs[(int64_t)(2 * q) * ldx];
         // R rows kk.. < c0 <= column: strictly above the diagonal.
 #pragma unroll
         for (int q = 0; q < kLoads; ++q) {
           const int col = c0o + cb + 16 * q;
-          const int colc = col < k ? col : k - 1;
-          const TC v = (TC)r_at(R, ldr32, kk + rb, colc);
-          rreg[q] = col < k ? v : (TC)0;
+          rreg[q] = r_at(R, ldr32, kk + rb, col < k ? col : k - 1);
         }
       };
       auto store = [&](int buf) {
         TC* At = lds + buf * 2 * kTileSz;
         TC* Rt = At + kTileSz;
 #pragma unroll
-        for (int q = 0; q < kLoads; ++q) At[(ca + 2 * q) * kSLd + ra] = areg[q];
+        for (int q = 0; q < kLoads; ++q) At[(ca + 2 * q) * kSLd + ra] = (TC)areg[q];
 #pragma unroll
-        for (int q = 0; q < kLoads; ++q) Rt[rb * kSLd + cb + 16 * q] = rreg[q];
+        for (int q = 0; q < kLoads; ++q)
+          Rt[rb * kSLd + cb + 16 * q] = c0o + cb + 16 * q < k ? (TC)rreg[q] : (TC)0;
       };
       load(0);
       __syncthreads();  // the previous panel's diagonal phase is done with LDS
@@ -209,8 +209,10 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
 #pragma unroll
       for (int q = 0; q < kLoads; ++q) {
         const bool diag = cb + 16 * q == 16 * to + rb;
-        Rs[rb * kSLd + cb + 16 * q] = diag ? (TC)1 / sreg[q] : sreg[q];
-        Tt[(ca + 2 * q) * kSLd + ra] = breg[q];
+        const TC rv = r_entry<TC>(sreg[q], c0o + 16 * to + rb, c0o + cb + 16 * q, k);
+        Rs[rb * kSLd + cb + 16 * q] = diag ? (TC)1 / rv : rv;
+        const int cl = 16 * to + ca + 2 * q;
+        Tt[(ca + 2 * q) * kSLd + ra] = c0o + cl < k ? (TC)breg[q] : (TC)0;
       }
       if (wc == (to >> 2)) {
         // Column tile t & 3 of this wave's accumulators (selects, no
@@ -317,7 +319,6 @@ syrk_kernel(const T* __restrict__ X, int64_t ldx, int64_t m, const int64_t* kdev
   const int64_t i0 = (int64_t)I * kST;
   const int64_t j0 = (int64_t)J * kST;
   if (j0 >= k) return;
-  const bool diag = I == J;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -334,27 +335,31 @@ syrk_kernel(const T* __restrict__ X, int64_t ldx, int64_t m, const int64_t* kdev
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = d4_t{0, 0, 0, 0};
 
-  double vi[8], vj[8];
+  // Prefetched values stay in the input type until they are stored, so the
+  // loads of the next step are not waited for by a conversion. Rows past
+  // the split and columns past k read an in-bounds element and store zero.
+  T vi[8], vj[8];
+  const int rr = tid & (kRK - 1);
+  const int cl0 = tid >> 5;
+  const int64_t ci0 = i0 + cl0, cj0 = j0 + cl0;
+  bool rok = true;
   auto load = [&](int64_t rs) {
+    const int64_t row = rs + rr;
+    rok = row < r1;
+    const T* xr = X + (rok ? row : r1 - 1);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int e = tid + kThreads * q;
-      const int rr = e & (kRK - 1);
-      const int cl = e >> 5;
-      const int64_t row = rs + rr;
-      const bool ok = row < r1;
-      vi[q] = (ok && i0 + cl < k) ? (double)X[row + (i0 + cl) * ldx] : 0.0;
-      if (!diag) vj[q] = (ok && j0 + cl < k) ? (double)X[row + (j0 + cl) * ldx] : 0.0;
+      const int64_t ci = ci0 + 8 * q, cj = cj0 + 8 * q;
+      vi[q] = xr[(ci < k ? ci : k - 1) * ldx];
+      vj[q] = xr[(cj < k ? cj : k - 1) * ldx];
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int e = tid + kThreads * q;
-      const int rr = e & (kRK - 1);
-      const int cl = e >> 5;
-      XI[buf][cl * kXLd + rr] = vi[q];
-      if (!diag) XJ[buf][cl * kXLd + rr] = vj[q];
+      const int cl = cl0 + 8 * q;
+      XI[buf][cl * kXLd + rr] = (rok && ci0 + 8 * q < k) ? (double)vi[q] : 0.0;
+      XJ[buf][cl * kXLd + rr] = (rok && cj0 + 8 * q < k) ? (double)vj[q] : 0.0;
     }
   };
 
@@ -368,7 +373,7 @@ syrk_kernel(const T* __restrict__ X, int64_t ldx, int64_t m, const int64_t* kdev
       const bool more = rs + kRK < r1;
       if (more) load(rs + kRK);
       const double* xi = XI[buf];
-      const double* xj = diag ? XI[buf] : XJ[buf];
+      const double* xj = XJ[buf];
 #pragma unroll
       for (int s = 0; s < kRK / 4; ++s) {
         double af[2], bf[2];
