@@ -312,6 +312,22 @@ def main():
         except P.CqrrptError as exc:
             extra["mixed_vs_fp64_1048576x512_cond1e10"] = {"error": str(exc)}
 
+    if not args.no_extra_runs:
+        # One GPU's share (m/8 rows) of the 4,194,304 x 2,048 workload.
+        try:
+            A5, w5 = W.make_workload_gpu("fp64_4194304x2048_rank1536", seed=args.seed,
+                                         m=524_288)
+            torch.cuda.synchronize()
+            r = run_mode(P, torch, A5, w5, P.CQRRPT_FP64, w5["tol"], args.seed, 3, 1)
+            extra["share_524288x2048_fp64"] = {
+                "gflops_2mn2": r["gflops"], "ms_per_step": r["ms"], "p50_ms": r["p50"],
+                "rank": r["rank"], "orth": r["orth"], "recon": r["recon"],
+                "stages_ms": r["stages"]}
+            log(f"share 524288x2048: {extra['share_524288x2048_fp64']}")
+            del r, A5
+        except P.CqrrptError as exc:
+            extra["share_524288x2048_fp64"] = {"error": str(exc)}
+
     if not args.no_extra_runs and args.serving_requests > 0:
         srv_res = {}
         for name, mode in (("fp64", P.CQRRPT_FP64), ("mixed", P.CQRRPT_MIXED)):

@@ -1,0 +1,152 @@
+"""GPU parity at full workload sizes, in the launch configuration bench.py
+times (the same Factorization object and stream), where the oracle cannot
+run the whole path in seconds. Checked instead:
+
+  * the sketch against the oracle's sketch of the same input, within the
+    componentwise rounding bound of a p-term sum (p = largest row count of S);
+  * the pivots against the oracle's QRCP of that sketch (identical over the
+    planted rank, a permutation beyond);
+  * properties that hold at any size and pin the factors by their
+    definition: rank, ||Q^T Q - I||_2 and ||A[:,J] - Q R||_F / ||A||_F on the
+    device, R upper triangular with a positive diagonal, Q and R zero past the
+    rank, R^T R against A[:,J]^T A[:,J], and sampled rows of Q equal to the
+    corresponding rows of A[:,J] R^{-1} (solved on the host one row at a time).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+torch = pytest.importorskip("torch")
+
+from oracle import cqrrpt_oracle as O
+from paper_2311_08316_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    import paper_2311_08316_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def device_quality(A, Q, R, J, k):
+    Qk = Q[:, :k]
+    G = Qk.t() @ Qk
+    G -= torch.eye(k, dtype=torch.float64, device=G.device)
+    orth = float(torch.linalg.matrix_norm(G, ord=2)) if k else 0.0
+    AJ = A[:, J]
+    recon = float(torch.linalg.norm(AJ - Q @ R) / torch.linalg.norm(A))
+    gram = AJ[:, :k].t() @ AJ[:, :k]
+    Rk = R[:k, :k]
+    dgram = float(torch.linalg.norm(Rk.t() @ Rk - gram) / torch.linalg.norm(A) ** 2)
+    return orth, recon, dgram, AJ
+
+
+def check_factor(A, f, k, label, orth_max=1e-12, recon_max=1e-12, rows=48):
+    Q, R, J = f.Q, f.R, f.J
+    Jn = J.cpu().numpy()
+    n = R.shape[0]
+    assert sorted(Jn.tolist()) == list(range(n)), f"{label}: J is not a permutation"
+    orth, recon, dgram, AJ = device_quality(A, Q, R, J, k)
+    Rn = R.cpu().numpy()
+    assert np.array_equal(Rn, np.triu(Rn)) and np.all(np.diag(Rn)[:k] > 0), label
+    assert not Rn[k:, :].any(), label
+    assert not bool(Q[:, k:].abs().max() > 0) if k < n else True, label
+    assert orth <= orth_max, f"{label}: orth {orth:.2e}"
+    assert recon <= recon_max, f"{label}: recon {recon:.2e}"
+    assert dgram <= 1e-12, f"{label}: R^T R vs Gram {dgram:.2e}"
+    # Sampled rows of Q against A[r, J[:k]] R[:k,:k]^{-1}.
+    rng = np.random.Generator(np.random.PCG64(7))
+    m = A.shape[0]
+    idx = np.sort(rng.choice(m, size=min(rows, m), replace=False))
+    it = torch.as_tensor(idx, device=A.device)
+    a_rows = AJ[it, :k].cpu().numpy()
+    q_rows = Q[it, :k].cpu().numpy()
+    Rk = Rn[:k, :k]
+    ref = sla.solve_triangular(Rk, a_rows.T, trans="T", lower=False).T
+    kap = np.linalg.cond(Rk)
+    dq = np.linalg.norm(q_rows - ref) / np.linalg.norm(ref)
+    assert dq <= max(1e-12, 100 * 2.0 ** -53 * kap), f"{label}: sampled Q rows {dq:.2e}"
+    say(f"  {label}: rank {k} orth {orth:.2e} recon {recon:.2e} gram {dgram:.2e} "
+        f"rowsQ {dq:.2e}")
+
+
+def test_fullsize_131072x1024_planted(P):
+    """Benchmark workload: planted rank 512 + noise, d = 1280, nnz = 8."""
+    say("full size 131072 x 1024")
+    A, w = W.make_workload_gpu("fp64_131072x1024_rank512", seed=0)
+    m, n, d, nnz = w["m"], w["n"], w["d"], w["nnz"]
+    # Sketch and pivots against the oracle on the same input.
+    Ah = P.sketch(A, d, nnz, 0)
+    A_host = A.cpu().numpy()
+    rows, signs = O.saso_sample(m, d, nnz, 0)
+    Ah_o = O.sketch(A_host, rows, signs, d)
+    Ah_g = Ah.cpu().numpy()
+    p = int(np.bincount(rows.ravel(), minlength=d).max())
+    absS = O.sketch(np.abs(A_host), rows, np.ones_like(signs), d)
+    bound = (2 * p + 4) * 2.0 ** -53 * absS
+    assert np.all(np.abs(Ah_g - Ah_o) <= bound + 1e-300)
+    del A_host, absS, bound
+    J_o = O.qrcp(Ah_o)[0]
+    # At the planted rank the reconstruction cannot beat the noise that the
+    # truncation drops: ||noise||_F / ||A||_F with ||noise||_F about
+    # std sqrt(m n); allow 20 times that floor.
+    floor = w["noise"] * np.sqrt(m * n) / float(torch.linalg.norm(A))
+    for tol, k_expect, recon_max in ((1e-14, n, 1e-12), (1e-9, 512, 20 * floor)):
+        f = P.Factorization(m, n, d, nnz, P.CQRRPT_FP64)
+        f.run(A, 0, tol)
+        info = f.info()
+        assert info.status == 0 and info.rank == k_expect, (tol, info.rank)
+        Jg = f.J.cpu().numpy()
+        assert np.array_equal(Jg[:512], np.asarray(J_o)[:512]), f"pivots differ (tol {tol})"
+        check_factor(A, f, int(info.rank), f"131072x1024 tol {tol:g}", recon_max=recon_max)
+        del f
+
+
+def test_fullsize_1048576x512_mixed_and_fp64(P):
+    """Mixed against FP64 on the 1,048,576 x 512 cond-1e10 workload."""
+    say("full size 1048576 x 512")
+    A, w = W.make_workload_gpu("mixed_1048576x512_cond1e10", seed=0)
+    m, n, d, nnz, tol = w["m"], w["n"], w["d"], w["nnz"], w["tol"]
+    f64 = P.Factorization(m, n, d, nnz, P.CQRRPT_FP64)
+    f64.run(A, 0, tol)
+    i64 = f64.info()
+    assert i64.rank == n
+    check_factor(A, f64, n, "1048576x512 fp64", rows=32)
+    J64, R64 = f64.J.cpu().numpy(), f64.R.cpu().numpy()
+    del f64
+    fmx = P.Factorization(m, n, d, nnz, P.CQRRPT_MIXED)
+    fmx.run(A, 0, tol)
+    imx = fmx.info()
+    assert imx.rank == n and imx.cholqr2_passes == 1
+    assert np.array_equal(fmx.J.cpu().numpy(), J64)  # same FP64 sketch and QRCP
+    orth, recon, _, _ = device_quality(A, fmx.Q, fmx.R, fmx.J, n)
+    dR = np.linalg.norm(fmx.R.cpu().numpy() - R64) / np.linalg.norm(R64)
+    say(f"  mixed: orth {orth:.2e} recon {recon:.2e} dR vs fp64 {dR:.2e}")
+    assert orth <= 1e-12 and recon <= 1e-5 and dR <= 1e-4
+
+
+def test_fullsize_share_524288x2048(P):
+    """One GPU's share (m/8 rows) of the 4,194,304 x 2,048 planted-rank
+    workload: d = 2560 exercises the widest register QRCP variant."""
+    say("share 524288 x 2048")
+    A, w = W.make_workload_gpu("fp64_4194304x2048_rank1536", seed=0, m=524_288)
+    m, n, d, nnz, tol = w["m"], w["n"], w["d"], w["nnz"], w["tol"]
+    f = P.Factorization(m, n, d, nnz, P.CQRRPT_FP64)
+    f.run(A, 0, tol)
+    info = f.info()
+    say(f"  rank {info.rank} (stage 1 {info.rank_stage1})")
+    assert info.status == 0 and info.rank == n
+    check_factor(A, f, n, "524288x2048", rows=24)
