@@ -7,13 +7,14 @@
 //   * zero fill of Q's columns past the rank.
 //
 // The Cholesky factorization is one cooperative launch, right-looking over
-// 64-column blocks, two phases per block separated by grid barriers:
-//   1. one wave factors the diagonal block D (a column per lane, in
-//      registers) and forms D^{-1} (a column per lane, back substitution);
-//   2. every workgroup takes trailing tiles (p, q), p <= q: it forms the
-//      block-row tiles Y_p = D^{-T} G[block, p] and Y_q as small products
-//      with D^{-1}, writes Y_p as R_pre[block, p] when p == q, and applies
-//      G[p, q] -= Y_p^T Y_q.
+// 64-column blocks, three phases per block separated by grid barriers:
+//   1. one wave factors the diagonal block D = R_D^T R_D (a column per lane,
+//      in registers, rows broadcast with v_readlane) and forms R_D^{-1} the
+//      same way (back substitution, a column per lane);
+//   2a. the block row R[block, p] = R_D^{-T} G[block, p], one task per tile
+//      column, written over G's block row;
+//   2b. every workgroup takes trailing tiles (p, q), p <= q, and applies
+//      G[p, q] -= R[block, p]^T R[block, q].
 // G is overwritten by R_pre in place (upper triangle). Cross-workgroup data
 // goes through global memory ordered by agent-scope release/acquire fences
 // at the barriers.
@@ -35,7 +36,6 @@ struct CholArgs {
   int64_t* kout;
   int* flags;    // flags[0]: failing column (-1 = none) of the current block
   double* dinv;  // kB x kB inverse of the current diagonal block
-  double* panel; // kB x ldg: block row of R_pre produced by the last phase 2
   cqrrpt_info_t* info;
   cq::GridBarrier bar;
   double cond_max;
@@ -93,20 +93,19 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
   double* Gm = a.G;
   int fail = -1;
 
+  auto load_tile = [&](double* dst, int64_t r0, int64_t cc0) {
+    for (int e = tid; e < kB * kB; e += kThreads) {
+      const int l = e & (kB - 1);
+      const int c = e >> 6;
+      dst[l * kLd + c] = (r0 + l < ko && cc0 + c < ko) ? Gm[(r0 + l) + (cc0 + c) * ldg] : 0.0;
+    }
+  };
+
   for (int jb = 0; jb < nblk; ++jb) {
     const int64_t c0 = (int64_t)jb * kB;
-    // The previous block row of R_pre (columns past its diagonal block) was
-    // staged by phase 2; nobody reads those rows of G any more, so copy it in.
-    if (jb > 0) {
-      const int64_t pr = c0 - kB;
-      const int64_t ncopy = (ko - c0) * kB;
-      for (int64_t e = (int64_t)g * kThreads + tid; e < ncopy; e += (int64_t)G * kThreads) {
-        const int l = (int)(e % kB);
-        const int64_t col = c0 + e / kB;
-        Gm[(pr + l) + col * ldg] = a.panel[l + col * kB];
-      }
-    }
-    // Phase 1: factor the diagonal block and invert it.
+    // Phase 1: one wave factors the diagonal block (column `lane` in
+    // registers, rows broadcast with v_readlane) and inverts the factor the
+    // same way; the factor goes into G, its inverse to a.dinv.
     if (g == 0) {
       for (int e = tid; e < kB * kB; e += kThreads) {
         const int i = e & (kB - 1);
@@ -121,45 +120,51 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
       if (tid == 0) s_fail = -1;
       __syncthreads();
       if (wave == 0) {
-        // Lane c holds column c of D; row j values are broadcast with
-        // v_readlane (lane index known at compile time).
+        // Up-looking factorization, lane c = column c: row j of R_D is
+        //   R[j][c] = (D[j][c] - sum_{l<j} R[l][j] R[l][c]) / R[j][j],
+        // the pivot being the same expression at c = j. R[l][c] stays in
+        // this lane's registers; R[l][j] is read from LDS, where every lane
+        // writes its entry of row l once it is final (one wave: its LDS
+        // accesses are performed in program order).
         double cl[kB];
 #pragma unroll
         for (int i = 0; i < kB; ++i) cl[i] = D[i * kLd + lane];
         int fl = -1;
 #pragma unroll
         for (int j = 0; j < kB; ++j) {
-          if (fl < 0) {
-            const double piv = cq::readlane_d(cl[j], j);
-            if (!(piv > 0.0) || !isfinite(piv)) {
-              fl = j;
-            } else {
-              const double rj = sqrt(piv);
-              cl[j] = lane == j ? rj : (lane > j ? cl[j] / rj : cl[j]);
+          double s0 = cl[j], s1 = 0.0;
 #pragma unroll
-              for (int c1 = j + 1; c1 < kB; ++c1) {
-                const double sv = cq::readlane_d(cl[j], c1);
-                cl[c1] -= lane >= c1 ? sv * cl[j] : 0.0;
-              }
-            }
+          for (int l = 0; l < j; ++l) {
+            if (l & 1) s1 -= D[l * kLd + j] * cl[l];
+            else s0 -= D[l * kLd + j] * cl[l];
           }
+          const double sj = s0 + s1;
+          const double piv = cq::readlane_d(sj, j);
+          if (fl < 0 && (!(piv > 0.0) || !isfinite(piv))) fl = j;
+          const double rj = sqrt(piv);
+          const double rv = lane == j ? rj : (lane > j ? sj / rj : 0.0);
+          cl[j] = fl < 0 ? rv : cl[j];
+          D[j * kLd + lane] = cl[j];
         }
-#pragma unroll
-        for (int i = 0; i < kB; ++i) D[i * kLd + lane] = cl[i];
         if (lane == 0 && fl >= 0) s_fail = (int)(c0 + fl);
         if (fl < 0) {
-          // Column `lane` of D^{-1} by back substitution (zero below the
-          // diagonal follows from the zero start values).
+          // Row `lane` of W = R_D^{-1}: W[i][i] = 1 / R[i][i] and, for
+          // j > i, W[i][j] = -(sum_{i<=l<j} W[i][l] R[l][j]) / R[j][j], with
+          // R[l][j] from LDS and W[i][l] = 0 for l < i.
           double w[kB];
 #pragma unroll
-          for (int i = kB - 1; i >= 0; --i) {
-            double acc = lane == i ? 1.0 : 0.0;
+          for (int j = 0; j < kB; ++j) {
+            double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-            for (int l = i + 1; l < kB; ++l) acc -= D[i * kLd + l] * w[l];
-            w[i] = acc / D[i * kLd + i];
+            for (int l = 0; l < j; ++l) {
+              if (l & 1) s1 += w[l] * D[l * kLd + j];
+              else s0 += w[l] * D[l * kLd + j];
+            }
+            const double rjj = D[j * kLd + j];
+            w[j] = lane == j ? 1.0 / rjj : (lane < j ? -(s0 + s1) / rjj : 0.0);
           }
 #pragma unroll
-          for (int i = 0; i < kB; ++i) YA[i * kLd + lane] = w[i];
+          for (int j = 0; j < kB; ++j) YA[lane * kLd + j] = w[j];
         }
       }
       __syncthreads();
@@ -180,10 +185,39 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
     const int nrest = nblk - jb - 1;
     if (nrest == 0) break;
 
-    // Phase 2: trailing tiles (p, q), p <= q, with the block-row tiles formed
-    // on the fly as D^{-T} G[block, p].
+    // Phase 2a: block row of R_pre, R[block, p] = R_D^{-T} G[block, p], one
+    // task per tile column; each task overwrites only its own tile.
+    if (g < nrest) {
+      for (int e = tid; e < kB * kB; e += kThreads) {
+        const int i = e & (kB - 1);
+        const int j = e >> 6;
+        D[i * kLd + j] = a.dinv[i + j * kB];
+      }
+      for (int p = g; p < nrest; p += G) {
+        const int64_t cp = (int64_t)(jb + 1 + p) * kB;
+        __syncthreads();
+        load_tile(YA, c0, cp);
+        __syncthreads();
+        double acc[4][4];
+        // (R_D^{-1})^T is lower: row i of the product uses l <= i.
+        tile_atb<true>(D, YA, ti, tj, acc);
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) {
+            const int64_t i = c0 + 4 * ti + x;
+            const int64_t j = cp + 4 * tj + y;
+            if (i < ko && j < ko) Gm[i + j * ldg] = acc[x][y];
+          }
+      }
+    }
+    if (!chol_sync(a.bar)) {
+      if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
+      return;
+    }
+
+    // Phase 2b: trailing tiles (p, q), p <= q: G[p, q] -= R[block, p]^T R[block, q].
     const int ntr = nrest * (nrest + 1) / 2;
-    bool have_dinv = false;
     for (int t = g; t < ntr; t += G) {
       int q = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
       while ((q + 1) * (q + 2) / 2 <= t) ++q;
@@ -192,45 +226,11 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
       const int64_t ca = (int64_t)(jb + 1 + p) * kB;
       const int64_t cb = (int64_t)(jb + 1 + q) * kB;
       const bool same = p == q;
-      if (!have_dinv) {
-        for (int e = tid; e < kB * kB; e += kThreads) {
-          const int i = e & (kB - 1);
-          const int j = e >> 6;
-          D[i * kLd + j] = a.dinv[i + j * kB];
-        }
-        have_dinv = true;
-      }
-      for (int e = tid; e < kB * kB; e += kThreads) {
-        const int l = e & (kB - 1);
-        const int c = e >> 6;
-        const bool lv = c0 + l < ko;
-        YA[l * kLd + c] = (lv && ca + c < ko) ? Gm[(c0 + l) + (ca + c) * ldg] : 0.0;
-        if (!same) YB[l * kLd + c] = (lv && cb + c < ko) ? Gm[(c0 + l) + (cb + c) * ldg] : 0.0;
-      }
+      __syncthreads();
+      load_tile(YA, c0, ca);
+      if (!same) load_tile(YB, c0, cb);
       __syncthreads();
       double acc[4][4];
-      // Y_p = D^{-T} G[block, p]: (D^{-1})^T is lower, so row i uses l <= i.
-      tile_atb<true>(D, YA, ti, tj, acc);
-      double accb[4][4];
-      if (!same) tile_atb<true>(D, YB, ti, tj, accb);
-      __syncthreads();
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          YA[(4 * ti + x) * kLd + 4 * tj + y] = acc[x][y];
-          if (!same) YB[(4 * ti + x) * kLd + 4 * tj + y] = accb[x][y];
-        }
-      __syncthreads();
-      if (same) {
-        // Block row of R_pre, staged by the diagonal task of column p (other
-        // tasks of this phase still read G[block, p]).
-        for (int e = tid; e < kB * kB; e += kThreads) {
-          const int l = e & (kB - 1);
-          const int c = e >> 6;
-          if (ca + c < ko) a.panel[l + (ca + c) * kB] = YA[l * kLd + c];
-        }
-      }
       tile_atb<false>(YA, same ? YA : YB, ti, tj, acc);
 #pragma unroll
       for (int x = 0; x < 4; ++x)
@@ -240,7 +240,6 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
           const int64_t j = cb + 4 * tj + y;
           if (i <= j && j < ko) Gm[i + j * ldg] -= acc[x][y];
         }
-      __syncthreads();
     }
     if (!chol_sync(a.bar)) {
       if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
@@ -408,7 +407,8 @@ zero_cols_kernel(double* Q, int64_t ldq, int64_t m, int n, const int64_t* kdev) 
 namespace cqh {
 
 size_t chol_ws_bytes(int kmax) {
-  return 256 + (size_t)kB * kB * 8 + (size_t)kB * kmax * 8;
+  (void)kmax;
+  return 256 + (size_t)kB * kB * 8;  // barrier words and flags, R_D^{-1}
 }
 
 hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int kmax,
@@ -426,7 +426,6 @@ hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int km
   a.kout = k_dev;
   a.flags = reinterpret_cast<int*>(w + 4);
   a.dinv = reinterpret_cast<double*>(static_cast<char*>(ws) + 256);
-  a.panel = a.dinv + kB * kB;
   a.info = info;
   a.bar.count = w;
   a.bar.gen = w + 1;
