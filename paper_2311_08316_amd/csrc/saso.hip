@@ -214,12 +214,11 @@ saso_partial_kernel(const double* __restrict__ A, int64_t lda, int64_t m, int64_
 // ---------------------------------------------------------------------------
 // Register-accumulator variant of the partial sketch. Thread t owns targets
 // r = t + 256 i (i < T) for all NC columns of the block, held in registers.
-// Per sub-chunk it walks its T segments as one sequence (so lanes with short
-// segments do not wait at every target boundary), reading whole staged rows
-// of A (NC contiguous doubles) from LDS. Within a target the order of the
-// additions is ascending source row; across sub-chunks it is sub-chunk order.
+// Per sub-chunk it walks its T segments in lock step, reading whole staged
+// rows of A (NC contiguous doubles) from LDS. Within a target the order of
+// the additions is ascending source row, sub-chunk after sub-chunk.
 // ---------------------------------------------------------------------------
-template <int T, int NC>
+template <int T, int NC, int LL>
 __global__ void __launch_bounds__(kThreads)
 saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, int64_t n, int d,
                         int nnz, int ts, int subs_per_chunk, int nsub,
@@ -227,9 +226,13 @@ saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, in
                         double* __restrict__ part, int64_t part_ld, int64_t part_stride,
                         double scale, double* __restrict__ Ahat, int64_t ldah, int direct,
                         cqrrpt_info_t* info) {
+  // Staged rows of A are NC + 2 doubles apart: an odd multiple of 16 bytes,
+  // so random rows start on 16 different bank offsets (a 64-byte pitch
+  // gives 4) and 16-byte reads stay aligned.
+  constexpr int kRowPitch = NC + 2;
   extern __shared__ double smem[];
-  double* tile = smem;                                                   // ts * NC
-  int* sseg = reinterpret_cast<int*>(tile + (size_t)ts * NC);           // d + 1
+  double* tile = smem;                                                   // ts * (NC + 2)
+  int* sseg = reinterpret_cast<int*>(tile + (size_t)ts * kRowPitch);    // d + 1
   uint16_t* slst = reinterpret_cast<uint16_t*>(sseg + ((d + 1 + 3) & ~3));  // ts * nnz
 
   const int tid = threadIdx.x;
@@ -243,83 +246,98 @@ saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, in
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[i][c] = 0.0;
 
-  const int sb0 = q * subs_per_chunk;
-  const int sb1 = min(nsub, sb0 + subs_per_chunk);
-  for (int sb = sb0; sb < sb1; ++sb) {
+  // Sub-chunk sb's tile of A, segment table and entry list are loaded into
+  // registers one sub-chunk ahead (all loads of a sub-chunk issued back to
+  // back), then stored to LDS after the previous walk. Fixed per-thread load
+  // counts: the tile holds ts * NC <= 4096 values, the segment table
+  // d + 1 <= 256 T + 1 offsets, the list ts * nnz <= 512 LL entries.
+  constexpr int kTileLoads = 4096 / kThreads;
+  constexpr int kSegLoads = T + 1;
+  constexpr int kListLoads = LL;  // 32-bit words, two entries each
+  const int ts_shift = 31 - __clz(ts);       // ts is a power of two
+  double tv[kTileLoads];
+  int sv[kSegLoads];
+  uint32_t lv[kListLoads];
+  int rows_next = 0;
+  auto prefetch = [&](int sb) {
     const int64_t j0 = (int64_t)sb * ts;
     const int rows_here = (int)((m - j0) < ts ? (m - j0) : ts);
-    __syncthreads();
-    for (int e = tid; e < ts * NC; e += kThreads) {
-      const int c = e / ts;
-      const int jl = e - c * ts;
-      double v = 0.0;
-      if (jl < rows_here && c < ncols) v = A[(j0 + jl) + (c0 + c) * lda];
-      tile[jl * NC + c] = v;
+    rows_next = rows_here;
+#pragma unroll
+    for (int i = 0; i < kTileLoads; ++i) {
+      const int e = tid + kThreads * i;
+      const int c = e >> ts_shift;
+      const int jl = e & (ts - 1);
+      tv[i] = (e < ts * NC && jl < rows_here && c < ncols) ? A[(j0 + jl) + (c0 + c) * lda] : 0.0;
     }
     const int32_t* segb = seg + (int64_t)sb * (d + 1);
-    for (int r = tid; r <= d; r += kThreads) sseg[r] = segb[r];
-    const uint16_t* lb = list + (int64_t)sb * ts * nnz;
-    const int nent = rows_here * nnz;
-    for (int e = tid; e < nent; e += kThreads) slst[e] = lb[e];
-    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kSegLoads; ++i) {
+      const int r = tid + kThreads * i;
+      sv[i] = r <= d ? segb[r] : 0;
+    }
+    const uint32_t* lb = reinterpret_cast<const uint32_t*>(list + (int64_t)sb * ts * nnz);
+    const int nw = (rows_here * nnz + 1) >> 1;
+#pragma unroll
+    for (int i = 0; i < kListLoads; ++i) {
+      const int w = tid + kThreads * i;
+      lv[i] = w < nw ? lb[w] : 0u;
+    }
+  };
 
-    // This thread's segments, walked as one sequence.
-    int bounds[T + 1];
-    int total = 0;
+  const int sb0 = q * subs_per_chunk;
+  const int sb1 = min(nsub, sb0 + subs_per_chunk);
+  if (sb0 < sb1) prefetch(sb0);
+  for (int sb = sb0; sb < sb1; ++sb) {
+    const int rows_here = rows_next;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kTileLoads; ++i) {
+      const int e = tid + kThreads * i;
+      if (e < ts * NC) tile[(e & (ts - 1)) * kRowPitch + (e >> ts_shift)] = tv[i];
+    }
+#pragma unroll
+    for (int i = 0; i < kSegLoads; ++i) {
+      const int r = tid + kThreads * i;
+      if (r <= d) sseg[r] = sv[i];
+    }
+    {
+      uint32_t* sl32 = reinterpret_cast<uint32_t*>(slst);
+      const int nw = (rows_here * nnz + 1) >> 1;
+#pragma unroll
+      for (int i = 0; i < kListLoads; ++i) {
+        const int w = tid + kThreads * i;
+        if (w < nw) sl32[w] = lv[i];
+      }
+    }
+    __syncthreads();
+    if (sb + 1 < sb1) prefetch(sb + 1);
+
+    // Walk this thread's T target segments in lock step: at slot e every
+    // target with more than e entries adds its e-th entry (ascending source
+    // row), so the T targets' LDS reads overlap and no target switch needs a
+    // branch.
+    int base[T], len[T];
+    int lmax = 0;
 #pragma unroll
     for (int i = 0; i < T; ++i) {
       const int r = tid + kThreads * i;
-      bounds[i] = r < d ? sseg[r] : 0;
-      const int len = r < d ? sseg[r + 1] - sseg[r] : 0;
-      total += len;
+      base[i] = r < d ? sseg[r] : 0;
+      len[i] = r < d ? sseg[r + 1] - base[i] : 0;
+      lmax = len[i] > lmax ? len[i] : lmax;
     }
-    int cur = 0;                       // index of the current target
-    int e = bounds[0];
-    int left = (tid < d) ? sseg[tid + 1] - sseg[tid] : 0;  // entries left in it
-    double s[NC];
+    for (int e = 0; e < lmax; ++e) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) s[c] = 0.0;
-    for (int it = 0; it < total; ++it) {
-      while (left == 0) {
-        // Flush the finished target and move to the next one.
+      for (int i = 0; i < T; ++i) {
+        if (e < len[i]) {
+          const unsigned v = slst[base[i] + e];
+          const double* row = tile + (v >> 1) * kRowPitch;
+          const double sg = (v & 1u) ? -1.0 : 1.0;
 #pragma unroll
-        for (int i = 0; i < T; ++i)
-          if (i == cur) {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) acc[i][c] += s[c];
-          }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) s[c] = 0.0;
-        ++cur;
-        int nb = 0, nl = 0;
-#pragma unroll
-        for (int i = 0; i < T; ++i)
-          if (i == cur) {
-            const int r = tid + kThreads * i;
-            nb = r < d ? sseg[r] : 0;
-            nl = r < d ? sseg[r + 1] - sseg[r] : 0;
-          }
-        e = nb;
-        left = nl;
+          for (int c = 0; c < NC; ++c) acc[i][c] += sg * row[c];
+        }
       }
-      const unsigned v = slst[e];
-      const double* row = tile + (v >> 1) * NC;
-      if (v & 1u) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) s[c] -= row[c];
-      } else {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) s[c] += row[c];
-      }
-      ++e;
-      --left;
     }
-#pragma unroll
-    for (int i = 0; i < T; ++i)
-      if (i == cur) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) acc[i][c] += s[c];
-      }
   }
 #pragma unroll
   for (int i = 0; i < T; ++i) {
@@ -365,7 +383,7 @@ size_t index_lds_bytes(int d, int nnz, int ts) {
 }
 
 size_t partial_reg_lds_bytes(int d, int nnz, int ts, int nc) {
-  return (size_t)ts * nc * 8 + (size_t)((d + 1 + 3) & ~3) * 4 + (size_t)ts * nnz * 2;
+  return (size_t)ts * (nc + 2) * 8 + (size_t)((d + 1 + 3) & ~3) * 4 + (size_t)ts * nnz * 2;
 }
 
 // Targets per thread (rounded up to an instantiated value) for d rows.
@@ -377,9 +395,12 @@ int reg_targets(int d) {
   return 0;
 }
 
-const void* reg_partial_kernel(int T, int NC) {
-#define CQ_SK(TT, CC) \
-  if (T == TT && NC == CC) return (const void*)saso_partial_reg_kernel<TT, CC>;
+// LL: 32-bit list words per thread, ts * nnz / 512 rounded up to 8 or 16.
+const void* reg_partial_kernel(int T, int NC, int LL) {
+#define CQ_SK(TT, CC)                                                                   \
+  if (T == TT && NC == CC)                                                              \
+    return LL <= 8 ? (const void*)saso_partial_reg_kernel<TT, CC, 8>                    \
+                   : (const void*)saso_partial_reg_kernel<TT, CC, 16>;
   CQ_SK(1, 8) CQ_SK(2, 8) CQ_SK(3, 8) CQ_SK(4, 8) CQ_SK(5, 8) CQ_SK(6, 8) CQ_SK(8, 8)
   CQ_SK(10, 8) CQ_SK(12, 4) CQ_SK(16, 4)
 #undef CQ_SK
@@ -467,7 +488,7 @@ hipError_t launch_sketch(const SketchPlan& p, const double* A, int64_t lda, int6
   const int64_t ncb = (n + p.nc - 1) / p.nc;
   const int direct = p.nchunk == 1;
   if (p.reg_t > 0) {
-    const void* fn = reg_partial_kernel(p.reg_t, p.nc);
+    const void* fn = reg_partial_kernel(p.reg_t, p.nc, (p.ts * nnz + 511) / 512);
     if (!fn) return hipErrorInvalidValue;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
     if (e != hipSuccess) return e;
