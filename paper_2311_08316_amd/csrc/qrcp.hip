@@ -316,12 +316,21 @@ __global__ void __launch_bounds__(kThreads) qrcp_kernel(QrcpArgs a) {
 // ---------------------------------------------------------------------------
 constexpr int kRegMaxG = 256;
 
+// Partial sums p[0..C-1] added pairwise in a fixed order.
+template <int C>
+CQ_INLINE double chain_sum(const double (&p)[C]) {
+  if constexpr (C == 4) return (p[0] + p[1]) + (p[2] + p[3]);
+  else if constexpr (C == 2) return p[0] + p[1];
+  else return p[0];
+}
+
 template <int NT, int RPL, int CPW>
 __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
   constexpr int W = NT / cq::kWave;
   constexpr int KR = (cq::kWave * RPL + NT - 1) / NT;  // staged rows per thread
   constexpr int KS = kRegMaxG / cq::kWave;             // candidate slots per lane
   constexpr bool kHoldV = RPL * (CPW + 1) <= 40;       // v fits beside the columns
+  constexpr size_t kSlotWords = 2 * (size_t)cq::kWave * (RPL + 1);  // staged rows + padding
   extern __shared__ double smem[];
   __shared__ double s_rv[W];
   __shared__ int s_rc[W];
@@ -369,15 +378,18 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
     alive[k] = c < n;
     step[k] = -1;
     bdiag[k] = 0.0;
-    double acc = 0.0;
+    constexpr int kCh = RPL >= 8 ? 4 : RPL >= 2 ? 2 : 1;
+    double acc[kCh];
+#pragma unroll
+    for (int t = 0; t < kCh; ++t) acc[t] = 0.0;
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const int r = lane + cq::kWave * q;
       const double v = (alive[k] && r < d) ? a.X[r + (int64_t)c * a.ldx] : 0.0;
       X[k][q] = v;
-      acc += v * v;
+      acc[q % kCh] += v * v;
     }
-    nrm[k] = cq::wave_sum_dpp(acc);
+    nrm[k] = cq::wave_sum_dpp(chain_sum<kCh>(acc));
     nrm[k] = alive[k] ? sqrt(nrm[k]) : -1.0;
   }
 
@@ -398,35 +410,44 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
       s_rc[wave] = bc;
     }
     __syncthreads();
-    double wv = s_rv[0];
-    int wc = s_rc[0];
-    for (int w = 1; w < W; ++w)
-      if (cq::beats(s_rv[w], s_rc[w], wv, wc)) {
-        wv = s_rv[w];
-        wc = s_rc[w];
-      }
-    // Row lane + 64 q is at or below row0 exactly when q > q0.
-    const int q0 = (row0 - 1 - lane) >> 6;
-    uint64_t* dst = a.fstage + ((size_t)(stp & 1) * G + g) * 2 * (size_t)d +
-                    2 * (int64_t)(lane - row0);
-#pragma unroll
-    for (int k = 0; k < CPW; ++k) {
-      if (alive[k] && colid[k] == wc) {
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) {
-          if (q > q0 && lane + cq::kWave * q < d) {
-            cq::put_flagged(dst + 2 * cq::kWave * q, cq::lo_half(X[k][q]), flag);
-            cq::put_flagged(dst + 2 * cq::kWave * q + 1, cq::hi_half(X[k][q]), flag);
-          }
-        }
-      }
-    }
+    // Workgroup best: lanes 0..W-1 take the W wave bests and combine them
+    // with lane permutes (a total order, so the pairing does not matter).
+    double wv = lane < W ? s_rv[lane] : -2.0;
+    int wc = lane < W ? s_rc[lane] : INT_MAX;
+    cq::argmax_step<0xB1>(wv, wc);
+    if constexpr (W > 2) cq::argmax_step<0x4E>(wv, wc);
+    if constexpr (W > 4) cq::argmax_step<0x141>(wv, wc);
+    if constexpr (W > 8) cq::argmax_step<0x140>(wv, wc);
+    wv = cq::readlane_d(wv, 0);
+    wc = __builtin_amdgcn_readlane(wc, 0);
+    // The candidate goes out first: readers poll the staged rows' own flags,
+    // so the order of the two does not matter for correctness, and the
+    // candidate does not queue behind the rows.
     if (tid == 0) {
       uint64_t* cd = a.fcand + ((size_t)(stp & 1) * G + g) * 4;
       const double cv = wc == INT_MAX ? -1.0 : wv;
       cq::put_flagged(cd, cq::lo_half(cv), flag);
       cq::put_flagged(cd + 1, cq::hi_half(cv), flag);
       cq::put_flagged(cd + 2, (uint32_t)(wc == INT_MAX ? -1 : wc), flag);
+    }
+    // Rows row0..d-1 go to the slot at offsets 0..; a slot has 64 rows of
+    // padding in front and room for 64 RPL rows, so whole 64-row blocks can
+    // be written: block q holds a row at or below row0 exactly when q > qlo
+    // (the same for every lane), and its rows above row0 land in the padding.
+    const int qlo = (row0 - cq::kWave) >> 6;
+    uint64_t* dst = a.fstage + ((size_t)(stp & 1) * G + g) * kSlotWords +
+                    2 * (int64_t)(cq::kWave + lane - row0);
+#pragma unroll
+    for (int k = 0; k < CPW; ++k) {
+      if (alive[k] && colid[k] == wc) {
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+          if (q > qlo) {
+            cq::put_flagged(dst + 2 * cq::kWave * q, cq::lo_half(X[k][q]), flag);
+            cq::put_flagged(dst + 2 * cq::kWave * q + 1, cq::hi_half(X[k][q]), flag);
+          }
+        }
+      }
     }
   };
 
@@ -449,35 +470,49 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
   for (int i = 0; i < n; ++i) {
     const int par = i & 1;
     const uint32_t flag = (uint32_t)i + 1u;
-    // Wave 0: the G candidates of step i and their argmax.
+    // Wave 0: the G candidates of step i and their argmax. All of a lane's
+    // slots are polled together, so the wait is one round trip for any G.
     if (wave == 0) {
-      double bv = -2.0;
-      int bc = INT_MAX;
-      bool bad = false;
+      const uint64_t* cbase = a.fcand + (size_t)par * G * 4;
+      uint64_t cw[KS][3];
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const int slot = lane + cq::kWave * s;
-        if (slot < G) {
-          const uint64_t* cd = a.fcand + ((size_t)par * G + slot) * 4;
-          uint64_t w0 = cq::get_flagged(cd), w1 = cq::get_flagged(cd + 1),
-                   w2 = cq::get_flagged(cd + 2);
-          unsigned spins = 0;
-          while (cq::flag_of(w0) != flag || cq::flag_of(w1) != flag ||
-                 cq::flag_of(w2) != flag) {
-            if (timed_out(spins)) {
-              bad = true;
-              break;
-            }
-            w0 = cq::get_flagged(cd);
-            w1 = cq::get_flagged(cd + 1);
-            w2 = cq::get_flagged(cd + 2);
-          }
-          const double v = cq::join_halves(w0, w1);
-          const int c = (int)(uint32_t)w2;
-          if (!bad && cq::beats(v, c, bv, bc)) {
-            bv = v;
-            bc = c;
-          }
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+          cw[s][t] = slot < G ? cq::get_flagged(cbase + slot * 4 + t) : (uint64_t)flag << 32;
+      }
+      bool bad = false;
+      unsigned spins = 0;
+      while (true) {
+        bool ready = true;
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+          for (int t = 0; t < 3; ++t) ready = ready && cq::flag_of(cw[s][t]) == flag;
+        if (ready) break;
+        if (timed_out(spins)) {
+          bad = true;
+          break;
+        }
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const int slot = lane + cq::kWave * s;
+#pragma unroll
+          for (int t = 0; t < 3; ++t)
+            if (cq::flag_of(cw[s][t]) != flag) cw[s][t] = cq::get_flagged(cbase + slot * 4 + t);
+        }
+      }
+      double bv = -2.0;
+      int bc = INT_MAX;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int slot = lane + cq::kWave * s;
+        const double v = cq::join_halves(cw[s][0], cw[s][1]);
+        const int c = (int)(uint32_t)cw[s][2];
+        if (slot < G && !bad && cq::beats(v, c, bv, bc)) {
+          bv = v;
+          bc = c;
         }
       }
       cq::wave_argmax_dpp(bv, bc);
@@ -497,7 +532,7 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
     const int len = d - i;
     // The winner's rows i..d-1: row i (alpha) in every thread, then this
     // thread's share; v = x / (alpha - beta), v[0] = 1.
-    const uint64_t* src = a.fstage + ((size_t)par * G + owner) * 2 * (size_t)d;
+    const uint64_t* src = a.fstage + ((size_t)par * G + owner) * kSlotWords + 2 * cq::kWave;
     uint64_t al = cq::get_flagged(src), ah = cq::get_flagged(src + 1);
     uint64_t lo[KR], hi[KR];
 #pragma unroll
@@ -565,18 +600,27 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
     }
     // Apply I - tau v v^T to the alive columns, then recompute their norms
     // over rows i+1..d-1 (row lane + 64 q is below row i exactly when q > qi).
-    {
-      double w[CPW];
+    // A lane's share of each sum is kept in kCh interleaved partial sums
+    // (q mod kCh), added in a fixed order: shorter dependency chains. A wave
+    // whose columns are all pivoted has nothing to update and skips this.
+    bool any_alive = false;
 #pragma unroll
-      for (int k = 0; k < CPW; ++k) w[k] = 0.0;
+    for (int k = 0; k < CPW; ++k) any_alive = any_alive || alive[k];
+    if (any_alive) {
+      constexpr int kCh = RPL >= 8 ? 4 : RPL >= 2 ? 2 : 1;
+      double w[CPW], wp[CPW][kCh];
+#pragma unroll
+      for (int k = 0; k < CPW; ++k)
+#pragma unroll
+        for (int c = 0; c < kCh; ++c) wp[k][c] = 0.0;
 #pragma unroll
       for (int q = 0; q < RPL; ++q) {
         const double vq = vv[lane + cq::kWave * q];
 #pragma unroll
-        for (int k = 0; k < CPW; ++k) w[k] += vq * X[k][q];
+        for (int k = 0; k < CPW; ++k) wp[k][q % kCh] += vq * X[k][q];
       }
 #pragma unroll
-      for (int k = 0; k < CPW; ++k) w[k] = cq::wave_sum_dpp(w[k]);
+      for (int k = 0; k < CPW; ++k) w[k] = cq::wave_sum_dpp(chain_sum<kCh>(wp[k]));
 #pragma unroll
       for (int k = 0; k < CPW; ++k) w[k] = alive[k] ? tau * w[k] : 0.0;
       // Wide columns: read v from LDS again rather than holding it in VGPRs
@@ -584,20 +628,22 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
       // first pass's loads live).
       if (!kHoldV) asm volatile("" ::: "memory");
       const int qi = (i - lane) >> 6;
-      double nn[CPW];
+      double nn[CPW][kCh];
 #pragma unroll
-      for (int k = 0; k < CPW; ++k) nn[k] = 0.0;
+      for (int k = 0; k < CPW; ++k)
+#pragma unroll
+        for (int c = 0; c < kCh; ++c) nn[k][c] = 0.0;
 #pragma unroll
       for (int q = 0; q < RPL; ++q) {
         const double vq = vv[lane + cq::kWave * q];
 #pragma unroll
         for (int k = 0; k < CPW; ++k) {
           X[k][q] -= w[k] * vq;
-          nn[k] += q > qi ? X[k][q] * X[k][q] : 0.0;
+          nn[k][q % kCh] += q > qi ? X[k][q] * X[k][q] : 0.0;
         }
       }
 #pragma unroll
-      for (int k = 0; k < CPW; ++k) nrm[k] = cq::wave_sum_dpp(nn[k]);
+      for (int k = 0; k < CPW; ++k) nrm[k] = cq::wave_sum_dpp(chain_sum<kCh>(nn[k]));
 #pragma unroll
       for (int k = 0; k < CPW; ++k) nrm[k] = alive[k] ? sqrt(nrm[k]) : -1.0;
     }
@@ -710,13 +756,30 @@ size_t qrcp_lds_bytes(int d, int cols, bool lds) {
 
 namespace cqh {
 
-// Register variant: rows per lane RPL and columns per wave CPW chosen so a
-// lane's columns fit its VGPR share without spilling: 512-thread workgroups
-// (256 VGPRs per lane) up to RPL = 20, 256-thread workgroups above.
+// Register variant: rows per lane RPL, workgroup size and columns per wave
+// CPW. Shapes instantiated per RPL, in order of preference: one column per
+// wave in 256- then 512-thread workgroups, then more columns per wave (the
+// most that fit the VGPR share without spilling). The first shape whose grid
+// has at most kRegPreferG workgroups is taken (more workgroups make every
+// step's exchange wait longer; more columns per wave make its update and
+// publish longer), else the first that fits the device.
 static const int kRplSet[] = {1, 2, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40};
+constexpr int kRegPreferG = 128;
 
-static int threads_for(int rpl) { return rpl <= 20 ? 512 : 256; }
-static int cpw_for(int rpl) { return rpl == 20 ? 3 : rpl >= 32 ? 2 : 4; }
+struct RegShape {
+  int threads, cpw;
+};
+static constexpr int cpw_max(int rpl) { return rpl == 20 ? 3 : rpl >= 32 ? 2 : 4; }
+static constexpr int wide_threads(int rpl) { return rpl <= 20 ? 512 : 256; }
+
+static int reg_shapes(int rpl, RegShape* out) {
+  int k = 0;
+  out[k++] = {256, 1};
+  if (wide_threads(rpl) == 512) out[k++] = {512, 1};
+  out[k++] = {wide_threads(rpl), 2};
+  if (cpw_max(rpl) > 2) out[k++] = {wide_threads(rpl), cpw_max(rpl)};
+  return k;
+}
 
 QrcpPlan plan_qrcp(int d, int n) {
   const Device& dev = device_info();
@@ -728,14 +791,22 @@ QrcpPlan plan_qrcp(int d, int n) {
       break;
     }
   if (p.rpl > 0) {
-    p.cpw = cpw_for(p.rpl);
-    p.threads = threads_for(p.rpl);
-    const int per_block = (p.threads / 64) * p.cpw;
-    const int G = (n + per_block - 1) / per_block;
-    if (G <= dev.num_cu && G <= kRegMaxG) {
+    RegShape sh[4];
+    const int ns = reg_shapes(p.rpl, sh);
+    const int gmax = std::min(dev.num_cu, kRegMaxG);
+    int pick = -1;
+    for (int pass = 0; pass < 2 && pick < 0; ++pass)
+      for (int t = 0; t < ns && pick < 0; ++t) {
+        const int per_block = (sh[t].threads / 64) * sh[t].cpw;
+        const int G = (n + per_block - 1) / per_block;
+        if (G <= (pass == 0 ? std::min(gmax, kRegPreferG) : gmax)) pick = t;
+      }
+    if (pick >= 0) {
       p.reg = true;
-      p.nblocks = G;
-      p.cols_per_block = per_block;
+      p.threads = sh[pick].threads;
+      p.cpw = sh[pick].cpw;
+      p.cols_per_block = (p.threads / 64) * p.cpw;
+      p.nblocks = (n + p.cols_per_block - 1) / p.cols_per_block;
       p.lds_resident = false;
       p.lds_bytes = (size_t)64 * p.rpl * 8 + (((size_t)n + 7) & ~(size_t)7);
     }
@@ -752,8 +823,9 @@ QrcpPlan plan_qrcp(int d, int n) {
   }
   const int G = p.nblocks;
   if (p.reg) {
-    // flagged words: two per staged double, four per candidate
-    p.stage_bytes = align256((size_t)2 * G * 2 * d * 8);
+    // flagged words: two per staged double (64 (RPL + 1) rows per slot with
+    // the padding), four per candidate
+    p.stage_bytes = align256((size_t)2 * G * 2 * 64 * (p.rpl + 1) * 8);
     p.cand_bytes = align256((size_t)2 * G * 4 * 8);
   } else {
     p.stage_bytes = align256((size_t)2 * G * d * 8);
@@ -766,10 +838,22 @@ QrcpPlan plan_qrcp(int d, int n) {
   return p;
 }
 
-static const void* reg_kernel(int rpl) {
+template <int R>
+static const void* reg_kernel_r(int threads, int cpw) {
+  constexpr int TW = wide_threads(R);
+  constexpr int CM = cpw_max(R);
+  if (threads == 256 && cpw == 1) return (const void*)qrcp_reg_kernel<256, R, 1>;
+  if constexpr (TW == 512)
+    if (threads == 512 && cpw == 1) return (const void*)qrcp_reg_kernel<512, R, 1>;
+  if (threads == TW && cpw == 2) return (const void*)qrcp_reg_kernel<TW, R, 2>;
+  if constexpr (CM > 2)
+    if (threads == TW && cpw == CM) return (const void*)qrcp_reg_kernel<TW, R, CM>;
+  return nullptr;
+}
+
+static const void* reg_kernel(int rpl, int threads, int cpw) {
 #define CQ_REG(R) \
-  if (rpl == R)                                                                   \
-    return (const void*)qrcp_reg_kernel<(R <= 20 ? 512 : 256), R, (R == 20 ? 3 : R >= 32 ? 2 : 4)>;
+  if (rpl == R) return reg_kernel_r<R>(threads, cpw);
   CQ_REG(1) CQ_REG(2) CQ_REG(4) CQ_REG(6) CQ_REG(8) CQ_REG(10)
   CQ_REG(12) CQ_REG(16) CQ_REG(20) CQ_REG(24) CQ_REG(32) CQ_REG(40)
 #undef CQ_REG
@@ -823,7 +907,7 @@ hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, 
   const void* fn;
   int threads;
   if (p.reg) {
-    fn = reg_kernel(p.rpl);
+    fn = reg_kernel(p.rpl, p.threads, p.cpw);
     threads = p.threads;
     if (!fn) return hipErrorInvalidValue;
   } else {
