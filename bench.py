@@ -296,7 +296,8 @@ def main():
             A3, w3 = W.make_workload_gpu("mixed_1048576x512_cond1e10", seed=args.seed)
             torch.cuda.synchronize()
             runs = {}
-            for name, mode in (("fp64", P.CQRRPT_FP64), ("mixed", P.CQRRPT_MIXED)):
+            for name, mode in (("fp64", P.CQRRPT_FP64), ("mixed", P.CQRRPT_MIXED),
+                               ("mixed_checked", P.CQRRPT_MIXED_CHECKED)):
                 r = run_mode(P, torch, A3, w3, mode, w3["tol"], args.seed, steps2, 1)
                 runs[name] = {
                     "gflops_2mn2": r["gflops"], "ms_per_step": r["ms"], "p50_ms": r["p50"],
@@ -304,8 +305,9 @@ def main():
                     "recon": r["recon"], "cholqr2_passes": r["passes"],
                     "stages_ms": r["stages"]}
                 del r
-            runs["mixed"]["speedup_vs_fp64"] = (runs["fp64"]["ms_per_step"] /
-                                                runs["mixed"]["ms_per_step"])
+            for name in ("mixed", "mixed_checked"):
+                runs[name]["speedup_vs_fp64"] = (runs["fp64"]["ms_per_step"] /
+                                                 runs[name]["ms_per_step"])
             extra["mixed_vs_fp64_1048576x512_cond1e10"] = runs
             log(f"mixed vs fp64 (1048576x512): {runs}")
             del A3
@@ -330,7 +332,8 @@ def main():
 
     if not args.no_extra_runs and args.serving_requests > 0:
         srv_res = {}
-        for name, mode in (("fp64", P.CQRRPT_FP64), ("mixed", P.CQRRPT_MIXED)):
+        for name, mode in (("fp64", P.CQRRPT_FP64), ("mixed", P.CQRRPT_MIXED),
+                           ("mixed_checked", P.CQRRPT_MIXED_CHECKED)):
             srv_res[name] = serving_run(P, torch, W, args.serving_requests, mode, args.seed)
             log(f"serving ({name}): {srv_res[name]}")
         extra["serving_stream"] = srv_res

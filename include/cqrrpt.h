@@ -46,18 +46,23 @@ extern "C" {
 
 /* Precision modes (Sec. 3, Theorem "simple stability": the preconditioning
  * solve may run at a larger unit roundoff than the other steps).
- *   CQRRPT_FP64 : every step in FP64.
- *   CQRRPT_MIXED: the preconditioning solve M_pre = A[:,J] R_sk^{-1} runs on
- *                 FP32 matrix cores and stores M_pre in FP32; the Gram, the
- *                 Q solve, the sketch QRCP, Cholesky and R = R_pre R_sk stay
- *                 FP64; one extra CholeskyQR pass (Sec. 1.2, "CholeskyQR2":
- *                 G2 = Q^T Q, R2 = chol(G2), Q <- Q R2^{-1}, R <- R2 R) runs
- *                 when max |Q^T Q - I| exceeds 1e-13 and G2 has a full
- *                 Cholesky factor; the decision is taken on the device.
- *                 The second-stage rank bound on the diagonal of R_pre is
- *                 1e6 instead of 10 in this mode (the FP32 solve leaves
- *                 cond(M_pre) near u_fp32 cond(A); the re-pass handles it). */
-typedef enum { CQRRPT_FP64 = 0, CQRRPT_MIXED = 1 } cqrrpt_mode_t;
+ *   CQRRPT_FP64         : every step in FP64.
+ *   CQRRPT_MIXED        : the preconditioning solve M_pre = A[:,J] R_sk^{-1}
+ *                         runs on FP32 matrix cores and stores M_pre in FP32;
+ *                         the Gram, the Q solve, the sketch QRCP, Cholesky and
+ *                         R = R_pre R_sk stay FP64; one CholeskyQR pass, as
+ *                         the theorem analyses.
+ *   CQRRPT_MIXED_CHECKED: CQRRPT_MIXED, then G2 = Q^T Q (FP64) and an estimate
+ *                         of ||Q^T Q - I||_2 (power iteration on G2 - I); when
+ *                         it exceeds 5e-13, half the 1e-12 orthogonality
+ *                         target, and G2 has a full Cholesky factor, one more
+ *                         CholeskyQR pass (Sec. 1.2, "CholeskyQR2": R2 =
+ *                         chol(G2), Q <- Q R2^{-1}, R <- R2 R) runs; the
+ *                         decision is taken on the device.
+ * In both mixed modes the second-stage rank bound on the diagonal of R_pre
+ * is 1e6 instead of 10 (the FP32 solve can leave cond(M_pre) near
+ * u_fp32 cond(A), mostly as grading that CholeskyQR tolerates). */
+typedef enum { CQRRPT_FP64 = 0, CQRRPT_MIXED = 1, CQRRPT_MIXED_CHECKED = 2 } cqrrpt_mode_t;
 
 /* Per-call diagnostics, written to DEVICE memory by cqrrpt_factor_ex and
  * copied to the host by cqrrpt_factor. */
@@ -67,10 +72,11 @@ typedef struct {
     int64_t chol_fail_col;   /* 0-based column where Cholesky stopped, -1 if it did not
                                 (Remark on Cholesky failure, Sec. 3.3)                      */
     int32_t status;          /* CQRRPT_OK, CQRRPT_ENONFINITE or CQRRPT_EBARRIER             */
-    int32_t cholqr2_passes;  /* extra CholeskyQR passes run (mixed mode), 0 or 1            */
+    int32_t cholqr2_passes;  /* extra CholeskyQR passes run (checked mixed mode), 0 or 1    */
     double  smax;            /* max |R_sk|, the scale of the first-stage test               */
-    double  orth_est;        /* mixed mode: max |G2 - I| of the re-orthogonalisation Gram;
-                                0 when no estimate was formed                               */
+    double  orth_est;        /* checked mixed mode: estimate of ||Q^T Q - I||_2 for the Q
+                                of the first pass (16 power-iteration steps on G2 - I,
+                                G2 = Q^T Q in FP64); 0 when no estimate was formed         */
 } cqrrpt_info_t;
 
 /* Limits of this build: n <= 8192, d <= 16384, 1 <= nnz <= 32. */
@@ -173,8 +179,9 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n,
  * cqrrpt_stage_timing(slots): with slots > 0, every later cqrrpt_factor_ex
  * call records HIP events on its own stream at the boundaries of its nine
  * stages (sketch, qrcp, rank_stage1, precondition, gram, cholesky, q_solve,
- * r_product, cholqr2 -- the last is empty in FP64 mode), using event set
- * (call index mod slots); slots = 0 turns timing off and frees the events.
+ * r_product, cholqr2 -- the last is empty outside the checked mixed mode),
+ * using event set (call index mod slots); slots = 0 turns timing off and
+ * frees the events.
  * Process-wide setting, guarded by a mutex.
  * cqrrpt_stage_times(slot, ms): waits for that slot's last event and writes
  * the nine stage durations in milliseconds to the HOST array ms[9].

@@ -69,7 +69,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, int nnz, cqrrpt_mode_t mode)
   L.off_g = o; o += align256((size_t)n * n * 8);
   L.off_chol = o; o += align256(cqh::chol_ws_bytes((int)n));
   L.off_mpre32 = o;
-  if (mode == CQRRPT_MIXED) o += align256((size_t)m * n * 4);
+  if (mode != CQRRPT_FP64) o += align256((size_t)m * n * 4);
   L.total = o;
   return L;
 }
@@ -94,14 +94,17 @@ const char* const kStageNames[kStages] = {"sketch",   "qrcp",    "rank_stage1",
                                           "precondition", "gram", "cholesky",
                                           "q_solve",  "r_product", "cholqr2"};
 
-// Mixed mode re-runs CholeskyQR on Q when max |Q^T Q - I| exceeds this.
-constexpr double kCholQR2Threshold = 1e-13;
+// Checked mixed mode re-runs CholeskyQR on Q when its estimate of ||Q^T Q - I||_2
+// exceeds this: half the orthogonality target of 1e-12, which leaves room
+// for the estimate falling short of the norm and for rounding in G2.
+constexpr double kCholQR2Threshold = 5e-13;
 // Second-stage bound on max|diag R_pre| / min|diag R_pre| (Sec. 3.3): the
 // paper's sqrt(100) for a single FP64 CholeskyQR pass. With an FP32
-// preconditioning solve, cond(M_pre) is about u_fp32 cond(A) even when the
-// sketch resolves A, and the CholeskyQR2 re-pass restores orthogonality
-// whenever the first pass leaves u_fp64 cond(M_pre)^2 well below one, so
-// mixed mode accepts up to 1e6.
+// preconditioning solve, cond(M_pre) can reach about u_fp32 cond(A) even
+// when the sketch resolves A; most of that growth follows the grading of
+// the pivoted R_sk, which CholeskyQR on an accurate FP64 Gram tolerates (the
+// checked mode re-passes where it does not), so the mixed modes accept up
+// to 1e6.
 constexpr double kStage2CondFp64 = 10.0;
 constexpr double kStage2CondMixed = 1e6;
 struct StageTimer {
@@ -285,7 +288,7 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
   if (!R) return -11;
   if (ldr < n) return -12;
   if (!J) return -13;
-  if (mode != CQRRPT_FP64 && mode != CQRRPT_MIXED) return -14;
+  if (mode != CQRRPT_FP64 && mode != CQRRPT_MIXED && mode != CQRRPT_MIXED_CHECKED) return -14;
   if (!ws) return -15;
   if (!info) return -18;
   if (n > kMaxN || d > kMaxD || !cqh::sketch_fits((int)d, nnz)) return CQRRPT_ELIMIT;
@@ -334,7 +337,7 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
   mk.mark(5);
   // S7-S8: R_pre = chol(G) in place, second-stage rank k.
   CQ_TRY(cqh::launch_cholesky(G, n, ko_dev, ni, k_dev, base + L.off_chol, info, s,
-                              mode == CQRRPT_MIXED ? kStage2CondMixed : kStage2CondFp64));
+                              mode == CQRRPT_FP64 ? kStage2CondFp64 : kStage2CondMixed));
   mk.mark(6);
   // S9: Q = M_pre[:, :k] R_pre^{-1}.
   if (mode == CQRRPT_FP64) {
@@ -348,7 +351,7 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
   CQ_TRY(cqh::launch_trmm_r(G, n, Rsk, n, R, ldr, ni, k_dev, s));
   CQ_TRY(cqh::launch_zero_cols(Q, ldq, m, ni, k_dev, s));
   mk.mark(8);
-  if (mode == CQRRPT_MIXED) {
+  if (mode == CQRRPT_MIXED_CHECKED) {
     // S11: adaptive CholeskyQR2 pass, decided on the device. G2 = Q^T Q
     // (FP64) replaces R_pre in G, R's old value goes to the R_sk buffer
     // (both are dead after S10).
@@ -356,8 +359,9 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
     int* apply = pass + 1;
     int64_t* k2_dev = kv + 2;
     CQ_TRY(cqh::launch_syrk<double>(Q, ldq, m, k_dev, ni, Gp, G, n, info, s));
-    unsigned long long* mx = reinterpret_cast<unsigned long long*>(kv + 4);
-    CQ_TRY(cqh::launch_orth_check(G, n, k_dev, ni, kCholQR2Threshold, pass, mx, info, s));
+    // The partial Gram tiles are dead once G2 is summed: scratch for the
+    // power iteration.
+    CQ_TRY(cqh::launch_orth_check(G, n, k_dev, ni, kCholQR2Threshold, pass, Gp, info, s));
     CQ_TRY(cqh::launch_cholesky(G, n, k_dev, ni, k2_dev, base + L.off_chol, info, s, INFINITY,
                                 false, pass));
     CQ_TRY(cqh::launch_cholqr2_commit(pass, k_dev, k2_dev, apply, R, ldr, Rsk, n, ni, info, s));

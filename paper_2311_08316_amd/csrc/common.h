@@ -365,12 +365,13 @@ hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int km
 hipError_t launch_trmm_r(const double* Rpre, int64_t ldp, const double* Rsk, int64_t ldk,
                          double* R, int64_t ldr, int n, const int64_t* kdev, hipStream_t s,
                          const int* enable = nullptr);
-// CholeskyQR2 re-pass helpers: *pass = (max |G2 - I| > threshold); then
-// *apply = *pass and chol(G2) kept all k columns, and R is copied to Rcopy
-// when the pass applies.
+// CholeskyQR2 re-pass helpers: *pass = (estimate of ||G2 - I||_2 >
+// threshold), the estimate by power iteration on the k x k upper triangle of
+// G2 (vec: 2 n doubles of scratch); then *apply = *pass and chol(G2) kept all
+// k columns, and R is copied to Rcopy when the pass applies.
 hipError_t launch_orth_check(const double* G2, int64_t ldg, const int64_t* kdev, int n,
-                             double threshold, int* pass, unsigned long long* mx,
-                             cqrrpt_info_t* info, hipStream_t s);
+                             double threshold, int* pass, double* vec, cqrrpt_info_t* info,
+                             hipStream_t s);
 hipError_t launch_cholqr2_commit(const int* pass, const int64_t* k_dev, const int64_t* k2_dev,
                                  int* apply, const double* R, int64_t ldr, double* Rcopy,
                                  int64_t ldc, int n, cqrrpt_info_t* info, hipStream_t s);

@@ -336,42 +336,91 @@ trmm_kernel(const double* __restrict__ P, int64_t ldp, const double* __restrict_
 // decision to run the pass (estimate above the threshold). The pass applies
 // only if G2 then has a full Cholesky factor.
 // ---------------------------------------------------------------------------
-__global__ void orth_reset_kernel(unsigned long long* mx) {
-  if (threadIdx.x == 0) mx[0] = 0ull;
+// ||Q^T Q - I||_2 estimated by power iteration on E = sym(U) - I, where U is
+// the upper triangle of G2 = Q^T Q (k x k). Step t maps y_{t-1} to
+// y_t = E y_{t-1} / ||y_{t-1}||; y_{-1} is a fixed +-1 vector. For symmetric
+// E the norms ||y_t|| do not decrease and approach ||E||_2, so the last one
+// is the estimate. Every reduction has a fixed shape: deterministic.
+constexpr int kPowerSteps = 16;
+
+CQ_INLINE double start_sign(int64_t j) {
+  uint64_t h = (uint64_t)j * 0x9E3779B97F4A7C15ull;
+  h ^= h >> 29;
+  h *= 0xBF58476D1CE4E5B9ull;
+  h ^= h >> 32;
+  return (h & 1u) ? -1.0 : 1.0;
 }
 
-// One workgroup per column j < k: max |G2[i, j] - delta_ij| over i <= j,
-// folded into *mx as the bit pattern of a non-negative double (ordered like
-// the value, NaN above every number), so the result does not depend on the
-// order of the atomics.
-__global__ void __launch_bounds__(kThreads)
-orth_column_kernel(const double* __restrict__ G2, int64_t ldg, const int64_t* kdev,
-                   unsigned long long* mx) {
-  __shared__ double s_max[kWaves];
-  const int64_t j = blockIdx.x;
-  if (j >= *kdev) return;
-  double v = 0.0;
-  for (int64_t i = threadIdx.x; i <= j; i += kThreads) {
-    const double e = fabs(G2[i + j * ldg] - (i == j ? 1.0 : 0.0));
-    v = (e > v || e != e) ? e : v;
+// sqrt(sum v_j^2) over j < k, the same bits in every workgroup (v == null:
+// the start vector).
+__device__ double fixed_norm(const double* v, int64_t k, double* s_part) {
+  double acc = 0.0;
+  for (int64_t j = threadIdx.x; j < k; j += kThreads) {
+    const double x = v ? v[j] : start_sign(j);
+    acc += x * x;
   }
-  v = cq::wave_max(v);
-  if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = v;
+  acc = cq::wave_sum_dpp(acc);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = 0.0;
-    for (int w = 0; w < kWaves; ++w) m = (s_max[w] > m || s_max[w] != s_max[w]) ? s_max[w] : m;
-    atomicMax(mx, (unsigned long long)__double_as_longlong(m));
+  double t = s_part[0];
+  for (int w = 1; w < kWaves; ++w) t += s_part[w];
+  __syncthreads();
+  return sqrt(t);
+}
+
+// Rows 64 b .. 64 b + 63 of y_out = E x, x = y_in / ||y_in||. Entries of E
+// at or right of the diagonal come from U[i, j] (lanes along rows i, waves
+// over interleaved columns j); left of it from U[j, i], a column of U (one
+// row i per wave at a time, lanes along j).
+__global__ void __launch_bounds__(kThreads)
+orth_power_step_kernel(const double* __restrict__ G2, int64_t ldg, const int64_t* kdev,
+                       const double* __restrict__ yin, double* __restrict__ yout,
+                       const cqrrpt_info_t* info) {
+  __shared__ double s_part[kWaves];
+  __shared__ double s_a[kWaves][64];
+  __shared__ double s_b[64];
+  if (info->status != 0) return;
+  const int64_t k = *kdev;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  if (r0 >= k) return;
+  const double nu = fixed_norm(yin, k, s_part);
+  const double inv = nu > 0.0 ? 1.0 / nu : 0.0;
+  auto xval = [&](int64_t j) { return (yin ? yin[j] : start_sign(j)) * inv; };
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t i = r0 + lane;
+  double a = 0.0;
+  if (i < k)
+    for (int64_t j = r0 + wave; j < k; j += kWaves)
+      if (j >= i) a += G2[i + j * ldg] * xval(j);
+  s_a[wave][lane] = a;
+  for (int r = wave; r < 64 && r0 + r < k; r += kWaves) {
+    const int64_t ii = r0 + r;
+    double b = 0.0;
+    for (int64_t j = lane; j < ii; j += 64) b += G2[j + ii * ldg] * xval(j);
+    b = cq::wave_sum_dpp(b);
+    if (lane == 0) s_b[r] = b;
+  }
+  __syncthreads();
+  if (wave == 0 && i < k) {
+    double sa = s_a[0][lane];
+    for (int w = 1; w < kWaves; ++w) sa += s_a[w][lane];
+    yout[i] = (sa + s_b[lane]) - xval(i);
   }
 }
 
-__global__ void orth_decide_kernel(const unsigned long long* mx, const int64_t* kdev,
-                                   double threshold, int* pass, cqrrpt_info_t* info) {
+// Estimate ||y_T|| and the decision: a pass when it exceeds the threshold
+// (NaN fails the comparison: no pass on a non-finite Gram).
+__global__ void __launch_bounds__(kThreads)
+orth_power_decide_kernel(const double* __restrict__ y, const int64_t* kdev, double threshold,
+                         int* pass, cqrrpt_info_t* info) {
+  __shared__ double s_part[kWaves];
+  const int64_t k = *kdev;
+  const bool ok = info->status == 0 && k > 0;
+  const double est = ok ? fixed_norm(y, k, s_part) : 0.0;
   if (threadIdx.x == 0) {
-    const double m = __longlong_as_double((long long)mx[0]);
-    info->orth_est = m;
-    // NaN fails the comparison: no pass on a non-finite Gram.
-    pass[0] = (info->status == 0 && *kdev > 0 && m > threshold) ? 1 : 0;
+    info->orth_est = est;
+    pass[0] = (ok && est > threshold) ? 1 : 0;
   }
 }
 
@@ -461,16 +510,20 @@ hipError_t launch_trmm_r(const double* Rpre, int64_t ldp, const double* Rsk, int
 }
 
 hipError_t launch_orth_check(const double* G2, int64_t ldg, const int64_t* kdev, int n,
-                             double threshold, int* pass, unsigned long long* mx,
-                             cqrrpt_info_t* info, hipStream_t s) {
-  hipLaunchKernelGGL(orth_reset_kernel, dim3(1), dim3(64), 0, s, mx);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(orth_column_kernel, dim3(n), dim3(kThreads), 0, s, G2, ldg, kdev, mx);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(orth_decide_kernel, dim3(1), dim3(64), 0, s, mx, kdev, threshold, pass,
-                     info);
+                             double threshold, int* pass, double* vec, cqrrpt_info_t* info,
+                             hipStream_t s) {
+  const int nb = (n + 63) / 64;
+  const double* yin = nullptr;
+  for (int t = 0; t < kPowerSteps; ++t) {
+    double* yout = vec + (size_t)(t & 1) * n;
+    hipLaunchKernelGGL(orth_power_step_kernel, dim3(nb), dim3(kThreads), 0, s, G2, ldg, kdev, yin,
+                       yout, info);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    yin = yout;
+  }
+  hipLaunchKernelGGL(orth_power_decide_kernel, dim3(1), dim3(kThreads), 0, s, yin, kdev,
+                     threshold, pass, info);
   return hipGetLastError();
 }
 

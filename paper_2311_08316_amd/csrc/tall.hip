@@ -296,22 +296,34 @@ hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX*
 // ---------------------------------------------------------------------------
 // Gram G = X^T X (upper triangle), X m x k. Output tiles of 64 x 64, four
 // waves of 32 x 32, split over row ranges; each split writes its partial
-// tile, and a second kernel adds the splits in split order.
+// tile, and a second kernel adds the splits in split order. The number of
+// splits is a multiple of the XCD count, and workgroups are numbered so that
+// all tiles of one split land on the same XCD (workgroups are dealt to XCDs
+// round-robin): the tiles of a split read the same rows of X, which then
+// come from that XCD's L2 instead of once per XCD from memory.
 // ---------------------------------------------------------------------------
+constexpr int kXcds = 8;    // XCDs of the device; workgroups are dealt to them round-robin
 constexpr int kST = 64;     // output tile
 constexpr int kRK = 32;     // rows per staging step
 constexpr int kXLd = kRK + 1;
+constexpr int kFold = 4;    // staging steps per compensated chunk (a power of two)
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 syrk_kernel(const T* __restrict__ X, int64_t ldx, int64_t m, const int64_t* kdev, int kmax,
-            int64_t rows_per_split, double* __restrict__ P, const cqrrpt_info_t* info) {
+            int64_t rows_per_split, int tiles, double* __restrict__ P,
+            const cqrrpt_info_t* info) {
   __shared__ double XI[2][kST * kXLd];
   __shared__ double XJ[2][kST * kXLd];
   if (info->status != 0) return;
   const int64_t k = *kdev;
+  // Workgroup b runs on XCD b mod 8; its b / 8-th slot there takes tile
+  // (b / 8) mod tiles of split 8 ((b / 8) / tiles) + b mod 8.
+  const int xcd = blockIdx.x % kXcds;
+  const int slot = blockIdx.x / kXcds;
+  const int split = (slot / tiles) * kXcds + xcd;
   // Tile (I, J), I <= J, from the linear upper-triangle index.
-  const int t = blockIdx.x;
+  const int t = slot % tiles;
   int J = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((J + 1) * (J + 2) / 2 <= t) ++J;
   while (J * (J + 1) / 2 > t) --J;
@@ -326,14 +338,33 @@ syrk_kernel(const T* __restrict__ X, int64_t ldx, int64_t m, const int64_t* kdev
   const int lq = lane >> 4;
   const int wr = wave >> 1;
   const int wc = wave & 1;
-  const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t r0 = (int64_t)split * rows_per_split;
   const int64_t r1 = (r0 + rows_per_split) < m ? (r0 + rows_per_split) : m;
 
-  d4_t acc[2][2];
+  // The matrix cores add into acc, which restarts from zero every kFold
+  // staging steps (128 rows); each chunk sum is then added to (hi, lo) with
+  // an error-free two-sum, so the rounding error of the long sum over the
+  // split's rows stays at the level of one chunk's.
+  d4_t acc[2][2], hi[2][2], lo[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4_t{0, 0, 0, 0};
+    for (int b = 0; b < 2; ++b) acc[a][b] = hi[a][b] = lo[a][b] = d4_t{0, 0, 0, 0};
+  auto fold = [&]() {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double x = hi[a][b][r], y = acc[a][b][r];
+          const double sum = x + y;
+          const double yv = sum - x;
+          lo[a][b][r] += (x - (sum - yv)) + (y - yv);
+          hi[a][b][r] = sum;
+          acc[a][b][r] = 0.0;
+        }
+  };
 
   // Prefetched values stay in the input type until they are stored, so the
   // loads of the next step are not waited for by a conversion. Rows past
@@ -387,11 +418,13 @@ syrk_kernel(const T* __restrict__ X, int64_t ldx, int64_t m, const int64_t* kdev
           for (int b = 0; b < 2; ++b) acc[a][b] = mfma(af[a], bf[b], acc[a][b]);
       }
       if (more) store(buf ^ 1);
+      if ((it & (kFold - 1)) == kFold - 1) fold();
       __syncthreads();
     }
+    fold();
   }
 
-  double* Pout = P + (int64_t)blockIdx.y * kmax * kmax;
+  double* Pout = P + (int64_t)split * kmax * kmax;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -400,7 +433,7 @@ syrk_kernel(const T* __restrict__ X, int64_t ldx, int64_t m, const int64_t* kdev
       for (int r = 0; r < 4; ++r) {
         const int64_t i = i0 + 32 * wr + 16 * a + acc_row<double>(lq, r);
         const int64_t j = j0 + 32 * wc + 16 * b + l16;
-        if (i < kmax && j < kmax) Pout[i + j * kmax] = acc[a][b][r];
+        if (i < kmax && j < kmax) Pout[i + j * kmax] = hi[a][b][r] + lo[a][b][r];
       }
 }
 
@@ -416,9 +449,16 @@ syrk_reduce_kernel(const double* __restrict__ P, int nsplit, int kmax, const int
     const int64_t j = e / kmax;
     const int64_t i = e - j * kmax;
     if (i > j || j >= k) continue;
-    double s = 0.0;
-    for (int q = 0; q < nsplit; ++q) s += P[q * stride + e];
-    G[i + j * ldg] = s;
+    // Splits in order, compensated as in the partial tiles.
+    double s = 0.0, c = 0.0;
+    for (int q = 0; q < nsplit; ++q) {
+      const double y = P[q * stride + e];
+      const double t = s + y;
+      const double yv = t - s;
+      c += (s - (t - yv)) + (y - yv);
+      s = t;
+    }
+    G[i + j * ldg] = s + c;
   }
 }
 
@@ -458,8 +498,9 @@ int syrk_splits(int64_t m, int kmax) {
   int64_t want = (4 * (int64_t)device_info().num_cu + tiles - 1) / tiles;
   const int64_t maxs = (m + 4095) / 4096;  // at least 4096 rows per split
   if (want > maxs) want = maxs;
-  if (want < 1) want = 1;
   if (want > 64) want = 64;
+  // A multiple of the XCD count (splits past the rows add zero tiles).
+  want = (want + kXcds - 1) / kXcds * kXcds;
   return (int)want;
 }
 
@@ -476,8 +517,8 @@ hipError_t launch_syrk(const T* X, int64_t ldx, int64_t m, const int64_t* kdev, 
   rps = (rps + kRK - 1) / kRK * kRK;
   const int nt = (kmax + kST - 1) / kST;
   const int tiles = nt * (nt + 1) / 2;
-  hipLaunchKernelGGL((syrk_kernel<T>), dim3(tiles, nsplit), dim3(kThreads), 0, s, X, ldx, m, kdev,
-                     kmax, rps, partials, info);
+  hipLaunchKernelGGL((syrk_kernel<T>), dim3((unsigned)(tiles * nsplit)), dim3(kThreads), 0, s, X,
+                     ldx, m, kdev, kmax, rps, tiles, partials, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   int64_t grid = ((int64_t)kmax * kmax + kThreads - 1) / kThreads;

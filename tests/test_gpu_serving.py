@@ -40,9 +40,10 @@ def _solo(P, A, d, nnz, seed, tol, mode):
     return Q.cpu().numpy(), R.cpu().numpy(), J.cpu().numpy(), info.rank
 
 
-@pytest.mark.parametrize("mode_name", ["fp64", "mixed"])
+@pytest.mark.parametrize("mode_name", ["fp64", "mixed", "mixed_checked"])
 def test_server_mix_equals_solo(P, mode_name):
-    mode = P.CQRRPT_FP64 if mode_name == "fp64" else P.CQRRPT_MIXED
+    mode = {"fp64": P.CQRRPT_FP64, "mixed": P.CQRRPT_MIXED,
+            "mixed_checked": P.CQRRPT_MIXED_CHECKED}[mode_name]
     reqs = []
     for i, (m, n) in enumerate(SHAPES):
         A = W.serving_matrix_gpu(m, n, seed=100 + i)

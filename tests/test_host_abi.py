@@ -57,6 +57,7 @@ def test_workspace_bytes_argument_ranges(L):
     ws = L.cqrrpt_workspace_bytes
     assert ws(10000, 100, 125, 4, 0) > 0
     assert ws(10000, 100, 125, 4, 1) > ws(10000, 100, 125, 4, 0)  # FP32 M_pre
+    assert ws(10000, 100, 125, 4, 2) == ws(10000, 100, 125, 4, 1)  # checked: same buffers
     assert ws(100, 200, 250, 4, 0) == 0      # n > m
     assert ws(10000, 100, 99, 4, 0) == 0     # d < n
     assert ws(10000, 100, 125, 0, 0) == 0    # nnz < 1
@@ -95,6 +96,7 @@ def test_factor_ex_rejects_bad_arguments_before_any_device_work(L):
     assert call(R=None) == -11
     assert call(ldr=9) == -12
     assert call(J=None) == -13
+    assert call(mode=3) == -14
     assert call(mode=7) == -14
     assert call(ws=None) == -15
     assert call(info=None) == -18
