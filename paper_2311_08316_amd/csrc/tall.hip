@@ -424,30 +424,38 @@ syrk_kernel(const T* __restrict__ X, int64_t ldx, int64_t m, const int64_t* kdev
     fold();
   }
 
-  double* Pout = P + (int64_t)split * kmax * kmax;
+  // Partial tile (split, t), 64 x 64 column-major.
+  double* Pout = P + ((int64_t)split * tiles + t) * (kST * kST);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = i0 + 32 * wr + 16 * a + acc_row<double>(lq, r);
-        const int64_t j = j0 + 32 * wc + 16 * b + l16;
-        if (i < kmax && j < kmax) Pout[i + j * kmax] = hi[a][b][r] + lo[a][b][r];
+        const int li = 32 * wr + 16 * a + acc_row<double>(lq, r);
+        const int lj = 32 * wc + 16 * b + l16;
+        Pout[li + lj * kST] = hi[a][b][r] + lo[a][b][r];
       }
 }
 
 __global__ void __launch_bounds__(kThreads)
-syrk_reduce_kernel(const double* __restrict__ P, int nsplit, int kmax, const int64_t* kdev,
+syrk_reduce_kernel(const double* __restrict__ P, int nsplit, int tiles, const int64_t* kdev,
                    double* __restrict__ G, int64_t ldg, const cqrrpt_info_t* info) {
   if (info->status != 0) return;
   const int64_t k = *kdev;
-  const int64_t total = (int64_t)kmax * kmax;
+  const int64_t total = (int64_t)tiles * (kST * kST);
   const int64_t stride = total;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t j = e / kmax;
-    const int64_t i = e - j * kmax;
+    // Element (li, lj) of upper tile t = J (J + 1) / 2 + I.
+    const int t = (int)(e / (kST * kST));
+    const int loc = (int)(e - (int64_t)t * (kST * kST));
+    int J = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((J + 1) * (J + 2) / 2 <= t) ++J;
+    while (J * (J + 1) / 2 > t) --J;
+    const int I = t - J * (J + 1) / 2;
+    const int64_t i = (int64_t)I * kST + (loc % kST);
+    const int64_t j = (int64_t)J * kST + (loc / kST);
     if (i > j || j >= k) continue;
     // Splits in order, compensated as in the partial tiles.
     double s = 0.0, c = 0.0;
@@ -492,20 +500,33 @@ hipError_t launch_trsm_f32in(const float* B, int64_t ldb, double* X, int64_t ldx
                                                  nullptr, s);
 }
 
+// Splits: a multiple of the XCD count, at most 64, at least 1024 rows each,
+// partial tiles within 512 MB. Each XCD runs tiles x splits / 8 workgroups
+// in rounds of (two per CU) x (its CUs); the time goes as the number of
+// rounds times the rows per split, so take the count that minimises
+// ceil(rounds) / splits (a partly filled last round costs a whole round).
 int syrk_splits(int64_t m, int kmax) {
   const int nt = (kmax + kST - 1) / kST;
   const int64_t tiles = (int64_t)nt * (nt + 1) / 2;
-  int64_t want = (4 * (int64_t)device_info().num_cu + tiles - 1) / tiles;
-  const int64_t maxs = (m + 4095) / 4096;  // at least 4096 rows per split
-  if (want > maxs) want = maxs;
-  if (want > 64) want = 64;
-  // A multiple of the XCD count (splits past the rows add zero tiles).
-  want = (want + kXcds - 1) / kXcds * kXcds;
-  return (int)want;
+  const int64_t slots = 2 * (int64_t)device_info().num_cu / kXcds;
+  const int64_t tile_bytes = (int64_t)kST * kST * 8;
+  int best = kXcds;
+  double best_cost = 0.0;
+  for (int ns = kXcds; ns <= 64; ns += kXcds) {
+    if (ns > kXcds && ((m + ns - 1) / ns < 1024 || ns * tiles * tile_bytes > (512ll << 20))) break;
+    const int64_t items = tiles * ns / kXcds;
+    const double cost = (double)((items + slots - 1) / slots) / ns;
+    if (ns == kXcds || cost < best_cost * 0.999) {
+      best = ns;
+      best_cost = cost;
+    }
+  }
+  return best;
 }
 
 size_t syrk_ws_bytes(int64_t m, int kmax) {
-  return (size_t)syrk_splits(m, kmax) * kmax * kmax * 8;
+  const int nt = (kmax + kST - 1) / kST;
+  return (size_t)syrk_splits(m, kmax) * nt * (nt + 1) / 2 * kST * kST * 8;
 }
 
 template <typename T>
@@ -521,10 +542,10 @@ hipError_t launch_syrk(const T* X, int64_t ldx, int64_t m, const int64_t* kdev, 
                      ldx, m, kdev, kmax, rps, tiles, partials, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  int64_t grid = ((int64_t)kmax * kmax + kThreads - 1) / kThreads;
+  int64_t grid = ((int64_t)tiles * kST * kST + kThreads - 1) / kThreads;
   if (grid > 4096) grid = 4096;
   hipLaunchKernelGGL(syrk_reduce_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, partials,
-                     nsplit, kmax, kdev, G, ldg, info);
+                     nsplit, tiles, kdev, G, ldg, info);
   return hipGetLastError();
 }
 
