@@ -7,14 +7,17 @@
 //   * zero fill of Q's columns past the rank.
 //
 // The Cholesky factorization is one cooperative launch, right-looking over
-// 64-column blocks, three phases per block separated by grid barriers:
-//   1. one wave factors the diagonal block D = R_D^T R_D (a column per lane,
-//      in registers, rows broadcast with v_readlane) and forms R_D^{-1} the
-//      same way (back substitution, a column per lane);
+// 64-column blocks, two phases per block separated by grid barriers, with
+// the factorization of each diagonal block done one step early:
+//   *  one wave factors the diagonal block D = R_D^T R_D (a column per lane,
+//      in registers, rows broadcast through LDS) and forms R_D^{-1} the same
+//      way (back substitution, a column per lane);
 //   2a. the block row R[block, p] = R_D^{-T} G[block, p], one task per tile
 //      column, written over G's block row;
-//   2b. every workgroup takes trailing tiles (p, q), p <= q, and applies
-//      G[p, q] -= R[block, p]^T R[block, q].
+//   2b. trailing tiles (p, q), p <= q: G[p, q] -= R[block, p]^T R[block, q].
+//      Workgroup 0 takes only the next diagonal tile, keeps the updated tile
+//      in LDS and factors it (look-ahead); the other workgroups share the
+//      remaining tiles. The next step then starts at 2a.
 // G is overwritten by R_pre in place (upper triangle). Cross-workgroup data
 // goes through global memory ordered by agent-scope release/acquire fences
 // at the barriers.
@@ -101,85 +104,93 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
     }
   };
 
-  for (int jb = 0; jb < nblk; ++jb) {
-    const int64_t c0 = (int64_t)jb * kB;
-    // Phase 1: one wave factors the diagonal block (column `lane` in
-    // registers, rows broadcast with v_readlane) and inverts the factor the
-    // same way; the factor goes into G, its inverse to a.dinv.
-    if (g == 0) {
-      for (int e = tid; e < kB * kB; e += kThreads) {
-        const int i = e & (kB - 1);
-        const int j = e >> 6;
-        double v;
-        if (c0 + i < ko && c0 + j < ko)
-          v = i <= j ? Gm[(c0 + i) + (c0 + j) * ldg] : 0.0;
-        else
-          v = i == j ? 1.0 : 0.0;
-        D[i * kLd + j] = v;
-      }
-      if (tid == 0) s_fail = -1;
-      __syncthreads();
-      if (wave == 0) {
-        // Up-looking factorization, lane c = column c: row j of R_D is
-        //   R[j][c] = (D[j][c] - sum_{l<j} R[l][j] R[l][c]) / R[j][j],
-        // the pivot being the same expression at c = j. R[l][c] stays in
-        // this lane's registers; R[l][j] is read from LDS, where every lane
-        // writes its entry of row l once it is final (one wave: its LDS
-        // accesses are performed in program order).
-        double cl[kB];
+  // Factor the diagonal block held in D (upper triangle; identity past ko):
+  // one wave factors it (column `lane` in registers, rows broadcast through
+  // LDS) and inverts the factor the same way; the factor goes into G, its
+  // inverse to a.dinv, the failing column (or -1) to a.flags[0].
+  auto factor_in_lds = [&](int64_t c0) {
+    if (tid == 0) s_fail = -1;
+    __syncthreads();
+    if (wave == 0) {
+      // Up-looking factorization, lane c = column c: row j of R_D is
+      //   R[j][c] = (D[j][c] - sum_{l<j} R[l][j] R[l][c]) / R[j][j],
+      // the pivot being the same expression at c = j. R[l][c] stays in
+      // this lane's registers; R[l][j] is read from LDS, where every lane
+      // writes its entry of row l once it is final (one wave: its LDS
+      // accesses are performed in program order).
+      double cl[kB];
 #pragma unroll
-        for (int i = 0; i < kB; ++i) cl[i] = D[i * kLd + lane];
-        int fl = -1;
+      for (int i = 0; i < kB; ++i) cl[i] = D[i * kLd + lane];
+      int fl = -1;
+#pragma unroll
+      for (int j = 0; j < kB; ++j) {
+        double s0 = cl[j], s1 = 0.0;
+#pragma unroll
+        for (int l = 0; l < j; ++l) {
+          if (l & 1) s1 -= D[l * kLd + j] * cl[l];
+          else s0 -= D[l * kLd + j] * cl[l];
+        }
+        const double sj = s0 + s1;
+        const double piv = cq::readlane_d(sj, j);
+        if (fl < 0 && (!(piv > 0.0) || !isfinite(piv))) fl = j;
+        const double rj = sqrt(piv);
+        const double rv = lane == j ? rj : (lane > j ? sj / rj : 0.0);
+        cl[j] = fl < 0 ? rv : cl[j];
+        D[j * kLd + lane] = cl[j];
+      }
+      if (lane == 0 && fl >= 0) s_fail = (int)(c0 + fl);
+      if (fl < 0) {
+        // Row `lane` of W = R_D^{-1}: W[i][i] = 1 / R[i][i] and, for
+        // j > i, W[i][j] = -(sum_{i<=l<j} W[i][l] R[l][j]) / R[j][j], with
+        // R[l][j] from LDS and W[i][l] = 0 for l < i.
+        double w[kB];
 #pragma unroll
         for (int j = 0; j < kB; ++j) {
-          double s0 = cl[j], s1 = 0.0;
+          double s0 = 0.0, s1 = 0.0;
 #pragma unroll
           for (int l = 0; l < j; ++l) {
-            if (l & 1) s1 -= D[l * kLd + j] * cl[l];
-            else s0 -= D[l * kLd + j] * cl[l];
+            if (l & 1) s1 += w[l] * D[l * kLd + j];
+            else s0 += w[l] * D[l * kLd + j];
           }
-          const double sj = s0 + s1;
-          const double piv = cq::readlane_d(sj, j);
-          if (fl < 0 && (!(piv > 0.0) || !isfinite(piv))) fl = j;
-          const double rj = sqrt(piv);
-          const double rv = lane == j ? rj : (lane > j ? sj / rj : 0.0);
-          cl[j] = fl < 0 ? rv : cl[j];
-          D[j * kLd + lane] = cl[j];
+          const double rjj = D[j * kLd + j];
+          w[j] = lane == j ? 1.0 / rjj : (lane < j ? -(s0 + s1) / rjj : 0.0);
         }
-        if (lane == 0 && fl >= 0) s_fail = (int)(c0 + fl);
-        if (fl < 0) {
-          // Row `lane` of W = R_D^{-1}: W[i][i] = 1 / R[i][i] and, for
-          // j > i, W[i][j] = -(sum_{i<=l<j} W[i][l] R[l][j]) / R[j][j], with
-          // R[l][j] from LDS and W[i][l] = 0 for l < i.
-          double w[kB];
 #pragma unroll
-          for (int j = 0; j < kB; ++j) {
-            double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-            for (int l = 0; l < j; ++l) {
-              if (l & 1) s1 += w[l] * D[l * kLd + j];
-              else s0 += w[l] * D[l * kLd + j];
-            }
-            const double rjj = D[j * kLd + j];
-            w[j] = lane == j ? 1.0 / rjj : (lane < j ? -(s0 + s1) / rjj : 0.0);
-          }
-#pragma unroll
-          for (int j = 0; j < kB; ++j) YA[lane * kLd + j] = w[j];
-        }
+        for (int j = 0; j < kB; ++j) YA[lane * kLd + j] = w[j];
       }
-      __syncthreads();
-      for (int e = tid; e < kB * kB; e += kThreads) {
-        const int i = e & (kB - 1);
-        const int j = e >> 6;
-        if (i <= j && c0 + i < ko && c0 + j < ko) Gm[(c0 + i) + (c0 + j) * ldg] = D[i * kLd + j];
-        a.dinv[i + j * kB] = YA[i * kLd + j];
-      }
-      if (tid == 0) cq::st_agent(&a.flags[0], s_fail);
     }
-    if (!chol_sync(a.bar)) {
-      if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
-      return;
+    __syncthreads();
+    for (int e = tid; e < kB * kB; e += kThreads) {
+      const int i = e & (kB - 1);
+      const int j = e >> 6;
+      if (i <= j && c0 + i < ko && c0 + j < ko) Gm[(c0 + i) + (c0 + j) * ldg] = D[i * kLd + j];
+      a.dinv[i + j * kB] = YA[i * kLd + j];
     }
+    if (tid == 0) cq::st_agent(&a.flags[0], s_fail);
+  };
+
+  // Block 0 is factored before the loop; the factorization of block jb + 1
+  // runs inside step jb's trailing update (look-ahead, below).
+  if (g == 0 && nblk > 0) {
+    for (int e = tid; e < kB * kB; e += kThreads) {
+      const int i = e & (kB - 1);
+      const int j = e >> 6;
+      double v;
+      if (i < ko && j < ko)
+        v = i <= j ? Gm[i + (int64_t)j * ldg] : 0.0;
+      else
+        v = i == j ? 1.0 : 0.0;
+      D[i * kLd + j] = v;
+    }
+    factor_in_lds(0);
+  }
+  if (!chol_sync(a.bar)) {
+    if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
+    return;
+  }
+
+  for (int jb = 0; jb < nblk; ++jb) {
+    const int64_t c0 = (int64_t)jb * kB;
     fail = cq::ld_agent(&a.flags[0]);
     if (fail >= 0) break;
     const int nrest = nblk - jb - 1;
@@ -217,8 +228,10 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
     }
 
     // Phase 2b: trailing tiles (p, q), p <= q: G[p, q] -= R[block, p]^T R[block, q].
+    // Tile 0 is the next diagonal block: workgroup 0 updates it into LDS and
+    // factors it at once; the other tiles go to the other workgroups.
     const int ntr = nrest * (nrest + 1) / 2;
-    for (int t = g; t < ntr; t += G) {
+    auto trailing = [&](int t) {
       int q = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
       while ((q + 1) * (q + 2) / 2 <= t) ++q;
       while (q * (q + 1) / 2 > t) --q;
@@ -240,6 +253,37 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
           const int64_t j = cb + 4 * tj + y;
           if (i <= j && j < ko) Gm[i + j * ldg] -= acc[x][y];
         }
+    };
+    if (G > 1) {
+      for (int t = g; t < ntr; t += G - 1) {
+        if (g == 0) break;
+        trailing(t);
+      }
+    } else {
+      for (int t = 1; t < ntr; ++t) trailing(t);
+    }
+    if (g == 0) {
+      const int64_t cn = c0 + kB;
+      __syncthreads();
+      load_tile(YA, c0, cn);
+      __syncthreads();
+      double acc[4][4];
+      tile_atb<false>(YA, YA, ti, tj, acc);
+      __syncthreads();  // every thread is done reading YA (the factor reuses it)
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          const int i = 4 * ti + x;
+          const int j = 4 * tj + y;
+          double v;
+          if (cn + i < ko && cn + j < ko)
+            v = i <= j ? Gm[(cn + i) + (cn + j) * ldg] - acc[x][y] : 0.0;
+          else
+            v = i == j ? 1.0 : 0.0;
+          D[i * kLd + j] = v;
+        }
+      factor_in_lds(cn);
     }
     if (!chol_sync(a.bar)) {
       if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
