@@ -443,13 +443,36 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int d, int nnz) {
   }
   p.nc = nc;
   const int64_t ncb = (n + nc - 1) / nc;
-  // Enough workgroups to cover the chip about three times; each chunk keeps
-  // at least 8 sub-chunks so the partial sums stay small next to A.
-  int64_t want = (3 * dev.num_cu + ncb - 1) / ncb;
+  // Row chunks: the grid runs in rounds of (workgroups per CU) x CUs, and
+  // the time goes as rounds x sub-chunks per chunk (a partly filled last
+  // round costs a whole one), plus about one sub-chunk per round of
+  // prologue and epilogue. Each chunk keeps at least 8 sub-chunks so the
+  // partial sums stay small next to A.
+  int per_cu = 2;
+  if (p.reg_t > 0) {
+    const void* fn = reg_partial_kernel(p.reg_t, nc, (p.ts * nnz + 511) / 512);
+    int occ = 0;
+    if (fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kThreads, p.lds_bytes) ==
+                  hipSuccess &&
+        occ > 0)
+      per_cu = occ;
+    else
+      (void)hipGetLastError();
+  }
+  const int64_t slots = (int64_t)per_cu * dev.num_cu;
   int64_t maxchunks = p.nsub / 8;
   if (maxchunks < 1) maxchunks = 1;
-  if (want > maxchunks) want = maxchunks;
-  if (want < 1) want = 1;
+  int64_t want = 1;
+  int64_t best = -1;
+  for (int64_t c = 1; c <= maxchunks; ++c) {
+    const int64_t spc = (p.nsub + c - 1) / c;
+    const int64_t rounds = (ncb * c + slots - 1) / slots;
+    const int64_t cost = rounds * (spc + 1);
+    if (best < 0 || cost < best) {
+      best = cost;
+      want = c;
+    }
+  }
   p.subs_per_chunk = (int)((p.nsub + want - 1) / want);
   p.nchunk = (p.nsub + p.subs_per_chunk - 1) / p.subs_per_chunk;
   p.seg_bytes = align256((size_t)p.nsub * (d + 1) * 4);
