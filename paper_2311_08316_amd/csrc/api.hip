@@ -50,7 +50,7 @@ struct Layout {
   cqh::SketchPlan sk;
   cqh::QrcpPlan qr;
   size_t off_ahat, off_sketch, off_qrcp, off_rsk, off_rn2, off_bmax, off_k, off_syrkp, off_g,
-      off_chol, off_mpre32, total;
+      off_chol, off_tpack, off_mpre32, total;
 };
 
 Layout make_layout(int64_t m, int64_t n, int64_t d, int nnz, cqrrpt_mode_t mode) {
@@ -68,6 +68,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, int nnz, cqrrpt_mode_t mode)
   L.off_syrkp = o; o += align256(cqh::syrk_ws_bytes(m, (int)n));
   L.off_g = o; o += align256((size_t)n * n * 8);
   L.off_chol = o; o += align256(cqh::chol_ws_bytes((int)n));
+  L.off_tpack = o; o += align256(cqh::trsm_pack_bytes((int)n));
   L.off_mpre32 = o;
   if (mode != CQRRPT_FP64) o += align256((size_t)m * n * 4);
   L.total = o;
@@ -305,6 +306,7 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
   int64_t* ko_dev = kv;
   int64_t* k_dev = kv + 1;
   double* Gp = reinterpret_cast<double*>(base + L.off_syrkp);
+  double* tpack = reinterpret_cast<double*>(base + L.off_tpack);
   double* G = reinterpret_cast<double*>(base + L.off_g);
   const int ni = (int)n;
 
@@ -324,13 +326,13 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
   mk.mark(3);
   if (mode == CQRRPT_FP64) {
     // S5: M_pre = A[:, J[:k_o]] R_sk^{-1}, written into Q.
-    CQ_TRY(cqh::launch_trsm_f64(A, lda, J, Q, ldq, Rsk, n, m, ko_dev, ni, info, s));
+    CQ_TRY(cqh::launch_trsm_f64(A, lda, J, Q, ldq, Rsk, n, m, ko_dev, ni, tpack, info, s));
     mk.mark(4);
     // S6: G = M_pre^T M_pre.
     CQ_TRY(cqh::launch_syrk<double>(Q, ldq, m, ko_dev, ni, Gp, G, n, info, s));
   } else {
     float* M32 = reinterpret_cast<float*>(base + L.off_mpre32);
-    CQ_TRY(cqh::launch_trsm_mixed(A, lda, J, M32, m, Rsk, n, m, ko_dev, ni, info, s));
+    CQ_TRY(cqh::launch_trsm_mixed(A, lda, J, M32, m, Rsk, n, m, ko_dev, ni, tpack, info, s));
     mk.mark(4);
     CQ_TRY(cqh::launch_syrk<float>(M32, m, m, ko_dev, ni, Gp, G, n, info, s));
   }
@@ -341,10 +343,10 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
   mk.mark(6);
   // S9: Q = M_pre[:, :k] R_pre^{-1}.
   if (mode == CQRRPT_FP64) {
-    CQ_TRY(cqh::launch_trsm_f64(Q, ldq, nullptr, Q, ldq, G, n, m, k_dev, ni, info, s));
+    CQ_TRY(cqh::launch_trsm_f64(Q, ldq, nullptr, Q, ldq, G, n, m, k_dev, ni, tpack, info, s));
   } else {
     float* M32 = reinterpret_cast<float*>(base + L.off_mpre32);
-    CQ_TRY(cqh::launch_trsm_f32in(M32, m, Q, ldq, G, n, m, k_dev, ni, info, s));
+    CQ_TRY(cqh::launch_trsm_f32in(M32, m, Q, ldq, G, n, m, k_dev, ni, tpack, info, s));
   }
   mk.mark(7);
   // S10: R = R_pre R_sk[:k, :]; zero Q past the rank.
@@ -365,7 +367,8 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
     CQ_TRY(cqh::launch_cholesky(G, n, k_dev, ni, k2_dev, base + L.off_chol, info, s, INFINITY,
                                 false, pass));
     CQ_TRY(cqh::launch_cholqr2_commit(pass, k_dev, k2_dev, apply, R, ldr, Rsk, n, ni, info, s));
-    CQ_TRY(cqh::launch_trsm_f64(Q, ldq, nullptr, Q, ldq, G, n, m, k_dev, ni, info, s, apply));
+    CQ_TRY(cqh::launch_trsm_f64(Q, ldq, nullptr, Q, ldq, G, n, m, k_dev, ni, tpack, info, s,
+                                apply));
     CQ_TRY(cqh::launch_trmm_r(G, n, Rsk, n, R, ldr, ni, k_dev, s, apply));
   }
   mk.mark(9);
