@@ -134,7 +134,7 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wr = wave & 1;
-  const int wc = wave >> 1;
+  const int wc = __builtin_amdgcn_readfirstlane(wave >> 1);
   const int l16 = lane & 15;
   const int lq = lane >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * kRT;
@@ -295,9 +295,9 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
         for (int q = 0; q < kLoads; ++q)
           if (c0o + 16 * to + ca + 2 * q < k) xs[(int64_t)(2 * q) * ldx] = (TX)Tt[(ca + 2 * q) * kSLd + ra];
       }
-      // acc[:, tiles > t] += X_t R[tile t, tiles > t]. A wave with such a
-      // tile runs all four (done tiles take a zero R operand), which keeps
-      // the accumulators in place.
+      // acc[:, tiles > t] += X_t R[tile t, tiles > t]; a wave skips its
+      // column tiles that are already solved (the test is the same for every
+      // lane of the wave).
       if (4 * wc + 3 > to) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -306,10 +306,11 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
           for (int a = 0; a < 4; ++a) af[a] = Tt[(4 * s + lq) * kSLd + 64 * wr + 16 * a + l16];
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
-            const TC rv = Rs[(4 * s + lq) * kSLd + 64 * wc + 16 * b + l16];
-            const TC bf = 4 * wc + b > to ? rv : (TC)0;
+            if (4 * wc + b > to) {
+              const TC bf = Rs[(4 * s + lq) * kSLd + 64 * wc + 16 * b + l16];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) acc[a][b] = mfma(af[a], bf, acc[a][b]);
+              for (int a = 0; a < 4; ++a) acc[a][b] = mfma(af[a], bf, acc[a][b]);
+            }
           }
         }
       }
