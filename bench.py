@@ -53,8 +53,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-runs", action="store_true",
                     help="skip the planted-rank and mixed-precision runs")
-    ap.add_argument("--cpu-rows", type=int, default=16384,
-                    help="rows of the bounded sample the CPU oracle factors")
+    ap.add_argument("--cpu-rows", type=int, default=131072,
+                    help="rows of the bounded sample the CPU oracle factors (the default is "
+                         "the whole 131072-row benchmark input: about 10-20 s on the host)")
     ap.add_argument("--gaussian-input", action="store_true",
                     help="iid Gaussian input of the workload's shape (full rank; for "
                          "counter runs, where the QR-based generator is slow)")
