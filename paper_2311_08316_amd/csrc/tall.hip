@@ -177,7 +177,6 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
         sreg[q] = r_at(R, ldr32, ri < k ? ri : k - 1, cj < k ? cj : k - 1);
       }
     };
-    load_tile(0);
     acc_t acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -185,38 +184,32 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
       for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
     if (c0o > 0) {
-      TX areg[kLoads];
-      double rreg[kLoads];
-      auto load = [&](int kk) {
+      // Two register stages: the loads of K step s + 2 are issued while
+      // step s is multiplied out of LDS and step s + 1 waits in registers.
+      // The number of K steps, c0 / 16, is a multiple of 8.
+      TX areg0[kLoads], areg1[kLoads];
+      double rreg0[kLoads], rreg1[kLoads];
+      auto load = [&](int kk, TX (&ar)[kLoads], double (&rr)[kLoads]) {
         const TX* xs = X + rowa + (int64_t)(kk + ca) * ldx;
 #pragma unroll
-        for (int q = 0; q < kLoads; ++q) areg[q] = xs[(int64_t)(2 * q) * ldx];
+        for (int q = 0; q < kLoads; ++q) ar[q] = xs[(int64_t)(2 * q) * ldx];
         // R rows kk.. < c0 <= column: strictly above the diagonal.
 #pragma unroll
         for (int q = 0; q < kLoads; ++q) {
           const int col = c0o + cb + 16 * q;
-          rreg[q] = r_at(R, ldr32, kk + rb, col < k ? col : k - 1);
+          rr[q] = r_at(R, ldr32, kk + rb, col < k ? col : k - 1);
         }
       };
-      auto store = [&](int buf) {
+      auto store = [&](int buf, const TX (&ar)[kLoads], const double (&rr)[kLoads]) {
         TC* At = lds + buf * 2 * kTileSz;
         TC* Rt = At + kTileSz;
 #pragma unroll
-        for (int q = 0; q < kLoads; ++q) At[(ca + 2 * q) * kSLd + ra] = (TC)areg[q];
+        for (int q = 0; q < kLoads; ++q) At[(ca + 2 * q) * kSLd + ra] = (TC)ar[q];
 #pragma unroll
         for (int q = 0; q < kLoads; ++q)
-          Rt[rb * kSLd + cb + 16 * q] = c0o + cb + 16 * q < k ? (TC)rreg[q] : (TC)0;
+          Rt[rb * kSLd + cb + 16 * q] = c0o + cb + 16 * q < k ? (TC)rr[q] : (TC)0;
       };
-      load(0);
-      __syncthreads();  // the previous panel's diagonal phase is done with LDS
-      store(0);
-      __syncthreads();
-      for (int kk = 0; kk < c0o; kk += kKB) {
-        int kko = kk;
-        asm volatile("" : "+s"(kko));
-        const int buf = (kko / kKB) & 1;
-        const bool more = kko + kKB < c0o;
-        if (more) load(kko + kKB);
+      auto multiply = [&](int buf) {
         const TC* At = lds + buf * 2 * kTileSz;
         const TC* Rt = At + kTileSz;
 #pragma unroll
@@ -231,10 +224,29 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = mfma(af[a], bf[b], acc[a][b]);
         }
-        if (more) store(buf ^ 1);
+      };
+      const int nk = c0o / kKB;
+      load(0, areg0, rreg0);
+      load(kKB, areg1, rreg1);
+      __syncthreads();  // the previous panel's diagonal phase is done with LDS
+      store(0, areg0, rreg0);
+      __syncthreads();
+      for (int it = 0; it < nk; it += 2) {
+        int ito = it;
+        asm volatile("" : "+s"(ito));
+        // Step it is in LDS buffer 0, step it + 1 in registers 1.
+        if (ito + 2 < nk) load((ito + 2) * kKB, areg0, rreg0);
+        multiply(0);
+        store(1, areg1, rreg1);
+        __syncthreads();
+        // Step it + 1 is in LDS buffer 1, step it + 2 in registers 0.
+        if (ito + 3 < nk) load((ito + 3) * kKB, areg1, rreg1);
+        multiply(1);
+        if (ito + 2 < nk) store(0, areg0, rreg0);
         __syncthreads();
       }
     }
+    load_tile(0);  // the diagonal phase's first B tile and R strip
 
     // Diagonal block, one 16-column tile at a time.
     for (int t = 0; t < nt; ++t) {
