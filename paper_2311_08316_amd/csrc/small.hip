@@ -23,6 +23,8 @@
 // at the barriers.
 #include <math.h>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace {
@@ -53,32 +55,93 @@ CQ_INLINE bool chol_sync(const cq::GridBarrier& b) {
   return ok;
 }
 
-// C[4x4 per thread] = A^T B over l < kB for 64 x 64 LDS tiles (A, B stored
-// [l][c] with leading dimension kLd); A may be restricted to l <= row (upper).
-template <bool kUpperA>
-CQ_INLINE void tile_atb(const double* A, const double* B, int ti, int tj, double (&acc)[4][4]) {
+// 64 x 64 tile products on the matrix cores, operands staged in LDS as
+// [l][x] (l the contraction index, leading dimension kLd):
+//   T[i][j] = sum_l A[l][i] B[l][j].
+// Wave w owns the 32 x 32 quadrant i in [32 (w & 1), +32), j in
+// [32 (w >> 1), +32). The instruction runs with j as its M index and i as
+// its N index, so value r of accumulator acc[a][b] in lane (l16, lq) is
+// T[i = 32 (w & 1) + 16 a + l16][j = 32 (w >> 1) + 16 b + lq + 4 r]: 16
+// consecutive lanes hold 16 consecutive i, the contiguous index of G.
+CQ_INLINE d4_t mfma64(double a, double b, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+CQ_INLINE void tile_atb(const double* A, const double* B, int wi, int wj, int l16, int lq,
+                        d4_t (&acc)[2][2]) {
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-  const int lmax = kUpperA ? 4 * ti + 4 : kB;
-  for (int l = 0; l < lmax; ++l) {
-    double av[4], bv[4];
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int s = 0; s < kB / 4; ++s) {
+    const int l = 4 * s + lq;
+    double bi[2], aj[2];
 #pragma unroll
-    for (int x = 0; x < 4; ++x) av[x] = A[l * kLd + 4 * ti + x];
+    for (int x = 0; x < 2; ++x) bi[x] = A[l * kLd + 32 * wi + 16 * x + l16];
 #pragma unroll
-    for (int y = 0; y < 4; ++y) bv[y] = B[l * kLd + 4 * tj + y];
+    for (int y = 0; y < 2; ++y) aj[y] = B[l * kLd + 32 * wj + 16 * y + l16];
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] += av[x] * bv[y];
+      for (int y = 0; y < 2; ++y) acc[x][y] = mfma64(aj[y], bi[x], acc[x][y]);
+  }
+}
+
+typedef __attribute__((address_space(3))) const double lds_cdouble;
+
+// Address of element (j, j + 1) of a [64][kLd] LDS array, held in a vector
+// register: the reads of a row then share one address register and take
+// their distance from the instruction's offset field (a uniform address is
+// otherwise formed in scalar registers and copied for every read).
+CQ_INLINE const lds_cdouble* lds_row(const double* arr, int j) {
+  uint32_t a = (uint32_t)(size_t)((const lds_cdouble*)arr + j * (kLd + 1) + 1);
+  asm volatile("" : "+v"(a));
+  return (const lds_cdouble*)(size_t)a;
+}
+
+// v[i] = v[i + 1] - row[i] * s for slots kFirst..kN-1 (the register window
+// moves by one row). The product is negated in the source so that it maps
+// to the three-operand FMA (the two-operand form needs a copy per slot).
+// The row is read in chunks of 16 values, each chunk's reads issued before
+// the previous chunk's multiply-adds (the compiler's own schedule kept about
+// three reads in flight, leaving most of the LDS latency exposed); the
+// empty asm statements with a memory clobber keep the reads in place.
+// hook() runs right after the first chunks' reads are issued (the next
+// step's pivot work, whose chain then overlaps the reads and the update).
+template <int kFirst, int kN, typename Hook>
+CQ_INLINE void shift_update(double (&v)[kB], const lds_cdouble* row, double s, Hook&& hook) {
+  constexpr int kC = 16;
+  constexpr int kLen = kN - kFirst;
+  constexpr int kChunks = (kLen + kC - 1) / kC;
+  double buf[2][kC];
+#pragma unroll
+  for (int u = 0; u < kC && u < kLen; ++u) buf[0][u] = row[kFirst + u];
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) {
+    if (c + 1 < kChunks) {
+#pragma unroll
+      for (int u = 0; u < kC; ++u)
+        if ((c + 1) * kC + u < kLen) buf[(c + 1) & 1][u] = row[kFirst + (c + 1) * kC + u];
+    }
+    asm volatile("" ::: "memory");
+    if (c == 0) hook();
+#pragma unroll
+    for (int u = 0; u < kC; ++u) {
+      const int i = kFirst + c * kC + u;
+      if (c * kC + u < kLen) v[i] = fma(-buf[c & 1][u], s, v[i + 1]);
+    }
   }
 }
 
 __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
-  __shared__ double D[kB * kLd];
+  // D and YB carry 16 extra values: the factor's row updates read a fixed
+  // number of values past the diagonal (results for rows past the block are
+  // discarded).
+  __shared__ double D[kB * kLd + 16];
   __shared__ double YA[kB * kLd];
-  __shared__ double YB[kB * kLd];
+  __shared__ double YB[kB * kLd + 16];
+  __shared__ double IR[kB];
   __shared__ int s_fail;
 
   const int G = gridDim.x;
@@ -86,8 +149,10 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int ti = tid >> 4;
-  const int tj = tid & 15;
+  const int l16 = lane & 15;
+  const int lq = lane >> 4;
+  const int wi = wave & 1;
+  const int wj = wave >> 1;
   if (a.enable && *a.enable == 0) return;
   int64_t ko = *a.ko;
   if (cq::ld_agent(&a.info->status) != 0) ko = 0;
@@ -96,69 +161,140 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
   double* Gm = a.G;
   int fail = -1;
 
+  // G[r0 + l][c0 + c] (zero past ko) into dst[l][c]: all 16 loads of a
+  // thread are issued before the first LDS store; addresses are clamped
+  // into the valid k_o x k_o block.
   auto load_tile = [&](double* dst, int64_t r0, int64_t cc0) {
-    for (int e = tid; e < kB * kB; e += kThreads) {
+    double v[kB * kB / kThreads];
+#pragma unroll
+    for (int u = 0; u < kB * kB / kThreads; ++u) {
+      const int e = tid + u * kThreads;
+      const int64_t r = r0 + (e & (kB - 1));
+      const int64_t c = cc0 + (e >> 6);
+      v[u] = Gm[(r < ko ? r : ko - 1) + (c < ko ? c : ko - 1) * ldg];
+    }
+#pragma unroll
+    for (int u = 0; u < kB * kB / kThreads; ++u) {
+      const int e = tid + u * kThreads;
       const int l = e & (kB - 1);
       const int c = e >> 6;
-      dst[l * kLd + c] = (r0 + l < ko && cc0 + c < ko) ? Gm[(r0 + l) + (cc0 + c) * ldg] : 0.0;
+      dst[l * kLd + c] = (r0 + l < ko && cc0 + c < ko) ? v[u] : 0.0;
     }
   };
+  // G[r0 + i][c0 + j] at the accumulator positions of this lane (zero past ko).
+  auto load_acc = [&](int64_t r0, int64_t cc0, double (&t)[2][2][4]) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = r0 + 32 * wi + 16 * x + l16;
+          const int64_t j = cc0 + 32 * wj + 16 * y + lq + 4 * r;
+          t[x][y][r] = Gm[(i < ko ? i : ko - 1) + (j < ko ? j : ko - 1) * ldg];
+        }
+  };
 
-  // Factor the diagonal block held in D (upper triangle; identity past ko):
-  // one wave factors it (column `lane` in registers, rows broadcast through
-  // LDS) and inverts the factor the same way; the factor goes into G, its
-  // inverse to a.dinv, the failing column (or -1) to a.flags[0].
-  auto factor_in_lds = [&](int64_t c0) {
+  // Factor the diagonal block held in D (upper triangle; identity past ko)
+  // and invert the factor. Right-looking, one step per row j, all waves
+  // meeting at one barrier per step:
+  //   wave 0 (lane c = column c of the Schur complement S, in registers)
+  //     publishes row j to YB, writes row j of R_D (S[j][c] / sqrt(p),
+  //     sqrt(p) on the diagonal, p = S[j][j]) to D and 1 / sqrt(p) to IR,
+  //     and updates S[i][c] -= S[j][i] (S[j][c] / p) for i > j;
+  //   wave 1 (lane i = row i of W = R_D^{-1}), one step behind, forms
+  //     W[i][j] = (delta_ij - sum_{l<j} W[i][l] R[l][j]) / R[j][j] from row
+  //     j of R and adds W[i][j] R[j][c] to its running sums for c > j.
+  // Both keep their 64 values in registers as a window that moves by one
+  // row per step (slot 0 is always the current row), so the step body has
+  // fixed register indices and the loop over j stays rolled. One loop per
+  // quarter of j updates a fixed number of slots (63, 48, 32, 16) with no
+  // branches, so the LDS reads of a step can all be in flight together;
+  // slots past row 63 hold values that are never used. The factor goes into
+  // G, W to a.dinv, the failing column (or -1) to a.flags[0]. After a
+  // failure wave 0 stops updating; W is then unused.
+  auto factor_in_lds = [&](int64_t c0) __attribute__((always_inline)) {
     if (tid == 0) s_fail = -1;
     __syncthreads();
+    double v[kB];
     if (wave == 0) {
-      // Up-looking factorization, lane c = column c: row j of R_D is
-      //   R[j][c] = (D[j][c] - sum_{l<j} R[l][j] R[l][c]) / R[j][j],
-      // the pivot being the same expression at c = j. R[l][c] stays in
-      // this lane's registers; R[l][j] is read from LDS, where every lane
-      // writes its entry of row l once it is final (one wave: its LDS
-      // accesses are performed in program order).
-      double cl[kB];
 #pragma unroll
-      for (int i = 0; i < kB; ++i) cl[i] = D[i * kLd + lane];
-      int fl = -1;
+      for (int i = 0; i < kB; ++i) v[i] = D[i * kLd + lane];
+    } else {
 #pragma unroll
-      for (int j = 0; j < kB; ++j) {
-        double s0 = cl[j], s1 = 0.0;
-#pragma unroll
-        for (int l = 0; l < j; ++l) {
-          if (l & 1) s1 -= D[l * kLd + j] * cl[l];
-          else s0 -= D[l * kLd + j] * cl[l];
-        }
-        const double sj = s0 + s1;
-        const double piv = cq::readlane_d(sj, j);
-        if (fl < 0 && (!(piv > 0.0) || !isfinite(piv))) fl = j;
-        const double rj = sqrt(piv);
-        const double rv = lane == j ? rj : (lane > j ? sj / rj : 0.0);
-        cl[j] = fl < 0 ? rv : cl[j];
-        D[j * kLd + lane] = cl[j];
-      }
-      if (lane == 0 && fl >= 0) s_fail = (int)(c0 + fl);
-      if (fl < 0) {
-        // Row `lane` of W = R_D^{-1}: W[i][i] = 1 / R[i][i] and, for
-        // j > i, W[i][j] = -(sum_{i<=l<j} W[i][l] R[l][j]) / R[j][j], with
-        // R[l][j] from LDS and W[i][l] = 0 for l < i.
-        double w[kB];
-#pragma unroll
-        for (int j = 0; j < kB; ++j) {
-          double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-          for (int l = 0; l < j; ++l) {
-            if (l & 1) s1 += w[l] * D[l * kLd + j];
-            else s0 += w[l] * D[l * kLd + j];
-          }
-          const double rjj = D[j * kLd + j];
-          w[j] = lane == j ? 1.0 / rjj : (lane < j ? -(s0 + s1) / rjj : 0.0);
-        }
-#pragma unroll
-        for (int j = 0; j < kB; ++j) YA[lane * kLd + j] = w[j];
-      }
+      for (int i = 0; i < kB; ++i) v[i] = 0.0;
     }
+    // Wave 0: quantities of step j from the current row sj = S[j][lane]:
+    // ir = 1 / sqrt(p), the row of R_D (rv; the unscaled row after a
+    // failure) and the update factor f = S[j][lane] / p (0 for lanes <= j).
+    // The failure state lives in vector registers (fl: failing row or -1)
+    // so that a step compiles to selects, not branches, and its chain can
+    // be interleaved with the update.
+    int fl = -1;
+    double f = 0.0, rv = 0.0, ir = 0.0;
+    auto pivot = [&](int j, double sj) __attribute__((always_inline)) {
+      double piv = cq::readlane_d(sj, j);
+      asm volatile("" : "+v"(piv));
+      asm volatile("" : "+v"(fl));
+      const bool bad = !(piv > 0.0) || !isfinite(piv);
+      fl = (fl < 0 && bad) ? j : fl;
+      const bool ok = fl < 0;
+      // 1 / sqrt(p): the hardware estimate refined by two Newton steps for
+      // y = p^{-1/2} (y <- y + y (1 - p y^2) / 2), a short dependency chain
+      // next to the correctly rounded square root and division; R_D then
+      // agrees with them to a few ulps.
+      double y = __builtin_amdgcn_rsq(piv);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const double e = fma(-piv * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+      }
+      ir = y;
+      const double rj = piv * y;
+      const double sc = sj * y;
+      f = (ok && lane > j) ? sc * y : 0.0;
+      rv = ok ? (lane == j ? rj : (lane > j ? sc : 0.0)) : sj;
+    };
+    if (wave == 0) pivot(0, v[0]);
+    // Steps it0..it1-1 with kN window slots updated per step (enough for
+    // wave 0 at row j = it and for wave 1 at row j = it - 1). Wave 0 forms
+    // the next row's first entry from S[j][j + 1] (read from lane j + 1)
+    // and the next step's pivot quantities before the bulk of the update,
+    // so their dependency chain overlaps the multiply-adds.
+    auto steps = [&](int it0, int it1, auto ntag) __attribute__((always_inline)) {
+      constexpr int kN = decltype(ntag)::value;
+      for (int it = it0; it < it1; ++it) {
+        if (wave == 0 && it < kB) {
+          const int j = it;
+          const double sj = v[0];
+          YB[j * kLd + lane] = sj;
+          D[j * kLd + lane] = rv;
+          IR[j] = ir;
+          if (j + 1 < kB) {
+            const double s1 = fma(-cq::readlane_d(sj, j + 1), f, v[1]);
+            const double fj = f;
+            shift_update<1, kN>(v, lds_row(YB, j), fj, [&]() __attribute__((always_inline)) {
+              pivot(j + 1, s1);
+            });
+            v[0] = s1;
+          }
+        }
+        if (wave == 1 && it > 0) {
+          const int j = it - 1;
+          const double w = ((lane == j ? 1.0 : 0.0) - v[0]) * IR[j];
+          YA[lane * kLd + j] = w;
+          double nw = -w;
+          asm volatile("" : "+v"(nw));  // keeps the product's sign on the load
+          shift_update<0, kN>(v, lds_row(D, j), nw, []() {});
+        }
+        __syncthreads();
+      }
+    };
+    steps(0, 16, std::integral_constant<int, 63>());
+    steps(16, 32, std::integral_constant<int, 48>());
+    steps(32, 48, std::integral_constant<int, 32>());
+    steps(48, kB + 1, std::integral_constant<int, 16>());
+    if (wave == 0 && lane == 0 && fl >= 0) s_fail = (int)(c0 + fl);
     __syncthreads();
     for (int e = tid; e < kB * kB; e += kThreads) {
       const int i = e & (kB - 1);
@@ -172,15 +308,13 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
   // Block 0 is factored before the loop; the factorization of block jb + 1
   // runs inside step jb's trailing update (look-ahead, below).
   if (g == 0 && nblk > 0) {
+    load_tile(D, 0, 0);
+    __syncthreads();
     for (int e = tid; e < kB * kB; e += kThreads) {
       const int i = e & (kB - 1);
       const int j = e >> 6;
-      double v;
-      if (i < ko && j < ko)
-        v = i <= j ? Gm[i + (int64_t)j * ldg] : 0.0;
-      else
-        v = i == j ? 1.0 : 0.0;
-      D[i * kLd + j] = v;
+      if (i >= ko || j >= ko) D[i * kLd + j] = i == j ? 1.0 : 0.0;
+      else if (i > j) D[i * kLd + j] = 0.0;
     }
     factor_in_lds(0);
   }
@@ -199,27 +333,34 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
     // Phase 2a: block row of R_pre, R[block, p] = R_D^{-T} G[block, p], one
     // task per tile column; each task overwrites only its own tile.
     if (g < nrest) {
-      for (int e = tid; e < kB * kB; e += kThreads) {
-        const int i = e & (kB - 1);
-        const int j = e >> 6;
-        D[i * kLd + j] = a.dinv[i + j * kB];
+      {
+        // W = R_D^{-1} as A[l][i] = W[l][i] (column-major in a.dinv).
+        double v[kB * kB / kThreads];
+#pragma unroll
+        for (int u = 0; u < kB * kB / kThreads; ++u) v[u] = a.dinv[tid + u * kThreads];
+#pragma unroll
+        for (int u = 0; u < kB * kB / kThreads; ++u) {
+          const int e = tid + u * kThreads;
+          YA[(e & (kB - 1)) * kLd + (e >> 6)] = v[u];
+        }
       }
       for (int p = g; p < nrest; p += G) {
         const int64_t cp = (int64_t)(jb + 1 + p) * kB;
         __syncthreads();
-        load_tile(YA, c0, cp);
+        load_tile(YB, c0, cp);
         __syncthreads();
-        double acc[4][4];
-        // (R_D^{-1})^T is lower: row i of the product uses l <= i.
-        tile_atb<true>(D, YA, ti, tj, acc);
+        d4_t acc[2][2];
+        tile_atb(YA, YB, wi, wj, l16, lq, acc);
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-          for (int y = 0; y < 4; ++y) {
-            const int64_t i = c0 + 4 * ti + x;
-            const int64_t j = cp + 4 * tj + y;
-            if (i < ko && j < ko) Gm[i + j * ldg] = acc[x][y];
-          }
+          for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int64_t i = c0 + 32 * wi + 16 * x + l16;
+              const int64_t j = cp + 32 * wj + 16 * y + lq + 4 * r;
+              if (i < ko && j < ko) Gm[i + j * ldg] = acc[x][y][r];
+            }
       }
     }
     if (!chol_sync(a.bar)) {
@@ -242,17 +383,21 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
       __syncthreads();
       load_tile(YA, c0, ca);
       if (!same) load_tile(YB, c0, cb);
+      double tg[2][2][4];
+      load_acc(ca, cb, tg);
       __syncthreads();
-      double acc[4][4];
-      tile_atb<false>(YA, same ? YA : YB, ti, tj, acc);
+      d4_t acc[2][2];
+      tile_atb(YA, same ? YA : YB, wi, wj, l16, lq, acc);
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          const int64_t i = ca + 4 * ti + x;
-          const int64_t j = cb + 4 * tj + y;
-          if (i <= j && j < ko) Gm[i + j * ldg] -= acc[x][y];
-        }
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t i = ca + 32 * wi + 16 * x + l16;
+            const int64_t j = cb + 32 * wj + 16 * y + lq + 4 * r;
+            if (i <= j && j < ko) Gm[i + j * ldg] = tg[x][y][r] - acc[x][y][r];
+          }
     };
     if (G > 1) {
       for (int t = g; t < ntr; t += G - 1) {
@@ -266,23 +411,26 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
       const int64_t cn = c0 + kB;
       __syncthreads();
       load_tile(YA, c0, cn);
+      double tg[2][2][4];
+      load_acc(cn, cn, tg);
       __syncthreads();
-      double acc[4][4];
-      tile_atb<false>(YA, YA, ti, tj, acc);
-      __syncthreads();  // every thread is done reading YA (the factor reuses it)
+      d4_t acc[2][2];
+      tile_atb(YA, YA, wi, wj, l16, lq, acc);
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          const int i = 4 * ti + x;
-          const int j = 4 * tj + y;
-          double v;
-          if (cn + i < ko && cn + j < ko)
-            v = i <= j ? Gm[(cn + i) + (cn + j) * ldg] - acc[x][y] : 0.0;
-          else
-            v = i == j ? 1.0 : 0.0;
-          D[i * kLd + j] = v;
-        }
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 32 * wi + 16 * x + l16;
+            const int j = 32 * wj + 16 * y + lq + 4 * r;
+            double v;
+            if (cn + i < ko && cn + j < ko)
+              v = i <= j ? tg[x][y][r] - acc[x][y][r] : 0.0;
+            else
+              v = i == j ? 1.0 : 0.0;
+            D[i * kLd + j] = v;
+          }
       factor_in_lds(cn);
     }
     if (!chol_sync(a.bar)) {

@@ -193,6 +193,29 @@ def test_factor_planted_rank(P):
         assert not Qn[:, r:].any() and not Rn[r:, :].any()
 
 
+def test_factor_cholesky_failure(P):
+    """Cholesky stops early and the second rank stage truncates (Sec. 3.3).
+
+    Rows of magnitude 1e10 next to rows of magnitude 1 with a one-nonzero
+    sketch (8000 x 128, d = 128): the sketch keeps full rank (k_o = 128) but
+    the preconditioned Gram is numerically singular. The oracle's pivots of
+    rows 0..81 are positive with margin (row 81: 3.1e15); the pivot of row 82
+    is 256 against a diagonal of 2e22, i.e. rounding noise, so the GPU must
+    stop at row 82 or later, where exactly depends on summation order. The
+    rank of stage 2 is robust (the diagonal ratio jumps from 2.5 to 1.9e8 at
+    row 75) and must match, together with the factors on those 75 columns.
+    """
+    say("factor cholesky failure 8000x128 coherent nnz=1")
+    A = W.high_coherence_matrix(8000, 128, 4, boost=1e10)
+    orc = O.cqrrpt(A, 128, 1, seed=0, tol=1e-14)
+    assert orc["rank_stage1"] == 128 and orc["rank"] == 75 and orc["chol_fail_col"] == 83
+    gpu = P.factor(to_gpu(A), 128, 1, 0, 1e-14)
+    info = gpu[3]
+    say(f"  chol_fail_col gpu {info.chol_fail_col} oracle {orc['chol_fail_col']}")
+    assert 82 <= info.chol_fail_col < 128 and info.status == 0
+    compare_factor(A, gpu, orc, "cholesky-failure")
+
+
 def test_factor_degenerate(P):
     say("factor zero / nonfinite")
     Z = np.zeros((400, 12))
