@@ -50,7 +50,7 @@ struct Layout {
   cqh::SketchPlan sk;
   cqh::QrcpPlan qr;
   size_t off_ahat, off_sketch, off_qrcp, off_rsk, off_rn2, off_bmax, off_k, off_syrkp, off_g,
-      off_chol, off_tpack, off_mpre32, total;
+      off_winv, off_chol, off_tpack, off_mpre32, total;
 };
 
 Layout make_layout(int64_t m, int64_t n, int64_t d, int nnz, cqrrpt_mode_t mode) {
@@ -67,6 +67,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, int nnz, cqrrpt_mode_t mode)
   L.off_k = o; o += 256;
   L.off_syrkp = o; o += align256(cqh::syrk_ws_bytes(m, (int)n));
   L.off_g = o; o += align256((size_t)n * n * 8);
+  L.off_winv = o; o += align256((size_t)n * n * 8);
   L.off_chol = o; o += align256(cqh::chol_ws_bytes((int)n));
   L.off_tpack = o; o += align256(cqh::trsm_pack_bytes((int)n));
   L.off_mpre32 = o;
@@ -308,6 +309,7 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
   double* Gp = reinterpret_cast<double*>(base + L.off_syrkp);
   double* tpack = reinterpret_cast<double*>(base + L.off_tpack);
   double* G = reinterpret_cast<double*>(base + L.off_g);
+  double* Winv = reinterpret_cast<double*>(base + L.off_winv);
   const int ni = (int)n;
 
   CallMarks mk = begin_marks(s);
@@ -337,16 +339,16 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
     CQ_TRY(cqh::launch_syrk<float>(M32, m, m, ko_dev, ni, Gp, G, n, info, s));
   }
   mk.mark(5);
-  // S7-S8: R_pre = chol(G) in place, second-stage rank k.
-  CQ_TRY(cqh::launch_cholesky(G, n, ko_dev, ni, k_dev, base + L.off_chol, info, s,
+  // S7-S8: R_pre = chol(G) in place, second-stage rank k; Winv = R_pre^{-1}.
+  CQ_TRY(cqh::launch_cholesky(G, n, ko_dev, ni, k_dev, Winv, n, base + L.off_chol, info, s,
                               mode == CQRRPT_FP64 ? kStage2CondFp64 : kStage2CondMixed));
   mk.mark(6);
-  // S9: Q = M_pre[:, :k] R_pre^{-1}.
+  // S9: Q = M_pre[:, :k] R_pre^{-1}, as the product with Winv[:k, :k].
   if (mode == CQRRPT_FP64) {
-    CQ_TRY(cqh::launch_trsm_f64(Q, ldq, nullptr, Q, ldq, G, n, m, k_dev, ni, tpack, info, s));
+    CQ_TRY(cqh::launch_qform_f64(Q, ldq, Q, ldq, Winv, n, m, k_dev, info, s));
   } else {
     float* M32 = reinterpret_cast<float*>(base + L.off_mpre32);
-    CQ_TRY(cqh::launch_trsm_f32in(M32, m, Q, ldq, G, n, m, k_dev, ni, tpack, info, s));
+    CQ_TRY(cqh::launch_qform_f32in(M32, m, Q, ldq, Winv, n, m, k_dev, info, s));
   }
   mk.mark(7);
   // S10: R = R_pre R_sk[:k, :]; zero Q past the rank.
@@ -364,11 +366,10 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
     // The partial Gram tiles are dead once G2 is summed: scratch for the
     // power iteration.
     CQ_TRY(cqh::launch_orth_check(G, n, k_dev, ni, kCholQR2Threshold, pass, Gp, info, s));
-    CQ_TRY(cqh::launch_cholesky(G, n, k_dev, ni, k2_dev, base + L.off_chol, info, s, INFINITY,
-                                false, pass));
+    CQ_TRY(cqh::launch_cholesky(G, n, k_dev, ni, k2_dev, Winv, n, base + L.off_chol, info, s,
+                                INFINITY, false, pass));
     CQ_TRY(cqh::launch_cholqr2_commit(pass, k_dev, k2_dev, apply, R, ldr, Rsk, n, ni, info, s));
-    CQ_TRY(cqh::launch_trsm_f64(Q, ldq, nullptr, Q, ldq, G, n, m, k_dev, ni, tpack, info, s,
-                                apply));
+    CQ_TRY(cqh::launch_qform_f64(Q, ldq, Q, ldq, Winv, n, m, k_dev, info, s, apply));
     CQ_TRY(cqh::launch_trmm_r(G, n, Rsk, n, R, ldr, ni, k_dev, s, apply));
   }
   mk.mark(9);

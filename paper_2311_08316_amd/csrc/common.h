@@ -189,48 +189,49 @@ CQ_INLINE void wave_argmax_dpp(double& v, int& c) {
 }
 
 // ---------------------------------------------------------------------------
-// Grid barrier for cooperative launches. Arrival counter plus a generation
-// word, both in device memory; agent-scope release/acquire orders every
-// wave's global writes before the barrier against reads after it. The spin is
-// bounded: on timeout the barrier raises *abort, which every participant
-// checks, so all workgroups leave the kernel.
+// Grid barrier for cooperative launches, on an arrival counter in device
+// memory that only grows within a launch (zeroed before it): barrier number k
+// (1, 2, ... in the order every workgroup passes them) is complete once the
+// counter reaches k * nblocks. Arriving is one atomic add whose result is not
+// needed; waiting polls the counter. Callers order their global writes before
+// an arrival with an agent-scope release fence and their reads after a wait
+// with an acquire fence. The spin is bounded: on timeout the barrier raises
+// *abort, which every participant checks, so all workgroups leave the kernel.
 // ---------------------------------------------------------------------------
 struct GridBarrier {
   unsigned* count;
-  unsigned* gen;
   int* abort;
   unsigned nblocks;
 };
 
 constexpr unsigned kSpinLimit = 1u << 24;
 
-// Returns false if the barrier was aborted.
-CQ_INLINE bool grid_sync(const GridBarrier& b) {
-  __shared__ int s_ok;
+CQ_INLINE void grid_arrive(const GridBarrier& b) {
   __syncthreads();
+  if (threadIdx.x == 0 && b.nblocks > 1)
+    __hip_atomic_fetch_add(b.count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits for barrier number k; false if the barrier was aborted.
+CQ_INLINE bool grid_wait(const GridBarrier& b, unsigned k) {
+  __shared__ int s_ok;
   if (threadIdx.x == 0) {
     int ok = 1;
     if (b.nblocks > 1) {
-      const unsigned g = __hip_atomic_load(b.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned arrived =
-          __hip_atomic_fetch_add(b.count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (arrived == b.nblocks - 1) {
-        __hip_atomic_store(b.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(b.gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        unsigned spins = 0;
-        while (__hip_atomic_load(b.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-          if (__hip_atomic_load(b.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            ok = 0;
-            break;
-          }
-          if (++spins > kSpinLimit) {
-            __hip_atomic_store(b.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = 0;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(2);
+      const unsigned target = k * b.nblocks;
+      unsigned spins = 0;
+      while ((int)(__hip_atomic_load(b.count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) -
+                   target) < 0) {
+        if (__hip_atomic_load(b.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ok = 0;
+          break;
         }
+        if (++spins > kSpinLimit) {
+          __hip_atomic_store(b.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
       }
       if (__hip_atomic_load(b.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
     }
@@ -241,7 +242,7 @@ CQ_INLINE bool grid_sync(const GridBarrier& b) {
 }
 
 // Agent-scope (device-coherent) loads and stores for data exchanged between
-// workgroups of one launch. Relaxed; ordering comes from grid_sync.
+// workgroups of one launch. Relaxed; ordering comes from the grid barrier.
 CQ_INLINE double ld_agent(const double* p) {
   const uint64_t v = __hip_atomic_load(reinterpret_cast<uint64_t*>(const_cast<double*>(p)),
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -351,6 +352,17 @@ hipError_t launch_trsm_f32in(const float* B, int64_t ldb, double* X, int64_t ldx
                              const double* R, int64_t ldr, int64_t m, const int64_t* kdev,
                              int kmax, double* pack, const cqrrpt_info_t* info, hipStream_t s);
 
+// Q[:, :k] = M[:, :k] W[:k, :k], W upper triangular (read above the
+// diagonal and on it only), 32-bit element offsets (ldw * 8192 < 2^32).
+// M may alias Q (same ld). enable as for the solve.
+hipError_t launch_qform_f64(const double* M, int64_t ldm, double* Q, int64_t ldq,
+                            const double* W, int64_t ldw, int64_t m, const int64_t* kdev,
+                            const cqrrpt_info_t* info, hipStream_t s,
+                            const int* enable = nullptr);
+hipError_t launch_qform_f32in(const float* M, int64_t ldm, double* Q, int64_t ldq,
+                              const double* W, int64_t ldw, int64_t m, const int64_t* kdev,
+                              const cqrrpt_info_t* info, hipStream_t s);
+
 int syrk_splits(int64_t m, int kmax);
 size_t syrk_ws_bytes(int64_t m, int kmax);
 template <typename T>
@@ -360,11 +372,14 @@ hipError_t launch_syrk(const T* X, int64_t ldx, int64_t m, const int64_t* kdev, 
 
 size_t chol_ws_bytes(int kmax);
 // cond_max: second-stage bound on max|diag| / min|diag| (infinity: none);
-// record: write rank and failing column into info.
+// record: write rank and failing column into info. W (ldw >= kmax) receives
+// R_pre^{-1} in its upper triangle (the leading k x k block is the inverse
+// of R_pre[:k, :k] for every k up to the failing column); its lower
+// triangle is left as it was.
 hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int kmax,
-                           int64_t* k_dev, void* ws, cqrrpt_info_t* info, hipStream_t s,
-                           double cond_max = 10.0, bool record = true,
-                           const int* enable = nullptr);
+                           int64_t* k_dev, double* W, int64_t ldw, void* ws,
+                           cqrrpt_info_t* info, hipStream_t s, double cond_max = 10.0,
+                           bool record = true, const int* enable = nullptr);
 
 hipError_t launch_trmm_r(const double* Rpre, int64_t ldp, const double* Rsk, int64_t ldk,
                          double* R, int64_t ldr, int n, const int64_t* kdev, hipStream_t s,

@@ -7,17 +7,20 @@
 //   * zero fill of Q's columns past the rank.
 //
 // The Cholesky factorization is one cooperative launch, right-looking over
-// 64-column blocks, two phases per block separated by grid barriers, with
-// the factorization of each diagonal block done one step early:
-//   *  one wave factors the diagonal block D = R_D^T R_D (a column per lane,
-//      in registers, rows broadcast through LDS) and forms R_D^{-1} the same
-//      way (back substitution, a column per lane);
+// 64-column blocks, with the factorization of each diagonal block done one
+// step early (look-ahead). Per block step:
 //   2a. the block row R[block, p] = R_D^{-T} G[block, p], one task per tile
-//      column, written over G's block row;
+//       column, a matrix-core product with the precomputed R_D^{-1}, written
+//       over G's block row;
+//   (grid barrier)
 //   2b. trailing tiles (p, q), p <= q: G[p, q] -= R[block, p]^T R[block, q].
-//      Workgroup 0 takes only the next diagonal tile, keeps the updated tile
-//      in LDS and factors it (look-ahead); the other workgroups share the
-//      remaining tiles. The next step then starts at 2a.
+//   (grid barrier)
+// Workgroup 0 holds the critical path: it computes the block row's first
+// tile itself, forms the next diagonal block from it in LDS and factors it
+// while the others finish 2a and 2b; it only counts itself in at the middle
+// barrier. The diagonal block D = R_D^T R_D is factored by one wave (a
+// column per lane, in registers, rows broadcast through LDS) while a second
+// wave forms R_D^{-1} one row behind it.
 // G is overwritten by R_pre in place (upper triangle). Cross-workgroup data
 // goes through global memory ordered by agent-scope release/acquire fences
 // at the barriers.
@@ -40,7 +43,8 @@ struct CholArgs {
   const int64_t* ko;
   int64_t* kout;
   int* flags;    // flags[0]: failing column (-1 = none) of the current block
-  double* dinv;  // kB x kB inverse of the current diagonal block
+  double* W;     // R_pre^{-1} (upper triangle of the k_o x k_o block), built alongside
+  int64_t ldw;
   cqrrpt_info_t* info;
   cq::GridBarrier bar;
   double cond_max;
@@ -48,12 +52,7 @@ struct CholArgs {
   bool record;        // write rank and failing column into info
 };
 
-CQ_INLINE bool chol_sync(const cq::GridBarrier& b) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  const bool ok = cq::grid_sync(b);
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return ok;
-}
+
 
 // 64 x 64 tile products on the matrix cores, operands staged in LDS as
 // [l][x] (l the contraction index, leading dimension kLd):
@@ -160,29 +159,47 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
   const int64_t ldg = a.ldg;
   double* Gm = a.G;
   int fail = -1;
+  // Grid barriers, numbered in the order every workgroup passes them.
+  unsigned nbar = 0;
+  auto arrive = [&]() -> unsigned {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    cq::grid_arrive(a.bar);
+    return ++nbar;
+  };
+  auto wait = [&](unsigned k) -> bool {
+    const bool ok = cq::grid_wait(a.bar, k);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!ok && tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
+    return ok;
+  };
 
-  // G[r0 + l][c0 + c] (zero past ko) into dst[l][c]: all 16 loads of a
-  // thread are issued before the first LDS store; addresses are clamped
-  // into the valid k_o x k_o block.
-  auto load_tile = [&](double* dst, int64_t r0, int64_t cc0) {
+  // Tile src[r0 + l][c0 + c] (zero past ko) into dst[l][c], or transposed
+  // into dst[c][l]: all 16 loads of a thread are issued before the first
+  // LDS store; addresses are clamped into the valid k_o x k_o block.
+  auto load_blk = [&](double* dst, const double* src, int64_t ld, int64_t r0, int64_t cc0,
+                      bool trans) {
     double v[kB * kB / kThreads];
 #pragma unroll
     for (int u = 0; u < kB * kB / kThreads; ++u) {
       const int e = tid + u * kThreads;
       const int64_t r = r0 + (e & (kB - 1));
       const int64_t c = cc0 + (e >> 6);
-      v[u] = Gm[(r < ko ? r : ko - 1) + (c < ko ? c : ko - 1) * ldg];
+      v[u] = src[(r < ko ? r : ko - 1) + (c < ko ? c : ko - 1) * ld];
     }
 #pragma unroll
     for (int u = 0; u < kB * kB / kThreads; ++u) {
       const int e = tid + u * kThreads;
       const int l = e & (kB - 1);
       const int c = e >> 6;
-      dst[l * kLd + c] = (r0 + l < ko && cc0 + c < ko) ? v[u] : 0.0;
+      dst[trans ? c * kLd + l : l * kLd + c] = (r0 + l < ko && cc0 + c < ko) ? v[u] : 0.0;
     }
   };
-  // G[r0 + i][c0 + j] at the accumulator positions of this lane (zero past ko).
-  auto load_acc = [&](int64_t r0, int64_t cc0, double (&t)[2][2][4]) {
+  auto load_tile = [&](double* dst, int64_t r0, int64_t cc0) {
+    load_blk(dst, Gm, ldg, r0, cc0, false);
+  };
+  // src[r0 + i][c0 + j] at the accumulator positions of this lane (zero past ko).
+  auto load_acc_from = [&](const double* src, int64_t ld, int64_t r0, int64_t cc0,
+                           double (&t)[2][2][4]) {
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -191,8 +208,11 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
         for (int r = 0; r < 4; ++r) {
           const int64_t i = r0 + 32 * wi + 16 * x + l16;
           const int64_t j = cc0 + 32 * wj + 16 * y + lq + 4 * r;
-          t[x][y][r] = Gm[(i < ko ? i : ko - 1) + (j < ko ? j : ko - 1) * ldg];
+          t[x][y][r] = (i < ko && j < ko) ? src[i + j * ld] : 0.0;
         }
+  };
+  auto load_acc = [&](int64_t r0, int64_t cc0, double (&t)[2][2][4]) {
+    load_acc_from(Gm, ldg, r0, cc0, t);
   };
 
   // Factor the diagonal block held in D (upper triangle; identity past ko)
@@ -211,8 +231,9 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
   // quarter of j updates a fixed number of slots (63, 48, 32, 16) with no
   // branches, so the LDS reads of a step can all be in flight together;
   // slots past row 63 hold values that are never used. The factor goes into
-  // G, W to a.dinv, the failing column (or -1) to a.flags[0]. After a
-  // failure wave 0 stops updating; W is then unused.
+  // G, W to the diagonal block of a.W, the failing column (or -1) to
+  // a.flags[0]. After a failure wave 0 stops updating; the columns of W
+  // past the failing one are then unused.
   auto factor_in_lds = [&](int64_t c0) __attribute__((always_inline)) {
     if (tid == 0) s_fail = -1;
     __syncthreads();
@@ -299,8 +320,10 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
     for (int e = tid; e < kB * kB; e += kThreads) {
       const int i = e & (kB - 1);
       const int j = e >> 6;
-      if (i <= j && c0 + i < ko && c0 + j < ko) Gm[(c0 + i) + (c0 + j) * ldg] = D[i * kLd + j];
-      a.dinv[i + j * kB] = YA[i * kLd + j];
+      if (c0 + i < ko && c0 + j < ko) {
+        if (i <= j) Gm[(c0 + i) + (c0 + j) * ldg] = D[i * kLd + j];
+        a.W[(c0 + i) + (c0 + j) * a.ldw] = YA[i * kLd + j];
+      }
     }
     if (tid == 0) cq::st_agent(&a.flags[0], s_fail);
   };
@@ -318,59 +341,45 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
     }
     factor_in_lds(0);
   }
-  if (!chol_sync(a.bar)) {
-    if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
-    return;
-  }
+  if (!wait(arrive())) return;
 
+  // W = R_pre^{-1} is built alongside, block column by block column: with
+  // Y[i, c] = sum_{i <= l < c} W[i, l] R[l, c] (held in a.W's tile (i, c)
+  // until column c is finished), block column c is W[i, c] = -Y[i, c] W_cc
+  // for i < c (W_cc = R_D^{-1} from the factorization), computed in step c's
+  // first phase; the second phase then adds W[i, c] R[c, c'] into Y[i, c']
+  // for i <= c < c' (R's block row c is ready by then). These tile products
+  // go to the workgroups other than 0, next to the trailing update.
   for (int jb = 0; jb < nblk; ++jb) {
     const int64_t c0 = (int64_t)jb * kB;
     fail = cq::ld_agent(&a.flags[0]);
-    if (fail >= 0) break;
     const int nrest = nblk - jb - 1;
-    if (nrest == 0) break;
+    const int64_t cn = c0 + kB;
 
-    // Phase 2a: block row of R_pre, R[block, p] = R_D^{-T} G[block, p], one
-    // task per tile column; each task overwrites only its own tile.
-    if (g < nrest) {
-      {
-        // W = R_D^{-1} as A[l][i] = W[l][i] (column-major in a.dinv).
-        double v[kB * kB / kThreads];
+    // W_jj = R_D^{-1} (diagonal block of a.W) into YA as A[l][i] = W[l][i].
+    auto load_w = [&]() { load_blk(YA, a.W, a.ldw, c0, c0, false); };
+    // Block row of R_pre, R[block, p] = R_D^{-T} G[block, p] (W_jj in YA),
+    // written over its own tile of G; with keep, also into D as [l][c].
+    auto block_row = [&](int p, bool keep) {
+      const int64_t cp = (int64_t)(jb + 1 + p) * kB;
+      __syncthreads();
+      load_tile(YB, c0, cp);
+      __syncthreads();
+      d4_t acc[2][2];
+      tile_atb(YA, YB, wi, wj, l16, lq, acc);
 #pragma unroll
-        for (int u = 0; u < kB * kB / kThreads; ++u) v[u] = a.dinv[tid + u * kThreads];
+      for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int u = 0; u < kB * kB / kThreads; ++u) {
-          const int e = tid + u * kThreads;
-          YA[(e & (kB - 1)) * kLd + (e >> 6)] = v[u];
-        }
-      }
-      for (int p = g; p < nrest; p += G) {
-        const int64_t cp = (int64_t)(jb + 1 + p) * kB;
-        __syncthreads();
-        load_tile(YB, c0, cp);
-        __syncthreads();
-        d4_t acc[2][2];
-        tile_atb(YA, YB, wi, wj, l16, lq, acc);
+        for (int y = 0; y < 2; ++y)
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int64_t i = c0 + 32 * wi + 16 * x + l16;
-              const int64_t j = cp + 32 * wj + 16 * y + lq + 4 * r;
-              if (i < ko && j < ko) Gm[i + j * ldg] = acc[x][y][r];
-            }
-      }
-    }
-    if (!chol_sync(a.bar)) {
-      if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
-      return;
-    }
-
-    // Phase 2b: trailing tiles (p, q), p <= q: G[p, q] -= R[block, p]^T R[block, q].
-    // Tile 0 is the next diagonal block: workgroup 0 updates it into LDS and
-    // factors it at once; the other tiles go to the other workgroups.
+          for (int r = 0; r < 4; ++r) {
+            const int il = 32 * wi + 16 * x + l16;
+            const int jl = 32 * wj + 16 * y + lq + 4 * r;
+            if (c0 + il < ko && cp + jl < ko) Gm[(c0 + il) + (cp + jl) * ldg] = acc[x][y][r];
+            if (keep) D[il * kLd + jl] = acc[x][y][r];
+          }
+    };
+    // Trailing tile t = (p, q), p <= q: G[p, q] -= R[block, p]^T R[block, q].
     const int ntr = nrest * (nrest + 1) / 2;
     auto trailing = [&](int t) {
       int q = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -399,23 +408,78 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
             if (i <= j && j < ko) Gm[i + j * ldg] = tg[x][y][r] - acc[x][y][r];
           }
     };
-    if (G > 1) {
-      for (int t = g; t < ntr; t += G - 1) {
-        if (g == 0) break;
-        trailing(t);
-      }
-    } else {
-      for (int t = 1; t < ntr; ++t) trailing(t);
-    }
-    if (g == 0) {
-      const int64_t cn = c0 + kB;
+    // W[i, jb] = -Y[i, jb] W_jj, over its own tile of a.W.
+    auto w_col = [&](int i) {
+      const int64_t ri = (int64_t)i * kB;
       __syncthreads();
-      load_tile(YA, c0, cn);
-      double tg[2][2][4];
-      load_acc(cn, cn, tg);
+      load_blk(YA, a.W, a.ldw, ri, c0, true);   // A[l][r] = Y[r][l]
+      load_blk(YB, a.W, a.ldw, c0, c0, false);  // B[l][c] = W_jj[l][c]
       __syncthreads();
       d4_t acc[2][2];
-      tile_atb(YA, YA, wi, wj, l16, lq, acc);
+      tile_atb(YA, YB, wi, wj, l16, lq, acc);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t i2 = ri + 32 * wi + 16 * x + l16;
+            const int64_t j2 = c0 + 32 * wj + 16 * y + lq + 4 * r;
+            if (i2 < ko && j2 < ko) a.W[i2 + j2 * a.ldw] = -acc[x][y][r];
+          }
+    };
+    // Y[i, cq] += W[i, jb] R[jb, cq] (i == jb: the first term, written).
+    auto y_update = [&](int i, int cq) {
+      const int64_t ri = (int64_t)i * kB;
+      const int64_t cc = (int64_t)cq * kB;
+      __syncthreads();
+      load_blk(YA, a.W, a.ldw, ri, c0, true);  // A[l][r] = W[i, jb][r][l]
+      load_tile(YB, c0, cc);                   // B[l][c] = R[jb, cq][l][c]
+      double tg[2][2][4];
+      if (i < jb) load_acc_from(a.W, a.ldw, ri, cc, tg);
+      __syncthreads();
+      d4_t acc[2][2];
+      tile_atb(YA, YB, wi, wj, l16, lq, acc);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t i2 = ri + 32 * wi + 16 * x + l16;
+            const int64_t j2 = cc + 32 * wj + 16 * y + lq + 4 * r;
+            if (i2 < ko && j2 < ko)
+              a.W[i2 + j2 * a.ldw] = (i < jb ? tg[x][y][r] : 0.0) + acc[x][y][r];
+          }
+    };
+
+    if (fail >= 0 || nrest == 0) {
+      // Last block, or block jb's factorization failed (its inverse is valid
+      // on the columns before the failing one): finish block column jb of W
+      // and stop.
+      for (int i = g; i < jb; i += G) w_col(i);
+      if (!wait(arrive())) return;
+      break;
+    }
+
+    if (g == 0) {
+      // Workgroup 0 owns the critical path: its block row tile p = 0 (W_jj
+      // is still in YA from its own factorization), then the next diagonal
+      // block G[next, next] - R[block, next]^T R[block, next] and its
+      // factorization, without waiting for the other workgroups' block
+      // rows (it only counts itself in at the middle barrier).
+      double tg[2][2][4];
+      load_acc(cn, cn, tg);
+      if (G == 1) load_w();  // YA held other tiles
+      block_row(0, true);
+      for (int p = G; p < nrest; p += G) block_row(p, false);
+      if (G == 1)
+        for (int i = 0; i < jb; ++i) w_col(i);
+      const unsigned mid = arrive();
+      __syncthreads();
+      d4_t acc[2][2];
+      tile_atb(D, D, wi, wj, l16, lq, acc);
+      __syncthreads();  // every wave is done reading D
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -432,11 +496,33 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
             D[i * kLd + j] = v;
           }
       factor_in_lds(cn);
+      if (G == 1) {
+        for (int t = 1; t < ntr; ++t) trailing(t);
+        for (int y = 0; y < (jb + 1) * nrest; ++y) y_update(y / nrest, jb + 1 + y % nrest);
+      }
+      if (!wait(mid)) return;
+    } else {
+      // Block rows p = g, g + G, ..., then the W tasks of block column jb
+      // (dealt after the block rows, round-robin over workgroups 1..G-1).
+      if (g < nrest) {
+        load_w();
+        for (int p = g; p < nrest; p += G) block_row(p, false);
+      }
+      for (int i = 0; i < jb; ++i)
+        if (1 + (nrest - 1 + i) % (G - 1) == g) w_col(i);
+      if (!wait(arrive())) return;
+      // Trailing tiles t >= 1, then the Y updates, round-robin.
+      const int ny = (jb + 1) * nrest;
+      for (int u = g; u < ntr + ny; u += G - 1) {
+        if (u < ntr) {
+          trailing(u);
+        } else {
+          const int y = u - ntr;
+          y_update(y / nrest, jb + 1 + y % nrest);
+        }
+      }
     }
-    if (!chol_sync(a.bar)) {
-      if (tid == 0) cq::set_status(a.info, CQRRPT_EBARRIER);
-      return;
-    }
+    if (!wait(arrive())) return;
   }
 
   // Second-stage rank on the (possibly truncated) factor.
@@ -649,12 +735,13 @@ namespace cqh {
 
 size_t chol_ws_bytes(int kmax) {
   (void)kmax;
-  return 256 + (size_t)kB * kB * 8;  // barrier words and flags, R_D^{-1}
+  return 256;  // barrier counter, abort word and flags
 }
 
 hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int kmax,
-                           int64_t* k_dev, void* ws, cqrrpt_info_t* info, hipStream_t s,
-                           double cond_max, bool record, const int* enable) {
+                           int64_t* k_dev, double* W, int64_t ldw, void* ws,
+                           cqrrpt_info_t* info, hipStream_t s, double cond_max, bool record,
+                           const int* enable) {
   (void)kmax;
   unsigned* w = static_cast<unsigned*>(ws);
   hipLaunchKernelGGL(chol_reset_kernel, dim3(1), dim3(64), 0, s, w, 8);
@@ -666,10 +753,10 @@ hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int km
   a.ko = ko_dev;
   a.kout = k_dev;
   a.flags = reinterpret_cast<int*>(w + 4);
-  a.dinv = reinterpret_cast<double*>(static_cast<char*>(ws) + 256);
+  a.W = W;
+  a.ldw = ldw;
   a.info = info;
   a.bar.count = w;
-  a.bar.gen = w + 1;
   a.bar.abort = reinterpret_cast<int*>(w + 2);
   a.cond_max = cond_max;
   a.record = record;

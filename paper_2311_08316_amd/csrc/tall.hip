@@ -353,6 +353,160 @@ hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX*
 }
 
 // ---------------------------------------------------------------------------
+// Q = M[:, :k] W[:k, :k] with W = R_pre^{-1} upper triangular (formed by the
+// Cholesky step): the Q-factor triangular solve of Algorithm 2 carried out
+// as a product with the inverse, which is accurate because R_pre is well
+// conditioned (it inherits the conditioning of M_pre, the preconditioned
+// matrix of Sec. 3). No substitution remains, so every block is a plain
+// matrix-core product. A workgroup owns kRT rows and walks the 128-column
+// panels from the last to the first, so M may alias Q: panel c reads the
+// columns below c + 128 only, which later (lower) panels have not written.
+// The K loop is the solve's (two register stages over double-buffered LDS);
+// a wave skips the K steps below its columns' diagonal. The accumulators
+// hold the transposed tile (rows on the N index), so the stores of 16
+// consecutive lanes cover 16 consecutive rows.
+// ---------------------------------------------------------------------------
+template <typename TM, typename TQ, typename TC>
+__global__ void __launch_bounds__(kTThreads, 2)
+qform_kernel(const TM* M, int64_t ldm, TQ* Q, int64_t ldq, const double* __restrict__ W,
+             int64_t ldw, int64_t m, const int64_t* kdev, const cqrrpt_info_t* info,
+             const int* enable) {
+  typedef typename MfmaAcc<TC>::type acc_t;
+  extern __shared__ unsigned char smem_raw[];
+  TC* lds = reinterpret_cast<TC*>(smem_raw);
+
+  if (info->status != 0 || (enable && *enable == 0)) return;
+  const int k = (int)*kdev;
+  if (k <= 0) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave & 1;
+  const int wc = __builtin_amdgcn_readfirstlane(wave >> 1);
+  const int l16 = lane & 15;
+  const int lq = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * kRT;
+  constexpr int kLoads = kKB * kRT / kTThreads;  // 8 per operand and step
+  const int ra = tid & (kRT - 1), ca = tid >> 7;
+  const int rb = tid & 15, cb = tid >> 4;
+  // Rows past m read row m-1 (in bounds); their results are never stored.
+  const int64_t rowa = row0 + ra < m ? row0 + ra : m - 1;
+  const uint32_t ldw32 = (uint32_t)ldw;
+
+  for (int c0 = ((k - 1) / kPW) * kPW; c0 >= 0; c0 -= kPW) {
+    int c0o = c0;
+    asm volatile("" : "+s"(c0o));
+    const int kend = k - c0o < kPW ? k : c0o + kPW;  // W[:, panel] is zero below row kend
+    const int nk = ((kend + 2 * kKB - 1) / (2 * kKB)) * 2;  // K steps, even
+    acc_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+    TM areg0[kLoads], areg1[kLoads];
+    double wreg0[kLoads], wreg1[kLoads];
+    // Columns of M past k read column k-1 and rows of W past k read row
+    // k-1 (in bounds); the W values are masked to zero when stored.
+    auto load = [&](int kk, TM (&ar)[kLoads], double (&wv)[kLoads]) {
+#pragma unroll
+      for (int q = 0; q < kLoads; ++q) {
+        const int col = kk + ca + 2 * q;
+        ar[q] = M[rowa + (int64_t)(col < k ? col : k - 1) * ldm];
+      }
+      const int wrow = kk + rb < k ? kk + rb : k - 1;
+#pragma unroll
+      for (int q = 0; q < kLoads; ++q) {
+        const int col = c0o + cb + 16 * q;
+        wv[q] = W[(uint32_t)wrow + (uint32_t)(col < k ? col : k - 1) * ldw32];
+      }
+    };
+    auto store = [&](int buf, int kk, const TM (&ar)[kLoads], const double (&wv)[kLoads]) {
+      TC* At = lds + buf * 2 * kTileSz;
+      TC* Wt = At + kTileSz;
+#pragma unroll
+      for (int q = 0; q < kLoads; ++q) At[(ca + 2 * q) * kSLd + ra] = (TC)ar[q];
+      const int wrow = kk + rb;
+#pragma unroll
+      for (int q = 0; q < kLoads; ++q) {
+        const int col = c0o + cb + 16 * q;
+        Wt[rb * kSLd + cb + 16 * q] = (wrow <= col && col < k) ? (TC)wv[q] : (TC)0;
+      }
+    };
+    // K step kk is above this wave's columns' diagonal block only while kk
+    // is below c0 + 64 (wc + 1); later steps meet zeros of W.
+    const int kwave = c0o + 64 * (wc + 1);
+    auto multiply = [&](int buf, int kk) {
+      if (kk >= kwave) return;
+      const TC* At = lds + buf * 2 * kTileSz;
+      const TC* Wt = At + kTileSz;
+#pragma unroll
+      for (int s = 0; s < kKB / 4; ++s) {
+        TC af[4], bf[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) af[a] = At[(4 * s + lq) * kSLd + 64 * wr + 16 * a + l16];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bf[b] = Wt[(4 * s + lq) * kSLd + 64 * wc + 16 * b + l16];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = mfma(bf[b], af[a], acc[a][b]);
+      }
+    };
+    load(0, areg0, wreg0);
+    load(kKB, areg1, wreg1);
+    __syncthreads();  // the previous panel's readers are done with LDS
+    store(0, 0, areg0, wreg0);
+    __syncthreads();
+    for (int it = 0; it < nk; it += 2) {
+      int ito = it;
+      asm volatile("" : "+s"(ito));
+      // Step it is in LDS buffer 0, step it + 1 in registers 1.
+      if (ito + 2 < nk) load((ito + 2) * kKB, areg0, wreg0);
+      multiply(0, ito * kKB);
+      store(1, (ito + 1) * kKB, areg1, wreg1);
+      __syncthreads();
+      // Step it + 1 is in LDS buffer 1, step it + 2 in registers 0.
+      if (ito + 3 < nk) load((ito + 3) * kKB, areg1, wreg1);
+      multiply(1, (ito + 1) * kKB);
+      if (ito + 2 < nk) store(0, (ito + 2) * kKB, areg0, wreg0);
+      __syncthreads();
+    }
+    // acc[a][b] register r: row 64 wr + 16 a + l16, column 64 wc + 16 b +
+    // acc_row(lq, r) of the panel.
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int64_t row = row0 + 64 * wr + 16 * a + l16;
+      if (row < m) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int col = c0o + 64 * wc + 16 * b + acc_row<TC>(lq, r);
+            if (col < k) Q[row + (int64_t)col * ldq] = (TQ)acc[a][b][r];
+          }
+      }
+    }
+  }
+}
+
+template <typename TM, typename TQ, typename TC>
+hipError_t launch_qform_impl(const TM* M, int64_t ldm, TQ* Q, int64_t ldq, const double* W,
+                             int64_t ldw, int64_t m, const int64_t* kdev,
+                             const cqrrpt_info_t* info, const int* enable, hipStream_t s) {
+  const size_t lds = (size_t)kTrsmLds * sizeof(TC);
+  // W is addressed with 32-bit element offsets.
+  if (ldw <= 0 || (uint64_t)ldw * 8192u > 0xffffffffull) return hipErrorInvalidValue;
+  const void* fn = (const void*)qform_kernel<TM, TQ, TC>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int64_t grid = (m + kRT - 1) / kRT;
+  hipLaunchKernelGGL((qform_kernel<TM, TQ, TC>), dim3((unsigned)grid), dim3(kTThreads), lds, s,
+                     M, ldm, Q, ldq, W, ldw, m, kdev, info, enable);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Gram G = X^T X (upper triangle), X m x k. Output tiles of 64 x 64, four
 // waves of 32 x 32, split over row ranges; each split writes its partial
 // tile, and a second kernel adds the splits in split order. The number of
@@ -558,6 +712,20 @@ hipError_t launch_trsm_f32in(const float* B, int64_t ldb, double* X, int64_t ldx
                              int kmax, double* pack, const cqrrpt_info_t* info, hipStream_t s) {
   return launch_trsm_impl<float, double, double>(B, ldb, nullptr, X, ldx, R, ldr, m, kdev, kmax,
                                                  pack, info, nullptr, s);
+}
+
+hipError_t launch_qform_f64(const double* M, int64_t ldm, double* Q, int64_t ldq,
+                            const double* W, int64_t ldw, int64_t m, const int64_t* kdev,
+                            const cqrrpt_info_t* info, hipStream_t s, const int* enable) {
+  return launch_qform_impl<double, double, double>(M, ldm, Q, ldq, W, ldw, m, kdev, info, enable,
+                                                   s);
+}
+
+hipError_t launch_qform_f32in(const float* M, int64_t ldm, double* Q, int64_t ldq,
+                              const double* W, int64_t ldw, int64_t m, const int64_t* kdev,
+                              const cqrrpt_info_t* info, hipStream_t s) {
+  return launch_qform_impl<float, double, double>(M, ldm, Q, ldq, W, ldw, m, kdev, info,
+                                                  nullptr, s);
 }
 
 // Splits: a multiple of the XCD count, at most 64, at least 1024 rows each,
