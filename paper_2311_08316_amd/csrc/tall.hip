@@ -52,13 +52,21 @@ constexpr int kPW = 128;        // panel width
 constexpr int kKB = 16;         // K per staging step
 constexpr int kSLd = 144;       // LDS row pitch: 128 + 16 keeps lane groups on distinct banks
 
-// LDS (units of TC): staging 2 x (X tile kKB x kRT, R tile kKB x kPW), each
-// row padded to kSLd; during the diagonal phase the same space holds the
-// tile of B (then T_t, then X_t; 16 x kRT, column-major), the R strip
-// (16 x kPW) and the accumulator tile (16 x kRT).
+// LDS (units of TC): staging 2 x (X tile kKB x kRT with rows padded to kSLd,
+// R tile kPW x kKB transposed with rows padded to kWLd); during the diagonal
+// phase the same space holds the tile of B (then T_t, then X_t; 16 x kRT,
+// column-major), the R strip (transposed, kPW x 16) and the accumulator
+// tile (16 x kRT).
 constexpr int kTileSz = kKB * kSLd;
-constexpr int kStageSz = 4 * kTileSz;
-constexpr int kTrsmLds = kStageSz;
+// Tiles of R (or W) are kept transposed, [column][K] with a pitch of kWLd:
+// the stores (K fastest across lanes, as loaded from the column-major
+// matrix) and the operand reads (K = lane / 16, column = lane % 16) then
+// spread over the banks; a [K][column] layout at a pitch of kSLd put the
+// stores on one bank in eight.
+constexpr int kWLd = 20;
+constexpr int kWTile = kPW * kWLd;
+constexpr int kQStage = kTileSz + kWTile;  // one staging buffer: B/X tile, then R tile
+constexpr int kTrsmLds = 2 * kQStage;
 // After the TC area: the panel's gathered column indices (int32).
 constexpr size_t kTrsmLdsBytes(size_t tc_bytes) { return kTrsmLds * tc_bytes + kPW * 4; }
 
@@ -123,8 +131,8 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
   extern __shared__ unsigned char smem_raw[];
   TC* lds = reinterpret_cast<TC*>(smem_raw);
   TC* Tt = lds;                // diagonal phase: B tile / T_t / X_t, [16][kSLd]
-  TC* Rs = lds + kTileSz;      // diagonal phase: R strip, [16][kSLd]
-  TC* Ta = lds + 2 * kTileSz;  // diagonal phase: accumulator tile, [16][kSLd]
+  TC* Rs = lds + kTileSz;               // diagonal phase: R strip, [kPW][kWLd]
+  TC* Ta = lds + kTileSz + kWTile;      // diagonal phase: accumulator tile, [16][kSLd]
   int* gcols = reinterpret_cast<int*>(lds + kTrsmLds);  // [kPW]
 
   if (info->status != 0 || (enable && *enable == 0)) return;
@@ -201,16 +209,16 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
         }
       };
       auto store = [&](int buf, const TX (&ar)[kLoads], const double (&rr)[kLoads]) {
-        TC* At = lds + buf * 2 * kTileSz;
+        TC* At = lds + buf * kQStage;
         TC* Rt = At + kTileSz;
 #pragma unroll
         for (int q = 0; q < kLoads; ++q) At[(ca + 2 * q) * kSLd + ra] = (TC)ar[q];
 #pragma unroll
         for (int q = 0; q < kLoads; ++q)
-          Rt[rb * kSLd + cb + 16 * q] = c0o + cb + 16 * q < k ? (TC)rr[q] : (TC)0;
+          Rt[(cb + 16 * q) * kWLd + rb] = c0o + cb + 16 * q < k ? (TC)rr[q] : (TC)0;
       };
       auto multiply = [&](int buf) {
-        const TC* At = lds + buf * 2 * kTileSz;
+        const TC* At = lds + buf * kQStage;
         const TC* Rt = At + kTileSz;
 #pragma unroll
         for (int s = 0; s < kKB / 4; ++s) {
@@ -218,7 +226,7 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
 #pragma unroll
           for (int a = 0; a < 4; ++a) af[a] = At[(4 * s + lq) * kSLd + 64 * wr + 16 * a + l16];
 #pragma unroll
-          for (int b = 0; b < 4; ++b) bf[b] = Rt[(4 * s + lq) * kSLd + 64 * wc + 16 * b + l16];
+          for (int b = 0; b < 4; ++b) bf[b] = Rt[(64 * wc + 16 * b + l16) * kWLd + 4 * s + lq];
 #pragma unroll
           for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -257,7 +265,7 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
       // columns of tile t and earlier).
 #pragma unroll
       for (int q = 0; q < kLoads; ++q) {
-        Rs[rb * kSLd + cb + 16 * q] =
+        Rs[(cb + 16 * q) * kWLd + rb] =
             r_entry<TC>(sreg[q], c0o + 16 * to + rb, c0o + cb + 16 * q, k);
         const int cl = 16 * to + ca + 2 * q;
         Tt[(ca + 2 * q) * kSLd + ra] = c0o + cl < k ? (TC)breg[q] : (TC)0;
@@ -319,7 +327,7 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             if (4 * wc + b > to) {
-              const TC bf = Rs[(4 * s + lq) * kSLd + 64 * wc + 16 * b + l16];
+              const TC bf = Rs[(64 * wc + 16 * b + l16) * kWLd + 4 * s + lq];
 #pragma unroll
               for (int a = 0; a < 4; ++a) acc[a][b] = mfma(af[a], bf, acc[a][b]);
             }
@@ -366,6 +374,8 @@ hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX*
 // hold the transposed tile (rows on the N index), so the stores of 16
 // consecutive lanes cover 16 consecutive rows.
 // ---------------------------------------------------------------------------
+constexpr int kQformLds = kTrsmLds;
+
 template <typename TM, typename TQ, typename TC>
 __global__ void __launch_bounds__(kTThreads, 2)
 qform_kernel(const TM* M, int64_t ldm, TQ* Q, int64_t ldq, const double* __restrict__ W,
@@ -421,8 +431,9 @@ qform_kernel(const TM* M, int64_t ldm, TQ* Q, int64_t ldq, const double* __restr
         wv[q] = W[(uint32_t)wrow + (uint32_t)(col < k ? col : k - 1) * ldw32];
       }
     };
+    // The W tile is kept transposed, [column][K] (pitch kWLd).
     auto store = [&](int buf, int kk, const TM (&ar)[kLoads], const double (&wv)[kLoads]) {
-      TC* At = lds + buf * 2 * kTileSz;
+      TC* At = lds + buf * kQStage;
       TC* Wt = At + kTileSz;
 #pragma unroll
       for (int q = 0; q < kLoads; ++q) At[(ca + 2 * q) * kSLd + ra] = (TC)ar[q];
@@ -430,7 +441,7 @@ qform_kernel(const TM* M, int64_t ldm, TQ* Q, int64_t ldq, const double* __restr
 #pragma unroll
       for (int q = 0; q < kLoads; ++q) {
         const int col = c0o + cb + 16 * q;
-        Wt[rb * kSLd + cb + 16 * q] = (wrow <= col && col < k) ? (TC)wv[q] : (TC)0;
+        Wt[(cb + 16 * q) * kWLd + rb] = (wrow <= col && col < k) ? (TC)wv[q] : (TC)0;
       }
     };
     // K step kk is above this wave's columns' diagonal block only while kk
@@ -438,7 +449,7 @@ qform_kernel(const TM* M, int64_t ldm, TQ* Q, int64_t ldq, const double* __restr
     const int kwave = c0o + 64 * (wc + 1);
     auto multiply = [&](int buf, int kk) {
       if (kk >= kwave) return;
-      const TC* At = lds + buf * 2 * kTileSz;
+      const TC* At = lds + buf * kQStage;
       const TC* Wt = At + kTileSz;
 #pragma unroll
       for (int s = 0; s < kKB / 4; ++s) {
@@ -446,7 +457,7 @@ qform_kernel(const TM* M, int64_t ldm, TQ* Q, int64_t ldq, const double* __restr
 #pragma unroll
         for (int a = 0; a < 4; ++a) af[a] = At[(4 * s + lq) * kSLd + 64 * wr + 16 * a + l16];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) bf[b] = Wt[(4 * s + lq) * kSLd + 64 * wc + 16 * b + l16];
+        for (int b = 0; b < 4; ++b) bf[b] = Wt[(64 * wc + 16 * b + l16) * kWLd + 4 * s + lq];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -494,7 +505,7 @@ template <typename TM, typename TQ, typename TC>
 hipError_t launch_qform_impl(const TM* M, int64_t ldm, TQ* Q, int64_t ldq, const double* W,
                              int64_t ldw, int64_t m, const int64_t* kdev,
                              const cqrrpt_info_t* info, const int* enable, hipStream_t s) {
-  const size_t lds = (size_t)kTrsmLds * sizeof(TC);
+  const size_t lds = (size_t)kQformLds * sizeof(TC);
   // W is addressed with 32-bit element offsets.
   if (ldw <= 0 || (uint64_t)ldw * 8192u > 0xffffffffull) return hipErrorInvalidValue;
   const void* fn = (const void*)qform_kernel<TM, TQ, TC>;
