@@ -348,9 +348,6 @@ hipError_t launch_trsm_mixed(const double* B, int64_t ldb, const int64_t* gather
                              int64_t ldx, const double* R, int64_t ldr, int64_t m,
                              const int64_t* kdev, int kmax, double* pack,
                              const cqrrpt_info_t* info, hipStream_t s);
-hipError_t launch_trsm_f32in(const float* B, int64_t ldb, double* X, int64_t ldx,
-                             const double* R, int64_t ldr, int64_t m, const int64_t* kdev,
-                             int kmax, double* pack, const cqrrpt_info_t* info, hipStream_t s);
 
 // Q[:, :k] = M[:, :k] W[:k, :k], W upper triangular (read above the
 // diagonal and on it only), 32-bit element offsets (ldw * 8192 < 2^32).

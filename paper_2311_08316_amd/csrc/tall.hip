@@ -718,13 +718,6 @@ hipError_t launch_trsm_mixed(const double* B, int64_t ldb, const int64_t* gather
                                                 pack, info, nullptr, s);
 }
 
-hipError_t launch_trsm_f32in(const float* B, int64_t ldb, double* X, int64_t ldx,
-                             const double* R, int64_t ldr, int64_t m, const int64_t* kdev,
-                             int kmax, double* pack, const cqrrpt_info_t* info, hipStream_t s) {
-  return launch_trsm_impl<float, double, double>(B, ldb, nullptr, X, ldx, R, ldr, m, kdev, kmax,
-                                                 pack, info, nullptr, s);
-}
-
 hipError_t launch_qform_f64(const double* M, int64_t ldm, double* Q, int64_t ldq,
                             const double* W, int64_t ldw, int64_t m, const int64_t* kdev,
                             const cqrrpt_info_t* info, hipStream_t s, const int* enable) {
