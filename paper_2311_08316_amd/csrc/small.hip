@@ -66,12 +66,8 @@ CQ_INLINE d4_t mfma64(double a, double b, d4_t c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-CQ_INLINE void tile_atb(const double* A, const double* B, int wi, int wj, int l16, int lq,
-                        d4_t (&acc)[2][2]) {
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = d4_t{0.0, 0.0, 0.0, 0.0};
+CQ_INLINE void tile_atb_add(const double* A, const double* B, int wi, int wj, int l16, int lq,
+                            d4_t (&acc)[2][2]) {
 #pragma unroll 4
   for (int s = 0; s < kB / 4; ++s) {
     const int l = 4 * s + lq;
@@ -85,6 +81,15 @@ CQ_INLINE void tile_atb(const double* A, const double* B, int wi, int wj, int l1
 #pragma unroll
       for (int y = 0; y < 2; ++y) acc[x][y] = mfma64(aj[y], bi[x], acc[x][y]);
   }
+}
+
+CQ_INLINE void tile_atb(const double* A, const double* B, int wi, int wj, int l16, int lq,
+                        d4_t (&acc)[2][2]) {
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4_t{0.0, 0.0, 0.0, 0.0};
+  tile_atb_add(A, B, wi, wj, l16, lq, acc);
 }
 
 typedef __attribute__((address_space(3))) const double lds_cdouble;
@@ -551,61 +556,80 @@ __global__ void chol_reset_kernel(unsigned* w, int nw) {
 
 // ---------------------------------------------------------------------------
 // R = R_pre[:k,:k] R_sk[:k,:], written as a full n x n array (zeros below the
-// diagonal and in rows >= k). 64 x 64 tiles, 4 x 4 outputs per thread.
+// diagonal and in rows >= k). One workgroup per 64 x 64 output tile (I, J);
+// tile products on the matrix cores over the 64-column blocks l = I..J (the
+// only ones where both triangular factors can be nonzero), the next block's
+// tiles loaded into registers while the current one is multiplied.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads)
 trmm_kernel(const double* __restrict__ P, int64_t ldp, const double* __restrict__ S, int64_t lds,
             double* __restrict__ R, int64_t ldr, int n, const int64_t* kdev, const int* enable) {
-  __shared__ double PA[32 * kLd];
-  __shared__ double SB[32 * kLd];
+  __shared__ double TA[kB * kLd];
+  __shared__ double TB[kB * kLd];
   if (enable && *enable == 0) return;
   const int64_t k = *kdev;
-  const int64_t i0 = (int64_t)blockIdx.x * kB;
-  const int64_t j0 = (int64_t)blockIdx.y * kB;
+  const int I = blockIdx.x, J = blockIdx.y;
+  const int64_t i0 = (int64_t)I * kB;
+  const int64_t j0 = (int64_t)J * kB;
   const int tid = threadIdx.x;
-  const int ti = tid >> 4;
-  const int tj = tid & 15;
-  double acc[4][4];
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int l16 = lane & 15;
+  const int lq = lane >> 4;
+  const int wi = wave & 1;
+  const int wj = wave >> 1;
+  constexpr int kPer = kB * kB / kThreads;
+  d4_t acc[2][2];
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-  if (i0 < k && i0 <= j0 + kB - 1) {
-    const int64_t lend = (j0 + kB) < k ? (j0 + kB) : k;
-    for (int64_t l0 = i0; l0 < lend; l0 += 32) {
-      for (int e = tid; e < 32 * kB; e += kThreads) {
-        const int ii = e & (kB - 1);
-        const int ll = e >> 6;
-        const int64_t i = i0 + ii;
-        const int64_t l = l0 + ll;
-        PA[ll * kLd + ii] = (i < k && l < lend && i <= l) ? P[i + l * ldp] : 0.0;
-        const int jj = e & (kB - 1);
-        const int64_t j = j0 + jj;
-        SB[ll * kLd + jj] = (l < lend && j < n) ? S[l + j * lds] : 0.0;
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4_t{0.0, 0.0, 0.0, 0.0};
+  if (i0 < k && I <= J) {
+    const int lb1 = J < (int)((k - 1) / kB) ? J : (int)((k - 1) / kB);
+    double pv[kPer], sv[kPer];
+    // Element e = tid + 256 u of a tile: row e & 63, column e >> 6. P rows
+    // and columns past k, and S rows past k or columns past n, read an
+    // in-bounds element and are stored as zero.
+    auto load = [&](int lb) {
+      const int64_t l0 = (int64_t)lb * kB;
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int e = tid + kThreads * u;
+        const int64_t r = e & (kB - 1), c = e >> 6;
+        const int64_t pi = i0 + r < k ? i0 + r : k - 1, pl = l0 + c < k ? l0 + c : k - 1;
+        pv[u] = P[pi + pl * ldp];
+        const int64_t sl = l0 + r < k ? l0 + r : k - 1, sj = j0 + c < n ? j0 + c : n - 1;
+        sv[u] = S[sl + sj * lds];
+      }
+    };
+    load(I);
+    for (int lb = I; lb <= lb1; ++lb) {
+      const int64_t l0 = (int64_t)lb * kB;
+      __syncthreads();  // the previous product is done with TA, TB
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int e = tid + kThreads * u;
+        const int r = e & (kB - 1), c = e >> 6;
+        // TA[l][i] = P[i][l] (upper triangle of the leading k x k block).
+        TA[c * kLd + r] = (i0 + r < k && l0 + c < k && i0 + r <= l0 + c) ? pv[u] : 0.0;
+        // TB[l][j] = S[l][j] (rows below k).
+        TB[r * kLd + c] = (l0 + r < k && j0 + c < n) ? sv[u] : 0.0;
       }
       __syncthreads();
-      for (int ll = 0; ll < 32; ++ll) {
-        double av[4], bv[4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x) av[x] = PA[ll * kLd + 4 * ti + x];
-#pragma unroll
-        for (int y = 0; y < 4; ++y) bv[y] = SB[ll * kLd + 4 * tj + y];
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] += av[x] * bv[y];
-      }
-      __syncthreads();
+      if (lb < lb1) load(lb + 1);
+      tile_atb_add(TA, TB, wi, wj, l16, lq, acc);
     }
   }
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int64_t i = i0 + 4 * ti + x;
-      const int64_t j = j0 + 4 * tj + y;
-      if (i < n && j < n) R[i + j * ldr] = (i < k && i <= j) ? acc[x][y] : 0.0;
-    }
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + 32 * wi + 16 * x + l16;
+        const int64_t j = j0 + 32 * wj + 16 * y + lq + 4 * r;
+        if (i < n && j < n) R[i + j * ldr] = (i < k && i <= j) ? acc[x][y][r] : 0.0;
+      }
 }
 
 // ---------------------------------------------------------------------------
