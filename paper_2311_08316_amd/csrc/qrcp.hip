@@ -702,7 +702,19 @@ rank1_rows_kernel(const double* __restrict__ R, int64_t ldr, int n, double* rn2,
   const int i = blockIdx.x * 64 + lane;
   double s = 0.0, mx = 0.0;
   if (i < n) {
-    for (int j = i + wave; j < n; j += kWaves) {
+    // Eight loads in flight per lane; the additions keep their order.
+    int j = i + wave;
+    for (; j + 7 * kWaves < n; j += 8 * kWaves) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = R[i + (int64_t)(j + u * kWaves) * ldr];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        s += v[u] * v[u];
+        mx = fmax(mx, fabs(v[u]));
+      }
+    }
+    for (; j < n; j += kWaves) {
       const double v = R[i + (int64_t)j * ldr];
       s += v * v;
       mx = fmax(mx, fabs(v));
