@@ -24,6 +24,7 @@
 // G is overwritten by R_pre in place (upper triangle). Cross-workgroup data
 // goes through global memory ordered by agent-scope release/acquire fences
 // at the barriers.
+#include <limits.h>
 #include <math.h>
 
 #include <type_traits>
@@ -530,22 +531,75 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
     if (!wait(arrive())) return;
   }
 
-  // Second-stage rank on the (possibly truncated) factor.
-  if (g == 0 && tid == 0) {
+  // Second-stage rank on the (possibly truncated) factor: k is one less than
+  // the first l whose leading l x l block has max|diag| / min|diag| above
+  // cond_max (kc if there is none). Workgroup 0 takes |diag| 4 * kThreads at a
+  // time, 4 consecutive entries per thread, and forms each entry's prefix max
+  // and min from a scan over the threads; max and min are exact in any order,
+  // so every ratio is the one the sequential definition divides.
+  if (g == 0) {
     const int64_t kc = fail >= 0 ? fail : ko;
-    int64_t k = 0;
-    double dmax = 0.0, dmin = INFINITY;
-    for (int64_t l = 1; l <= kc; ++l) {
-      const double v = fabs(Gm[(l - 1) + (l - 1) * ldg]);
-      dmax = fmax(dmax, v);
-      dmin = fmin(dmin, v);
-      if (dmax / dmin <= a.cond_max) k = l;
-      else break;
+    double* smax = YA;
+    double* smin = YB;
+    __shared__ int s_bad;
+    if (tid == 0) s_bad = INT_MAX;
+    double cmax = 0.0, cmin = INFINITY;  // over the chunks already done
+    for (int64_t base = 0; base < kc; base += 4 * kThreads) {
+      double v[4];
+      double lmax = 0.0, lmin = INFINITY;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t l = base + 4 * tid + u;
+        v[u] = l < kc ? fabs(Gm[l + l * ldg]) : 0.0;
+        if (l < kc) {
+          lmax = fmax(lmax, v[u]);
+          lmin = fmin(lmin, v[u]);
+        }
+      }
+      // Inclusive scan of (max, min) over the threads.
+      for (int off = 1; off < kThreads; off <<= 1) {
+        __syncthreads();
+        smax[tid] = lmax;
+        smin[tid] = lmin;
+        __syncthreads();
+        if (tid >= off) {
+          lmax = fmax(lmax, smax[tid - off]);
+          lmin = fmin(lmin, smin[tid - off]);
+        }
+      }
+      __syncthreads();
+      smax[tid] = lmax;
+      smin[tid] = lmin;
+      __syncthreads();
+      double pmax = cmax, pmin = cmin;
+      if (tid > 0) {
+        pmax = fmax(pmax, smax[tid - 1]);
+        pmin = fmin(pmin, smin[tid - 1]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t l = base + 4 * tid + u;
+        if (l < kc) {
+          pmax = fmax(pmax, v[u]);
+          pmin = fmin(pmin, v[u]);
+          if (!(pmax / pmin <= a.cond_max)) {
+            atomicMin(&s_bad, (int)l);
+            break;
+          }
+        }
+      }
+      cmax = fmax(cmax, smax[kThreads - 1]);
+      cmin = fmin(cmin, smin[kThreads - 1]);
+      __syncthreads();
+      if (s_bad != INT_MAX) break;
     }
-    a.kout[0] = k;
-    if (a.record) {
-      a.info->rank = k;
-      a.info->chol_fail_col = fail >= 0 ? fail : -1;
+    if (tid == 0) {
+      const int64_t k = s_bad != INT_MAX ? (int64_t)s_bad : kc;
+      a.kout[0] = k;
+      if (a.record) {
+        a.info->rank = k;
+        a.info->chol_fail_col = fail >= 0 ? fail : -1;
+      }
     }
   }
 }
