@@ -23,6 +23,13 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]
+# Per-source options. In the tall kernels the matrix-core accumulators stay in
+# ordinary vector registers (the instructions' VGPR form): with accumulation
+# registers the compiler copied every accumulator in and out of them around
+# code that reads the sums (the Gram's compensated fold).
+EXTRA = {
+    "tall.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+}
 
 
 def _hipcc():
@@ -31,7 +38,8 @@ def _hipcc():
 
 
 def _compile(src, obj):
-    cmd = [_hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
+    cmd = [_hipcc(), *FLAGS, *EXTRA.get(os.path.basename(src), []), "-I",
+           os.path.join(ROOT, "include"), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {os.path.basename(src)}:\n{r.stderr}")
