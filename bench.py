@@ -83,9 +83,9 @@ def quality(torch, A, f, k):
 
 
 def run_mode(P, torch, A, w, mode, tol, seed, steps, warmup, want_stages=True,
-             want_quality=True):
+             want_quality=True, implicit=False):
     m, n, d, nnz = w["m"], w["n"], w["d"], w["nnz"]
-    f = P.Factorization(m, n, d, nnz, mode)
+    f = P.Factorization(m, n, d, nnz, mode, implicit=implicit)
     for _ in range(warmup):
         f.run(A, seed, tol)
     torch.cuda.synchronize()
@@ -296,6 +296,16 @@ def main():
             "gflops_2mn2": pr["gflops"], "ms_per_step": pr["ms"], "p50_ms": pr["p50"],
             "p99_ms": pr["p99"], "rank": pr["rank"], "orth": pr["orth"], "recon": pr["recon"]}
         log(f"planted-rank run: {extra['planted_rank_tol1e-9']}")
+        # Implicit Q (M_pre and R_pre returned, Q solve skipped) on the same
+        # input; its correctness is covered by the parity tests.
+        ir = run_mode(P, torch, A, w, P.CQRRPT_FP64, tol, args.seed, steps2, 1,
+                      want_quality=False, implicit=True)
+        extra["implicit_q_tol1e-14"] = {
+            "gflops_2mn2": ir["gflops"], "ms_per_step": ir["ms"], "p50_ms": ir["p50"],
+            "p99_ms": ir["p99"], "rank": ir["rank"],
+            "speedup_vs_explicit": main_res["ms"] / ir["ms"], "stages_ms": ir["stages"]}
+        log(f"implicit-Q run: {extra['implicit_q_tol1e-14']}")
+        del ir
         # Mixed precision is measured on its own workload (1048576 x 512,
         # cond 1e10, full rank) next to FP64 on the same matrix.
         try:

@@ -173,6 +173,32 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n,
                      void* ws, size_t ws_bytes, void* stream,
                      cqrrpt_info_t* info);
 
+/* Implicit Q (Sec. 2.1, arithmetic complexity paragraph): Q is returned as
+ * the composition of M_pre and R_pre^{-1}, which skips the Q solve (the
+ * leading cost drops from 3mn^2 to 2mn^2; stability is unchanged).
+ * Same pipeline and workspace as cqrrpt_factor_ex in CQRRPT_FP64 mode
+ * (ws_bytes >= cqrrpt_workspace_bytes(m, n, d, nnz, CQRRPT_FP64)), with
+ * k = info->rank:
+ * M:    m x n output (ldm >= m): M[:, :k] = M_pre[:, :k] = A[:, J[:k]] R_sk[:k,:k]^{-1},
+ *       M[:, k:] = 0.
+ * Rpre: n x n output (ldrp >= n): Rpre[:k, :k] = R_pre[:k, :k], upper
+ *       triangular with a positive diagonal; zero elsewhere. The explicit
+ *       factor is Q[:, :k] = M[:, :k] Rpre[:k, :k]^{-1}.
+ * R, J, info: as in cqrrpt_factor_ex (R = R_pre[:k,:k] R_sk[:k, :]).
+ * All pointers are device pointers owned by the caller; stream-ordered, no
+ * allocation, no host synchronisation.
+ * Argument order: A lda m n d nnz seed tol M ldm Rpre ldrp R ldr J ws
+ * ws_bytes stream info.
+ * Errors (nothing is launched): -1..-8 as cqrrpt_factor_ex, -9 M NULL,
+ * -10 ldm < m, -11 Rpre NULL, -12 ldrp < n, -13 R NULL, -14 ldr < n,
+ * -15 J NULL, -16 ws NULL, -19 info NULL, CQRRPT_ELIMIT, CQRRPT_EWORKSPACE. */
+int cqrrpt_factor_implicit_ex(const double* A, int64_t lda, int64_t m, int64_t n,
+                              int64_t d, int32_t nnz, uint64_t seed, double tol,
+                              double* M, int64_t ldm, double* Rpre, int64_t ldrp,
+                              double* R, int64_t ldr, int64_t* J,
+                              void* ws, size_t ws_bytes, void* stream,
+                              cqrrpt_info_t* info);
+
 /* ------------------------------------------------------------------------
  * Stage timing (diagnostics)
  * ------------------------------------------------------------------------

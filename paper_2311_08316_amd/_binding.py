@@ -55,6 +55,9 @@ _SIGS = {
     "cqrrpt_factor_ex": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i32, _u64, _dbl,
                                         _vp, _i64, _vp, _i64, _vp, ctypes.c_int,
                                         _vp, _sz, _vp, _vp]),
+    "cqrrpt_factor_implicit_ex": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i32, _u64,
+                                                 _dbl, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
+                                                 _vp, _sz, _vp, _vp]),
     "cqrrpt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "cqrrpt_stage_timing": (ctypes.c_int, [ctypes.c_int]),
     "cqrrpt_stage_times": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
@@ -189,10 +192,18 @@ def workspace_bytes(m, n, d, nnz, mode=CQRRPT_FP64):
 class Factorization:
     """Preallocated outputs and workspace for repeated stream-ordered calls."""
 
-    def __init__(self, m, n, d, nnz, mode=CQRRPT_FP64, device="cuda"):
+    def __init__(self, m, n, d, nnz, mode=CQRRPT_FP64, device="cuda", implicit=False):
+        """With implicit=True (FP64 only) ``run`` calls
+        ``cqrrpt_factor_implicit_ex``: Q then holds M_pre[:, :k] and Rpre
+        holds R_pre[:k, :k], so that the orthonormal factor is
+        Q[:, :k] Rpre[:k, :k]^{-1}."""
+        if implicit and mode != CQRRPT_FP64:
+            raise CqrrptError("the implicit-Q form is FP64 only")
         self.m, self.n, self.d, self.nnz, self.mode = m, n, d, nnz, mode
+        self.implicit = implicit
         self.device = torch.device(device)
         self.Q = empty_colmajor(m, n, self.device)
+        self.Rpre = empty_colmajor(n, n, self.device) if implicit else None
         self.R = empty_colmajor(n, n, self.device)
         self.J = torch.empty(n, dtype=torch.int64, device=self.device)
         self.ws_bytes = workspace_bytes(m, n, d, nnz, mode)
@@ -208,6 +219,14 @@ class Factorization:
             raise CqrrptError("A has the wrong shape")
         s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else \
             _stream_handle(self.device)
+        if self.implicit:
+            rc = lib().cqrrpt_factor_implicit_ex(
+                A.data_ptr(), _ld(A), self.m, self.n, self.d, self.nnz, seed, tol,
+                self.Q.data_ptr(), self.m, self.Rpre.data_ptr(), self.n, self.R.data_ptr(),
+                self.n, self.J.data_ptr(), self.ws.data_ptr(), self.ws_bytes, s,
+                self.info_buf.data_ptr())
+            _check(rc, "cqrrpt_factor_implicit_ex")
+            return
         rc = lib().cqrrpt_factor_ex(A.data_ptr(), _ld(A), self.m, self.n, self.d, self.nnz,
                                     seed, tol, self.Q.data_ptr(), self.m, self.R.data_ptr(),
                                     self.n, self.J.data_ptr(), self.mode, self.ws.data_ptr(),
@@ -231,6 +250,19 @@ def factor(A, d, nnz, seed, tol, mode=CQRRPT_FP64):
     if info.status != 0:
         _check(info.status, "cqrrpt_factor_ex")
     return f.Q, f.R, f.J, info
+
+
+def factor_implicit(A, d, nnz, seed, tol):
+    """Implicit-Q factorization: returns (M, Rpre, R, J, info) with
+    Q[:, :k] = M[:, :k] Rpre[:k, :k]^{-1} (k = info.rank)."""
+    A = colmajor(A)
+    m, n = A.shape
+    f = Factorization(m, n, d, nnz, CQRRPT_FP64, A.device, implicit=True)
+    f.run(A, seed, tol)
+    info = f.info()
+    if info.status != 0:
+        _check(info.status, "cqrrpt_factor_implicit_ex")
+    return f.Q, f.Rpre, f.R, f.J, info
 
 
 def factor_sync(A, d, nnz, seed, tol):

@@ -279,20 +279,18 @@ size_t cqrrpt_workspace_bytes(int64_t m, int64_t n, int64_t d, int32_t nnz, cqrr
   return make_layout(m, n, d, nnz, mode).total;
 }
 
-int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, int32_t nnz,
-                     uint64_t seed, double tol, double* Q, int64_t ldq, double* R, int64_t ldr,
-                     int64_t* J, cqrrpt_mode_t mode, void* ws, size_t ws_bytes, void* stream,
-                     cqrrpt_info_t* info) {
-  const int c = check_common(A, lda, m, n, d, nnz, tol);
-  if (c) return c;
-  if (!Q) return -9;
-  if (ldq < m) return -10;
-  if (!R) return -11;
-  if (ldr < n) return -12;
-  if (!J) return -13;
-  if (mode != CQRRPT_FP64 && mode != CQRRPT_MIXED && mode != CQRRPT_MIXED_CHECKED) return -14;
-  if (!ws) return -15;
-  if (!info) return -18;
+}  // extern "C"
+
+namespace {
+
+// The factorization on validated arguments. With Rpre == nullptr (explicit
+// Q) the Q buffer receives Q; otherwise (FP64 only) it keeps M_pre[:, :k],
+// the Q solve is skipped and Rpre receives R_pre[:k, :k]: the implicit
+// representation Q = M_pre R_pre^{-1} (Sec. 2.1, arithmetic complexity).
+int factor_core(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, int32_t nnz,
+                uint64_t seed, double tol, double* Q, int64_t ldq, double* R, int64_t ldr,
+                int64_t* J, cqrrpt_mode_t mode, void* ws, size_t ws_bytes, void* stream,
+                cqrrpt_info_t* info, double* Rpre, int64_t ldrp) {
   if (n > kMaxN || d > kMaxD || !cqh::sketch_fits((int)d, nnz)) return CQRRPT_ELIMIT;
   const Layout L = make_layout(m, n, d, nnz, mode);
   if (ws_bytes < L.total) return CQRRPT_EWORKSPACE;
@@ -344,7 +342,9 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
                               mode == CQRRPT_FP64 ? kStage2CondFp64 : kStage2CondMixed));
   mk.mark(6);
   // S9: Q = M_pre[:, :k] R_pre^{-1}, as the product with Winv[:k, :k].
-  if (mode == CQRRPT_FP64) {
+  if (Rpre) {
+    // Implicit Q: M_pre stays.
+  } else if (mode == CQRRPT_FP64) {
     CQ_TRY(cqh::launch_qform_f64(Q, ldq, Q, ldq, Winv, n, m, k_dev, info, s));
   } else {
     float* M32 = reinterpret_cast<float*>(base + L.off_mpre32);
@@ -354,6 +354,7 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
   // S10: R = R_pre R_sk[:k, :]; zero Q past the rank.
   CQ_TRY(cqh::launch_trmm_r(G, n, Rsk, n, R, ldr, ni, k_dev, s));
   CQ_TRY(cqh::launch_zero_cols(Q, ldq, m, ni, k_dev, s));
+  if (Rpre) CQ_TRY(cqh::launch_copy_upper(G, n, Rpre, ldrp, ni, k_dev, s));
   mk.mark(8);
   if (mode == CQRRPT_MIXED_CHECKED) {
     // S11: adaptive CholeskyQR2 pass, decided on the device. G2 = Q^T Q
@@ -374,6 +375,47 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
   }
   mk.mark(9);
   return CQRRPT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, int32_t nnz,
+                     uint64_t seed, double tol, double* Q, int64_t ldq, double* R, int64_t ldr,
+                     int64_t* J, cqrrpt_mode_t mode, void* ws, size_t ws_bytes, void* stream,
+                     cqrrpt_info_t* info) {
+  const int c = check_common(A, lda, m, n, d, nnz, tol);
+  if (c) return c;
+  if (!Q) return -9;
+  if (ldq < m) return -10;
+  if (!R) return -11;
+  if (ldr < n) return -12;
+  if (!J) return -13;
+  if (mode != CQRRPT_FP64 && mode != CQRRPT_MIXED && mode != CQRRPT_MIXED_CHECKED) return -14;
+  if (!ws) return -15;
+  if (!info) return -18;
+  return factor_core(A, lda, m, n, d, nnz, seed, tol, Q, ldq, R, ldr, J, mode, ws, ws_bytes,
+                     stream, info, nullptr, 0);
+}
+
+int cqrrpt_factor_implicit_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d,
+                              int32_t nnz, uint64_t seed, double tol, double* M, int64_t ldm,
+                              double* Rpre, int64_t ldrp, double* R, int64_t ldr, int64_t* J,
+                              void* ws, size_t ws_bytes, void* stream, cqrrpt_info_t* info) {
+  const int c = check_common(A, lda, m, n, d, nnz, tol);
+  if (c) return c;
+  if (!M) return -9;
+  if (ldm < m) return -10;
+  if (!Rpre) return -11;
+  if (ldrp < n) return -12;
+  if (!R) return -13;
+  if (ldr < n) return -14;
+  if (!J) return -15;
+  if (!ws) return -16;
+  if (!info) return -19;
+  return factor_core(A, lda, m, n, d, nnz, seed, tol, M, ldm, R, ldr, J, CQRRPT_FP64, ws,
+                     ws_bytes, stream, info, Rpre, ldrp);
 }
 
 int cqrrpt_factor(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, int32_t nnz,

@@ -393,5 +393,8 @@ hipError_t launch_cholqr2_commit(const int* pass, const int64_t* k_dev, const in
                                  int64_t ldc, int n, cqrrpt_info_t* info, hipStream_t s);
 hipError_t launch_zero_cols(double* Q, int64_t ldq, int64_t m, int n, const int64_t* kdev,
                             hipStream_t s);
+// out[:k, :k] = upper triangle of G[:k, :k], zero elsewhere in the n x n out.
+hipError_t launch_copy_upper(const double* G, int64_t ldg, double* out, int64_t ldo, int n,
+                             const int64_t* kdev, hipStream_t s);
 
 }  // namespace cqh

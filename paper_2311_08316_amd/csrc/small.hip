@@ -807,6 +807,18 @@ zero_cols_kernel(double* Q, int64_t ldq, int64_t m, int n, const int64_t* kdev) 
     col[r] = 0.0;
 }
 
+// Leading k x k block of R_pre (upper triangle of G after the Cholesky step)
+// into an n x n output, zero below the diagonal and outside the block. One
+// workgroup per output column.
+__global__ void __launch_bounds__(kThreads)
+copy_upper_kernel(const double* __restrict__ G, int64_t ldg, double* __restrict__ out,
+                  int64_t ldo, int n, const int64_t* kdev) {
+  const int64_t j = blockIdx.x;
+  const int64_t k = *kdev;
+  for (int64_t i = threadIdx.x; i < n; i += kThreads)
+    out[i + j * ldo] = (i <= j && j < k) ? G[i + j * ldg] : 0.0;
+}
+
 }  // namespace
 
 namespace cqh {
@@ -902,6 +914,13 @@ hipError_t launch_zero_cols(double* Q, int64_t ldq, int64_t m, int n, const int6
   if (gx > 64) gx = 64;
   hipLaunchKernelGGL(zero_cols_kernel, dim3((unsigned)gx, n), dim3(kThreads), 0, s, Q, ldq, m, n,
                      kdev);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_upper(const double* G, int64_t ldg, double* out, int64_t ldo, int n,
+                             const int64_t* kdev, hipStream_t s) {
+  hipLaunchKernelGGL(copy_upper_kernel, dim3((unsigned)n), dim3(kThreads), 0, s, G, ldg, out, ldo,
+                     n, kdev);
   return hipGetLastError();
 }
 

@@ -247,6 +247,73 @@ def test_factor_deterministic_and_sync_entry(P):
     assert np.array_equal(Q1, to_np(Q2)) and np.array_equal(R1, to_np(R2))
 
 
+IMPLICIT_CASES = [
+    # label, m, n, d, nnz, spectrum kind, cond, tol (the planted and failing
+    # cases truncate the rank below the first-stage one)
+    ("implicit-c1-like", 3000, 60, 75, 4, "log", 1e6, 1e-14),
+    ("implicit-tiles-and-tail", 20003, 200, 250, 8, "log", 1e8, 1e-14),
+    ("implicit-planted", 6000, 96, 120, 8, "planted", 1e3, 1e-11),
+    ("implicit-cholesky-failure", 8000, 128, 128, 1, "coherent", 1e10, 1e-14),
+]
+
+
+@pytest.mark.parametrize("label,m,n,d,nnz,kind,cond,tol", IMPLICIT_CASES)
+def test_factor_implicit_q(P, label, m, n, d, nnz, kind, cond, tol):
+    """Implicit Q (Sec. 2.1, arithmetic complexity): M = M_pre[:, :k] and
+    Rpre = R_pre[:k, :k] against the oracle's, R and J bit-identical to the
+    explicit call, and Q = M Rpre^{-1} (formed here on the host) matching
+    the explicit Q with the same orthogonality and reconstruction bars.
+    M_pre and R_pre are each formed through the solve with R_sk, so each
+    carries a forward error of order u cond(R_sk) (a GPU and an oracle
+    M_pre differ by rounding amplified that way); only their combination,
+    Q = M_pre R_pre^{-1} and R = R_pre R_sk, is accurate to the FP64 bars.
+    Both therefore take the bound used for Q."""
+    import scipy.linalg
+    say(f"factor implicit {label} m={m} n={n} d={d} nnz={nnz}")
+    if kind == "planted":
+        sv = np.zeros(n)
+        sv[:40] = W.logspaced_spectrum(40, cond)
+        A = W.spectrum_matrix(m, n, sv, seed=3)
+    elif kind == "coherent":
+        A = W.high_coherence_matrix(m, n, 4, boost=cond)
+    else:
+        A = W.spectrum_matrix(m, n, W.logspaced_spectrum(n, cond), seed=m % 97)
+    orc = O.cqrrpt(A, d, nnz, seed=5 if kind == "log" else 0, tol=tol)
+    seed = 5 if kind == "log" else 0
+    Ag = to_gpu(A)
+    Mg, Rpg, Rg, Jg, info = P.factor_implicit(Ag, d, nnz, seed, tol)
+    Qe, Re, Je, info_e = P.factor(Ag, d, nnz, seed, tol)
+    Mg, Rpg, Rg, Jg = to_np(Mg), to_np(Rpg), to_np(Rg), to_np(Jg)
+    k = orc["rank"]
+    assert info.rank == k == info_e.rank, f"{label}: rank {info.rank} vs {k}"
+    # Pivots past the rank pick among noise-level columns (not unique): the
+    # leading k must match the oracle, all of them the explicit call's.
+    assert np.array_equal(Jg[:k], orc["J"][:k]) and np.array_equal(Jg, to_np(Je))
+    assert np.array_equal(np.sort(Jg), np.arange(n))
+    assert np.array_equal(Rg, to_np(Re)), f"{label}: R differs from the explicit call"
+    assert not Mg[:, k:].any()
+    assert not Rpg[k:, :].any() and not Rpg[:, k:].any()
+    assert np.array_equal(Rpg, np.triu(Rpg)) and np.all(np.diag(Rpg)[:k] > 0)
+    Rpo, Mpo = orc["Rpre"], orc["Mpre"][:, :k]
+    kap = np.linalg.cond(orc["R"][:k, :k])
+    bound = max(1e-12, 100 * U64 * kap)
+    dRp = np.linalg.norm(Rpg[:k, :k] - Rpo) / np.linalg.norm(Rpo)
+    assert dRp <= bound, f"{label}: dRpre {dRp:.3e} (cond {kap:.2e})"
+    dM = np.linalg.norm(Mg[:, :k] - Mpo) / np.linalg.norm(Mpo)
+    assert dM <= bound, f"{label}: dM {dM:.3e} (cond {kap:.2e})"
+    Qi = np.zeros_like(Mg)
+    Qi[:, :k] = scipy.linalg.solve_triangular(Rpg[:k, :k], Mg[:, :k].T, trans="T",
+                                              lower=False).T
+    dQ = np.linalg.norm(Qi - to_np(Qe)) / np.linalg.norm(to_np(Qe))
+    assert dQ <= bound, f"{label}: implicit vs explicit Q {dQ:.3e}"
+    recon, orth = metrics(A, Qi, Rg, Jg, k)
+    recon_o, _ = metrics(A, orc["Q"], orc["R"], orc["J"], k)
+    assert recon <= max(1e-12, recon_o * (1 + 1e-6)), f"{label}: recon {recon:.3e}"
+    assert orth <= 1e-12, f"{label}: orth {orth:.3e}"
+    say(f"  {label}: rank {k} dRpre {dRp:.2e} dM {dM:.2e} dQ {dQ:.2e} recon {recon:.2e} "
+        f"orth {orth:.2e}")
+
+
 # ---------------------------------------------------------------------------
 # Mixed precision (FP32 preconditioning solve, FP64 elsewhere) with the
 # adaptive CholeskyQR2 re-pass. Pivots and the first-stage rank come from the

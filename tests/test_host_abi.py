@@ -34,7 +34,8 @@ def L():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("cqrrpt_saso_sample", "cqrrpt_sketch", "cqrrpt_qrcp", "cqrrpt_factor",
-                 "cqrrpt_factor_ex", "cqrrpt_workspace_bytes", "cqrrpt_server_create",
+                 "cqrrpt_factor_ex", "cqrrpt_factor_implicit_ex", "cqrrpt_workspace_bytes",
+                 "cqrrpt_server_create",
                  "cqrrpt_server_submit", "cqrrpt_server_poll", "cqrrpt_server_drain",
                  "cqrrpt_server_destroy"):
         assert must in names
@@ -100,6 +101,41 @@ def test_factor_ex_rejects_bad_arguments_before_any_device_work(L):
     assert call(mode=7) == -14
     assert call(ws=None) == -15
     assert call(info=None) == -18
+    assert call(wsb=16) == 4  # CQRRPT_EWORKSPACE
+
+
+def test_factor_implicit_ex_rejects_bad_arguments_before_any_device_work(L):
+    f = L.cqrrpt_factor_implicit_ex
+    i64, i32, u64, dbl, vp, sz = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
+                                  ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t)
+    f.argtypes = [vp, i64, i64, i64, i64, i32, u64, dbl, vp, i64, vp, i64, vp, i64, vp,
+                  vp, sz, vp, vp]
+    p = vp(16)  # never dereferenced: every case fails an argument check first
+    base = dict(A=p, lda=100, m=100, n=10, d=12, nnz=4, seed=0, tol=1e-14, M=p, ldm=100,
+                Rp=p, ldrp=10, R=p, ldr=10, J=p, ws=p, wsb=1 << 30, s=None, info=p)
+
+    def call(**kw):
+        a = dict(base, **kw)
+        return f(a["A"], a["lda"], a["m"], a["n"], a["d"], a["nnz"], a["seed"], a["tol"], a["M"],
+                 a["ldm"], a["Rp"], a["ldrp"], a["R"], a["ldr"], a["J"], a["ws"], a["wsb"],
+                 a["s"], a["info"])
+
+    assert call(A=None) == -1
+    assert call(lda=99) == -2
+    assert call(m=0) == -3
+    assert call(n=101) == -4
+    assert call(d=9) == -5
+    assert call(nnz=33) == -6
+    assert call(tol=float("inf")) == -8
+    assert call(M=None) == -9
+    assert call(ldm=99) == -10
+    assert call(Rp=None) == -11
+    assert call(ldrp=9) == -12
+    assert call(R=None) == -13
+    assert call(ldr=9) == -14
+    assert call(J=None) == -15
+    assert call(ws=None) == -16
+    assert call(info=None) == -19
     assert call(wsb=16) == 4  # CQRRPT_EWORKSPACE
 
 
