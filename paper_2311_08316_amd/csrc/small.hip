@@ -797,14 +797,16 @@ copy_square_kernel(const double* __restrict__ src, int64_t lds, double* __restri
   for (int i = threadIdx.x; i < n; i += kThreads) dst[i + j * ldd] = src[i + j * lds];
 }
 
+// Columns k..n-1 of Q, each taken by gridDim.y-strided workgroup rows (the
+// grid does not depend on k, which is known on the device only).
 __global__ void __launch_bounds__(kThreads)
 zero_cols_kernel(double* Q, int64_t ldq, int64_t m, int n, const int64_t* kdev) {
-  const int64_t c = blockIdx.y;
-  if (c < *kdev || c >= n) return;
-  double* col = Q + c * ldq;
-  for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < m;
-       r += (int64_t)gridDim.x * kThreads)
-    col[r] = 0.0;
+  for (int64_t c = *kdev + blockIdx.y; c < n; c += gridDim.y) {
+    double* col = Q + c * ldq;
+    for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < m;
+         r += (int64_t)gridDim.x * kThreads)
+      col[r] = 0.0;
+  }
 }
 
 // Leading k x k block of R_pre (upper triangle of G after the Cholesky step)
@@ -912,8 +914,9 @@ hipError_t launch_zero_cols(double* Q, int64_t ldq, int64_t m, int n, const int6
                             hipStream_t s) {
   int64_t gx = (m + kThreads - 1) / kThreads;
   if (gx > 64) gx = 64;
-  hipLaunchKernelGGL(zero_cols_kernel, dim3((unsigned)gx, n), dim3(kThreads), 0, s, Q, ldq, m, n,
-                     kdev);
+  const int gy = n < 64 ? n : 64;
+  hipLaunchKernelGGL(zero_cols_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(kThreads), 0, s, Q,
+                     ldq, m, n, kdev);
   return hipGetLastError();
 }
 

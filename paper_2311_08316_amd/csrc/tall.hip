@@ -667,31 +667,38 @@ syrk_reduce_kernel(const double* __restrict__ P, int nsplit, int tiles, const in
                    double* __restrict__ G, int64_t ldg, const cqrrpt_info_t* info) {
   if (info->status != 0) return;
   const int64_t k = *kdev;
-  const int64_t total = (int64_t)tiles * (kST * kST);
-  const int64_t stride = total;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    // Element (li, lj) of upper tile t = J (J + 1) / 2 + I.
-    const int t = (int)(e / (kST * kST));
-    const int loc = (int)(e - (int64_t)t * (kST * kST));
-    int J = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while ((J + 1) * (J + 2) / 2 <= t) ++J;
-    while (J * (J + 1) / 2 > t) --J;
-    const int I = t - J * (J + 1) / 2;
-    const int64_t i = (int64_t)I * kST + (loc % kST);
-    const int64_t j = (int64_t)J * kST + (loc / kST);
-    if (i > j || j >= k) continue;
-    // Splits in order, compensated as in the partial tiles.
-    double s = 0.0, c = 0.0;
-    for (int q = 0; q < nsplit; ++q) {
-      const double y = P[q * stride + e];
-      const double t = s + y;
-      const double yv = t - s;
-      c += (s - (t - yv)) + (y - yv);
-      s = t;
-    }
-    G[i + j * ldg] = s + c;
+  // Upper tile t = J (J + 1) / 2 + I of this workgroup row; element (li, lj)
+  // of the tile from the thread index (16 consecutive workgroups per tile).
+  const int t = blockIdx.y;
+  int J = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((J + 1) * (J + 2) / 2 <= t) ++J;
+  while (J * (J + 1) / 2 > t) --J;
+  const int I = t - J * (J + 1) / 2;
+  const int loc = blockIdx.x * kThreads + threadIdx.x;
+  const int64_t i = (int64_t)I * kST + (loc % kST);
+  const int64_t j = (int64_t)J * kST + (loc / kST);
+  if (i > j || j >= k) return;
+  const int64_t stride = (int64_t)tiles * (kST * kST);
+  const double* p = P + (int64_t)t * (kST * kST) + loc;
+  // Splits in order, compensated as in the partial tiles; eight loads are
+  // issued ahead of each stretch of the dependent sum.
+  double s = 0.0, c = 0.0;
+  auto add = [&](double y) {
+    const double u = s + y;
+    const double yv = u - s;
+    c += (s - (u - yv)) + (y - yv);
+    s = u;
+  };
+  int q = 0;
+  for (; q + 8 <= nsplit; q += 8) {
+    double y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) y[u] = p[(int64_t)(q + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) add(y[u]);
   }
+  for (; q < nsplit; ++q) add(p[(int64_t)q * stride]);
+  G[i + j * ldg] = s + c;
 }
 
 }  // namespace
@@ -774,10 +781,8 @@ hipError_t launch_syrk(const T* X, int64_t ldx, int64_t m, const int64_t* kdev, 
                      ldx, m, kdev, kmax, rps, tiles, partials, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  int64_t grid = ((int64_t)tiles * kST * kST + kThreads - 1) / kThreads;
-  if (grid > 4096) grid = 4096;
-  hipLaunchKernelGGL(syrk_reduce_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, partials,
-                     nsplit, tiles, kdev, G, ldg, info);
+  hipLaunchKernelGGL(syrk_reduce_kernel, dim3(kST * kST / kThreads, (unsigned)tiles),
+                     dim3(kThreads), 0, s, partials, nsplit, tiles, kdev, G, ldg, info);
   return hipGetLastError();
 }
 
