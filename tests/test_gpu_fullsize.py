@@ -112,7 +112,23 @@ def test_fullsize_131072x1024_planted(P):
         Jg = f.J.cpu().numpy()
         assert np.array_equal(Jg[:512], np.asarray(J_o)[:512]), f"pivots differ (tol {tol})"
         check_factor(A, f, int(info.rank), f"131072x1024 tol {tol:g}", recon_max=recon_max)
-        del f
+        # Implicit Q at the same size: R and J bit-identical to the explicit
+        # call, M zero past the rank, and M_pre = Q R_pre (a product, so it
+        # holds to rounding at any size; R_pre is well conditioned).
+        fi = P.Factorization(m, n, d, nnz, P.CQRRPT_FP64, implicit=True)
+        fi.run(A, 0, tol)
+        ii = fi.info()
+        k = int(info.rank)
+        assert ii.status == 0 and ii.rank == k
+        assert torch.equal(fi.R, f.R) and torch.equal(fi.J, f.J)
+        if k < n:
+            assert not bool(fi.Q[:, k:].abs().max() > 0)
+        Rp = fi.Rpre[:k, :k]
+        dM = float(torch.linalg.norm(fi.Q[:, :k] - f.Q[:, :k] @ Rp) /
+                   torch.linalg.norm(fi.Q[:, :k]))
+        assert dM <= 1e-12, f"M_pre vs Q R_pre {dM:.2e} (tol {tol})"
+        say(f"  implicit tol {tol:g}: rank {k} ||M - Q R_pre|| / ||M|| {dM:.2e}")
+        del f, fi
 
 
 def test_fullsize_1048576x512_mixed_and_fp64(P):
