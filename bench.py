@@ -36,7 +36,7 @@ METRIC = ("CQRRPT GFLOP/s (2mn² norm.) FP64 vs mixed @ ‖QᵀQ−I‖; "
 PEAK_FP64_MFMA = 78.6e12
 PEAK_FP32_MFMA = 157.3e12
 PEAK_HBM = 8.0e12
-DOMINANT = "trsm_kernel<double,double,double>"
+DOMINANT = "trsm_rows_kernel"
 
 
 def log(msg):

@@ -1,7 +1,7 @@
 // The tall steps of Algorithm 2 on the matrix cores:
 //   * precondition  M_pre = A[:, J[:k]] R_sk[:k,:k]^{-1}   (right triangular
 //     solve with the column gather fused into the loads),
-//   * Q-factor      Q = M_pre R_pre^{-1}                   (same kernel, in place),
+//   * Q-factor      Q = M_pre W, W = R_pre^{-1}            (triangular product, in place),
 //   * Gram          G = M_pre^T M_pre                       (split-K, fixed-order sum).
 //
 // The solve is blocked in 16-column tiles: each tile is multiplied by the
@@ -12,6 +12,8 @@
 // reconstruction as plain substitution; the inverse of R itself is never
 // formed.
 #include <math.h>
+
+#include <type_traits>
 
 #include "common.h"
 
@@ -338,6 +340,204 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
   }
 }
 
+// FP64 solve with each wave owning 32 whole rows of the workgroup's 128 x 128
+// panel (row tiles a = 0, 1; column tiles b = 0..7). The accumulators hold
+// the transposed tile: register r of lane (l16, lq) in acc[b][a] is element
+// (row 32 w + 16 a + l16, column 16 b + lq + 4 r). For the FP64 16x16x4
+// instruction that register order is exactly the B operand of the next
+// product (lane (l16, lq), K index lq + 4 s in register s), so the diagonal
+// phase runs in registers: T_t = B_t - acc[t], X_t^T = inv(R_tt)^T T_t^T,
+// acc[b > t] += R[t, b]^T X_t^T, with no exchange between waves; only the
+// strip R[tile t, panel] is staged through LDS (one barrier per tile, where
+// the 64 x 64-wave layout needed three for the exchanges between waves).
+// The off-diagonal K loop stages X and R tiles through double-buffered LDS
+// with one register stage of prefetch (a second stage made the compiler
+// spill inside the loop).
+__global__ void __launch_bounds__(kTThreads, 2)
+trsm_rows_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gather, double* X,
+                 int64_t ldx, const double* __restrict__ R, int64_t ldr, int64_t m,
+                 const int64_t* kdev, const double* __restrict__ inv, const cqrrpt_info_t* info,
+                 const int* enable) {
+  extern __shared__ unsigned char smem_raw[];
+  double* lds = reinterpret_cast<double*>(smem_raw);
+  int* gcols = reinterpret_cast<int*>(lds + kTrsmLds);  // [kPW]
+
+  if (info->status != 0 || (enable && *enable == 0)) return;
+  const int k = (int)*kdev;
+  if (k <= 0) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int l16 = lane & 15;
+  const int lq = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * kRT;
+  constexpr int kLoads = kKB * kRT / kTThreads;  // 8 per operand and step
+  const int ra = tid & (kRT - 1), ca = tid >> 7;
+  const int rb = tid & 15, cb = tid >> 4;
+  const int64_t rowa = row0 + ra < m ? row0 + ra : m - 1;
+  const uint32_t ldr32 = (uint32_t)ldr;
+  for (int c0 = 0; c0 < k; c0 += kPW) {
+    int c0o = c0;
+    asm volatile("" : "+s"(c0o));
+    const int nt = ((k - c0o < kPW ? k - c0o : kPW) + 15) / 16;
+    __syncthreads();  // the previous panel's readers of gcols and LDS are done
+    if (tid < kPW) {
+      const int col = c0o + tid < k ? c0o + tid : k - 1;
+      gcols[tid] = gather ? (int)gather[col] : col;
+    }
+    d4_t acc[8][2];
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) acc[b][a] = d4_t{0, 0, 0, 0};
+
+    if (c0o > 0) {
+      double areg0[kLoads], rreg0[kLoads];
+      auto load = [&](int kk, double (&ar)[kLoads], double (&rr)[kLoads]) {
+        const double* xs = X + rowa + (int64_t)(kk + ca) * ldx;
+#pragma unroll
+        for (int q = 0; q < kLoads; ++q) ar[q] = xs[(int64_t)(2 * q) * ldx];
+#pragma unroll
+        for (int q = 0; q < kLoads; ++q) {
+          const int col = c0o + cb + 16 * q;
+          rr[q] = r_at(R, ldr32, kk + rb, col < k ? col : k - 1);
+        }
+      };
+      auto store = [&](int buf, const double (&ar)[kLoads], const double (&rr)[kLoads]) {
+        double* At = lds + buf * kQStage;
+        double* Rt = At + kTileSz;
+#pragma unroll
+        for (int q = 0; q < kLoads; ++q) At[(ca + 2 * q) * kSLd + ra] = ar[q];
+#pragma unroll
+        for (int q = 0; q < kLoads; ++q)
+          Rt[(cb + 16 * q) * kWLd + rb] = c0o + cb + 16 * q < k ? rr[q] : 0.0;
+      };
+      auto multiply = [&](int buf) {
+        const double* At = lds + buf * kQStage;
+        const double* Rt = At + kTileSz;
+#pragma unroll
+        for (int s = 0; s < kKB / 4; ++s) {
+          double xb[2], rf[8];
+#pragma unroll
+          for (int a = 0; a < 2; ++a) xb[a] = At[(4 * s + lq) * kSLd + 32 * wave + 16 * a + l16];
+#pragma unroll
+          for (int b = 0; b < 8; ++b) rf[b] = Rt[(16 * b + l16) * kWLd + 4 * s + lq];
+#pragma unroll
+          for (int b = 0; b < 8; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) acc[b][a] = mfma(rf[b], xb[a], acc[b][a]);
+        }
+      };
+      const int nk = c0o / kKB;
+      load(0, areg0, rreg0);
+      store(0, areg0, rreg0);
+      __syncthreads();
+      for (int it = 0; it < nk; ++it) {
+        int ito = it;
+        asm volatile("" : "+s"(ito));
+        if (ito + 1 < nk) load((ito + 1) * kKB, areg0, rreg0);
+        multiply(ito & 1);
+        if (ito + 1 < nk) store((ito + 1) & 1, areg0, rreg0);
+        __syncthreads();
+      }
+    } else {
+      __syncthreads();  // gcols
+    }
+
+    // Diagonal block. Strip t (rows of tile t over the panel, transposed,
+    // [column][row in tile], identity past k) is staged in LDS buffer t & 1;
+    // B_t and the next strip are loaded one tile ahead.
+    double* Rs0 = lds;
+    double* Rs1 = lds + kWTile;
+    // This lane's two rows (row tiles a = 0, 1), clamped for loads.
+    int64_t rowl[2], rowc[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      rowl[a] = row0 + 32 * wave + 16 * a + l16;
+      rowc[a] = rowl[a] < m ? rowl[a] : m - 1;
+    }
+    double sreg[kLoads];
+    auto load_strip = [&](int t) {
+      const int ri = c0o + 16 * t + rb;
+#pragma unroll
+      for (int q = 0; q < kLoads; ++q) {
+        const int cj = c0o + cb + 16 * q;
+        sreg[q] = r_at(R, ldr32, ri < k ? ri : k - 1, cj < k ? cj : k - 1);
+      }
+    };
+    auto store_strip = [&](int t, double* Rs) {
+#pragma unroll
+      for (int q = 0; q < kLoads; ++q)
+        Rs[(cb + 16 * q) * kWLd + rb] =
+            r_entry<double>(sreg[q], c0o + 16 * t + rb, c0o + cb + 16 * q, k);
+    };
+    double bt[2][4];
+    auto load_b = [&](int t) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int g = gcols[16 * t + lq + 4 * r];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) bt[a][r] = B[rowc[a] + (int64_t)g * ldb];
+      }
+    };
+    load_strip(0);
+    load_b(0);
+    store_strip(0, Rs0);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if (t < nt) {
+        double* Rs = (t & 1) ? Rs1 : Rs0;
+        double* Rn = (t & 1) ? Rs0 : Rs1;
+        // T_t = B_t - acc[t] (columns past k: B is taken as zero).
+        double tv[2][4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            tv[a][r] = (c0o + 16 * t + lq + 4 * r < k ? bt[a][r] : 0.0) - acc[t][a][r];
+        if (t + 1 < nt) {
+          load_strip(t + 1);
+          load_b(t + 1);
+        }
+        // X_t^T = inv(R_tt)^T T_t^T.
+        const double* pi = inv + (size_t)((c0o >> 4) + t) * kInvPack;
+        d4_t xt[2] = {d4_t{0, 0, 0, 0}, d4_t{0, 0, 0, 0}};
+#pragma unroll
+        for (int sq = 0; sq < 4; ++sq) {
+          const double vf = pi[sq * 64 + lane];
+#pragma unroll
+          for (int a = 0; a < 2; ++a) xt[a] = mfma(vf, tv[a][sq], xt[a]);
+        }
+        // X_t to memory: element (row 32 w + 16 a + l16, column 16 t + lq + 4 r).
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+          if (rowl[a] < m) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int col = c0o + 16 * t + lq + 4 * r;
+              if (col < k) X[rowl[a] + (int64_t)col * ldx] = xt[a][r];
+            }
+          }
+        // acc[b][a] += R[tile t, tile b]^T X_t^T for the later tiles b.
+#pragma unroll
+        for (int b = t + 1; b < 8; ++b) {
+          if (b < nt) {
+#pragma unroll
+            for (int sq = 0; sq < 4; ++sq) {
+              const double rf = Rs[(16 * b + l16) * kWLd + 4 * sq + lq];
+#pragma unroll
+              for (int a = 0; a < 2; ++a) acc[b][a] = mfma(rf, xt[a][sq], acc[b][a]);
+            }
+          }
+        }
+        if (t + 1 < nt) store_strip(t + 1, Rn);
+        __syncthreads();
+      }
+    }
+  }
+}
+
 template <typename TB, typename TX, typename TC>
 hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX* X, int64_t ldx,
                             const double* R, int64_t ldr, int64_t m, const int64_t* kdev,
@@ -351,13 +551,25 @@ hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX*
                      kdev, ntiles, inv, info, enable);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const void* fn = (const void*)trsm_kernel<TB, TX, TC>;
-  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
   const int64_t grid = (m + kRT - 1) / kRT;
-  hipLaunchKernelGGL((trsm_kernel<TB, TX, TC>), dim3((unsigned)grid), dim3(kTThreads), lds, s, B,
-                     ldb, gather, X, ldx, R, ldr, m, kdev, inv, info, enable);
-  return hipGetLastError();
+  if constexpr (std::is_same<TB, double>::value && std::is_same<TX, double>::value &&
+                std::is_same<TC, double>::value) {
+    // FP64: the row-owned kernel (its diagonal phase needs the FP64 MFMA
+    // register order; the FP32 instruction interleaves rows differently).
+    const void* fn = (const void*)trsm_rows_kernel;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)grid), dim3(kTThreads), lds, s, B, ldb,
+                       gather, X, ldx, R, ldr, m, kdev, inv, info, enable);
+    return hipGetLastError();
+  } else {
+    const void* fn = (const void*)trsm_kernel<TB, TX, TC>;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((trsm_kernel<TB, TX, TC>), dim3((unsigned)grid), dim3(kTThreads), lds, s,
+                       B, ldb, gather, X, ldx, R, ldr, m, kdev, inv, info, enable);
+    return hipGetLastError();
+  }
 }
 
 // ---------------------------------------------------------------------------
