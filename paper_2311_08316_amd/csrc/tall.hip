@@ -121,226 +121,7 @@ trsm_inv_kernel(const double* __restrict__ R, int64_t ldr, const int64_t* kdev, 
   for (int kk = 0; kk < kInvTile; ++kk) dst[(kk >> 2) * 64 + (kk & 3) * 16 + j] = x[kk];
 }
 
-// TB: type of B, TX: type of X, TC: arithmetic type. Wave w holds the
-// 64 x 64 sub-block (rows 64 (w % 2), panel columns 64 (w / 2)) of the
-// 128 x 128 panel as 4 x 4 MFMA tiles.
-template <typename TB, typename TX, typename TC>
-__global__ void __launch_bounds__(kTThreads, 2)
-trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X, int64_t ldx,
-            const double* __restrict__ R, int64_t ldr, int64_t m, const int64_t* kdev,
-            const double* __restrict__ inv, const cqrrpt_info_t* info, const int* enable) {
-  typedef typename MfmaAcc<TC>::type acc_t;
-  extern __shared__ unsigned char smem_raw[];
-  TC* lds = reinterpret_cast<TC*>(smem_raw);
-  TC* Tt = lds;                // diagonal phase: B tile / T_t / X_t, [16][kSLd]
-  TC* Rs = lds + kTileSz;               // diagonal phase: R strip, [kPW][kWLd]
-  TC* Ta = lds + kTileSz + kWTile;      // diagonal phase: accumulator tile, [16][kSLd]
-  int* gcols = reinterpret_cast<int*>(lds + kTrsmLds);  // [kPW]
-
-  if (info->status != 0 || (enable && *enable == 0)) return;
-  const int k = (int)*kdev;
-  if (k <= 0) return;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wr = wave & 1;
-  const int wc = __builtin_amdgcn_readfirstlane(wave >> 1);
-  const int l16 = lane & 15;
-  const int lq = lane >> 4;
-  const int64_t row0 = (int64_t)blockIdx.x * kRT;
-  constexpr int kLoads = kKB * kRT / kTThreads;  // 8 per operand and step
-  // Element e = tid + 256 q of a 16 x 128 tile: (e & 127, e >> 7) =
-  // (tid & 127, tid / 128 + 2 q) in column-major K tiles, and
-  // (e & 15, e >> 4) = (tid & 15, tid / 16 + 16 q) in row-major R tiles.
-  const int ra = tid & (kRT - 1), ca = tid >> 7;
-  const int rb = tid & 15, cb = tid >> 4;
-  // Rows past m read row m-1 (in bounds); their results are never stored.
-  const int64_t rowa = row0 + ra < m ? row0 + ra : m - 1;
-  const uint32_t ldr32 = (uint32_t)ldr;
-
-  for (int c0 = 0; c0 < k; c0 += kPW) {
-    // Keep the panel offset opaque so address arithmetic is not turned into
-    // loop-carried 64-bit pointers.
-    int c0o = c0;
-    asm volatile("" : "+s"(c0o));
-    const int nt = ((k - c0o < kPW ? k - c0o : kPW) + 15) / 16;
-    // Gathered column of each panel column (clamped past k; those values
-    // are zeroed on load). The previous panel's readers are done: its last
-    // tile step ended after a barrier that follows every load_tile call.
-    if (tid < kPW) {
-      const int col = c0o + tid < k ? c0o + tid : k - 1;
-      gcols[tid] = gather ? (int)gather[col] : col;
-    }
-    __syncthreads();
-    // Tile t's B values (column-major 16 x kRT, coalesced) and R strip,
-    // one tile ahead of use, kept in their storage types until stored (a
-    // conversion or mask at load time would wait for the load).
-    TB breg[kLoads];
-    double sreg[kLoads];
-    auto load_tile = [&](int t) {
-#pragma unroll
-      for (int q = 0; q < kLoads; ++q) breg[q] = B[rowa + (int64_t)gcols[16 * t + ca + 2 * q] * ldb];
-      const int ri = c0o + 16 * t + rb;
-#pragma unroll
-      for (int q = 0; q < kLoads; ++q) {
-        const int cj = c0o + cb + 16 * q;
-        sreg[q] = r_at(R, ldr32, ri < k ? ri : k - 1, cj < k ? cj : k - 1);
-      }
-    };
-    acc_t acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-
-    if (c0o > 0) {
-      // Two register stages: the loads of K step s + 2 are issued while
-      // step s is multiplied out of LDS and step s + 1 waits in registers.
-      // The number of K steps, c0 / 16, is a multiple of 8.
-      TX areg0[kLoads], areg1[kLoads];
-      double rreg0[kLoads], rreg1[kLoads];
-      auto load = [&](int kk, TX (&ar)[kLoads], double (&rr)[kLoads]) {
-        const TX* xs = X + rowa + (int64_t)(kk + ca) * ldx;
-#pragma unroll
-        for (int q = 0; q < kLoads; ++q) ar[q] = xs[(int64_t)(2 * q) * ldx];
-        // R rows kk.. < c0 <= column: strictly above the diagonal.
-#pragma unroll
-        for (int q = 0; q < kLoads; ++q) {
-          const int col = c0o + cb + 16 * q;
-          rr[q] = r_at(R, ldr32, kk + rb, col < k ? col : k - 1);
-        }
-      };
-      auto store = [&](int buf, const TX (&ar)[kLoads], const double (&rr)[kLoads]) {
-        TC* At = lds + buf * kQStage;
-        TC* Rt = At + kTileSz;
-#pragma unroll
-        for (int q = 0; q < kLoads; ++q) At[(ca + 2 * q) * kSLd + ra] = (TC)ar[q];
-#pragma unroll
-        for (int q = 0; q < kLoads; ++q)
-          Rt[(cb + 16 * q) * kWLd + rb] = c0o + cb + 16 * q < k ? (TC)rr[q] : (TC)0;
-      };
-      auto multiply = [&](int buf) {
-        const TC* At = lds + buf * kQStage;
-        const TC* Rt = At + kTileSz;
-#pragma unroll
-        for (int s = 0; s < kKB / 4; ++s) {
-          TC af[4], bf[4];
-#pragma unroll
-          for (int a = 0; a < 4; ++a) af[a] = At[(4 * s + lq) * kSLd + 64 * wr + 16 * a + l16];
-#pragma unroll
-          for (int b = 0; b < 4; ++b) bf[b] = Rt[(64 * wc + 16 * b + l16) * kWLd + 4 * s + lq];
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = mfma(af[a], bf[b], acc[a][b]);
-        }
-      };
-      const int nk = c0o / kKB;
-      load(0, areg0, rreg0);
-      load(kKB, areg1, rreg1);
-      __syncthreads();  // the previous panel's diagonal phase is done with LDS
-      store(0, areg0, rreg0);
-      __syncthreads();
-      for (int it = 0; it < nk; it += 2) {
-        int ito = it;
-        asm volatile("" : "+s"(ito));
-        // Step it is in LDS buffer 0, step it + 1 in registers 1.
-        if (ito + 2 < nk) load((ito + 2) * kKB, areg0, rreg0);
-        multiply(0);
-        store(1, areg1, rreg1);
-        __syncthreads();
-        // Step it + 1 is in LDS buffer 1, step it + 2 in registers 0.
-        if (ito + 3 < nk) load((ito + 3) * kKB, areg1, rreg1);
-        multiply(1);
-        if (ito + 2 < nk) store(0, areg0, rreg0);
-        __syncthreads();
-      }
-    }
-    load_tile(0);  // the diagonal phase's first B tile and R strip
-
-    // Diagonal block, one 16-column tile at a time.
-    for (int t = 0; t < nt; ++t) {
-      int to = t;
-      asm volatile("" : "+s"(to));
-      __syncthreads();  // LDS free: GEMM staging or the previous tile's update
-      // The strip: rows of tile t over the panel (the update below masks the
-      // columns of tile t and earlier).
-#pragma unroll
-      for (int q = 0; q < kLoads; ++q) {
-        Rs[(cb + 16 * q) * kWLd + rb] =
-            r_entry<TC>(sreg[q], c0o + 16 * to + rb, c0o + cb + 16 * q, k);
-        const int cl = 16 * to + ca + 2 * q;
-        Tt[(ca + 2 * q) * kSLd + ra] = c0o + cl < k ? (TC)breg[q] : (TC)0;
-      }
-      if (wc == (to >> 2)) {
-        // Column tile t & 3 of this wave's accumulators (selects, no
-        // branches on the accumulators).
-        const int bt = to & 3;
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            TC v = acc[a][0][r];
-            v = bt == 1 ? acc[a][1][r] : v;
-            v = bt == 2 ? acc[a][2][r] : v;
-            v = bt == 3 ? acc[a][3][r] : v;
-            Ta[l16 * kSLd + 64 * wr + 16 * a + acc_row<TC>(lq, r)] = v;
-          }
-      }
-      if (to + 1 < nt) load_tile(to + 1);
-      __syncthreads();
-      {
-        // X_t = (B_t - acc_t) inv(R_tt): wave w takes rows 32 w .. 32 w + 31
-        // (two 16-row tiles) and writes them back over its own rows of Tt.
-        const double* pi = inv + (size_t)((c0o >> 4) + to) * kInvPack;
-        acc_t xt[2] = {acc_t{0, 0, 0, 0}, acc_t{0, 0, 0, 0}};
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const TC bf = (TC)pi[s * 64 + lane];
-#pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            const int e = (4 * s + lq) * kSLd + 32 * wave + 16 * a + l16;
-            xt[a] = mfma(Tt[e] - Ta[e], bf, xt[a]);
-          }
-        }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            Tt[l16 * kSLd + 32 * wave + 16 * a + acc_row<TC>(lq, r)] = xt[a][r];
-      }
-      __syncthreads();
-      // X_t to memory.
-      if (row0 + ra < m) {
-        TX* xs = X + row0 + ra + (int64_t)(c0o + 16 * to + ca) * ldx;
-#pragma unroll
-        for (int q = 0; q < kLoads; ++q)
-          if (c0o + 16 * to + ca + 2 * q < k) xs[(int64_t)(2 * q) * ldx] = (TX)Tt[(ca + 2 * q) * kSLd + ra];
-      }
-      // acc[:, tiles > t] += X_t R[tile t, tiles > t]; a wave skips its
-      // column tiles that are already solved (the test is the same for every
-      // lane of the wave).
-      if (4 * wc + 3 > to) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          TC af[4];
-#pragma unroll
-          for (int a = 0; a < 4; ++a) af[a] = Tt[(4 * s + lq) * kSLd + 64 * wr + 16 * a + l16];
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            if (4 * wc + b > to) {
-              const TC bf = Rs[(64 * wc + 16 * b + l16) * kWLd + 4 * s + lq];
-#pragma unroll
-              for (int a = 0; a < 4; ++a) acc[a][b] = mfma(af[a], bf, acc[a][b]);
-            }
-          }
-        }
-      }
-    }
-  }
-}
-
-// FP64 solve with each wave owning 32 whole rows of the workgroup's 128 x 128
+// Triangular solve (FP64; FP32 in the mixed mode) with each wave owning 32 whole rows of the workgroup's 128 x 128
 // panel (row tiles a = 0, 1; column tiles b = 0..7). The accumulators hold
 // the transposed tile: register r of lane (l16, lq) in acc[b][a] is element
 // (row 32 w + 16 a + l16, column 16 b + lq + 4 r). For the FP64 16x16x4
@@ -348,18 +129,24 @@ trsm_kernel(const TB* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
 // product (lane (l16, lq), K index lq + 4 s in register s), so the diagonal
 // phase runs in registers: T_t = B_t - acc[t], X_t^T = inv(R_tt)^T T_t^T,
 // acc[b > t] += R[t, b]^T X_t^T, with no exchange between waves; only the
-// strip R[tile t, panel] is staged through LDS (one barrier per tile, where
-// the 64 x 64-wave layout needed three for the exchanges between waves).
+// strip R[tile t, panel] is staged through LDS (one barrier per tile; a
+// layout of 64 x 64 tiles per wave needed three, for exchanges between waves).
 // The off-diagonal K loop stages X and R tiles through double-buffered LDS
 // with one register stage of prefetch (a second stage made the compiler
 // spill inside the loop).
+template <typename TX, typename TC>
 __global__ void __launch_bounds__(kTThreads, 2)
-trsm_rows_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gather, double* X,
+trsm_rows_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
                  int64_t ldx, const double* __restrict__ R, int64_t ldr, int64_t m,
                  const int64_t* kdev, const double* __restrict__ inv, const cqrrpt_info_t* info,
                  const int* enable) {
+  typedef typename MfmaAcc<TC>::type acc_t;
+  // FP64: accumulator register r of lane (l16, lq) holds column lq + 4 r,
+  // which is the next product's operand order. FP32 holds column 4 lq + r;
+  // its tiles are regrouped through a per-wave LDS area (32 x 16, pitch 17).
+  constexpr bool kRegroup = std::is_same<TC, float>::value;
   extern __shared__ unsigned char smem_raw[];
-  double* lds = reinterpret_cast<double*>(smem_raw);
+  TC* lds = reinterpret_cast<TC*>(smem_raw);
   int* gcols = reinterpret_cast<int*>(lds + kTrsmLds);  // [kPW]
 
   if (info->status != 0 || (enable && *enable == 0)) return;
@@ -385,16 +172,17 @@ trsm_rows_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gathe
       const int col = c0o + tid < k ? c0o + tid : k - 1;
       gcols[tid] = gather ? (int)gather[col] : col;
     }
-    d4_t acc[8][2];
+    acc_t acc[8][2];
 #pragma unroll
     for (int b = 0; b < 8; ++b)
 #pragma unroll
-      for (int a = 0; a < 2; ++a) acc[b][a] = d4_t{0, 0, 0, 0};
+      for (int a = 0; a < 2; ++a) acc[b][a] = acc_t{0, 0, 0, 0};
 
     if (c0o > 0) {
-      double areg0[kLoads], rreg0[kLoads];
-      auto load = [&](int kk, double (&ar)[kLoads], double (&rr)[kLoads]) {
-        const double* xs = X + rowa + (int64_t)(kk + ca) * ldx;
+      TX areg0[kLoads];
+      double rreg0[kLoads];
+      auto load = [&](int kk, TX (&ar)[kLoads], double (&rr)[kLoads]) {
+        const TX* xs = X + rowa + (int64_t)(kk + ca) * ldx;
 #pragma unroll
         for (int q = 0; q < kLoads; ++q) ar[q] = xs[(int64_t)(2 * q) * ldx];
 #pragma unroll
@@ -403,21 +191,21 @@ trsm_rows_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gathe
           rr[q] = r_at(R, ldr32, kk + rb, col < k ? col : k - 1);
         }
       };
-      auto store = [&](int buf, const double (&ar)[kLoads], const double (&rr)[kLoads]) {
-        double* At = lds + buf * kQStage;
-        double* Rt = At + kTileSz;
+      auto store = [&](int buf, const TX (&ar)[kLoads], const double (&rr)[kLoads]) {
+        TC* At = lds + buf * kQStage;
+        TC* Rt = At + kTileSz;
 #pragma unroll
-        for (int q = 0; q < kLoads; ++q) At[(ca + 2 * q) * kSLd + ra] = ar[q];
+        for (int q = 0; q < kLoads; ++q) At[(ca + 2 * q) * kSLd + ra] = (TC)ar[q];
 #pragma unroll
         for (int q = 0; q < kLoads; ++q)
-          Rt[(cb + 16 * q) * kWLd + rb] = c0o + cb + 16 * q < k ? rr[q] : 0.0;
+          Rt[(cb + 16 * q) * kWLd + rb] = c0o + cb + 16 * q < k ? (TC)rr[q] : (TC)0;
       };
       auto multiply = [&](int buf) {
-        const double* At = lds + buf * kQStage;
-        const double* Rt = At + kTileSz;
+        const TC* At = lds + buf * kQStage;
+        const TC* Rt = At + kTileSz;
 #pragma unroll
         for (int s = 0; s < kKB / 4; ++s) {
-          double xb[2], rf[8];
+          TC xb[2], rf[8];
 #pragma unroll
           for (int a = 0; a < 2; ++a) xb[a] = At[(4 * s + lq) * kSLd + 32 * wave + 16 * a + l16];
 #pragma unroll
@@ -447,8 +235,10 @@ trsm_rows_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gathe
     // Diagonal block. Strip t (rows of tile t over the panel, transposed,
     // [column][row in tile], identity past k) is staged in LDS buffer t & 1;
     // B_t and the next strip are loaded one tile ahead.
-    double* Rs0 = lds;
-    double* Rs1 = lds + kWTile;
+    TC* Rs0 = lds;
+    TC* Rs1 = lds + kWTile;
+    // FP32 regroup area of this wave (past the two strips).
+    TC* Wl = lds + 2 * kWTile + wave * (32 * 17);
     // This lane's two rows (row tiles a = 0, 1), clamped for loads.
     int64_t rowl[2], rowc[2];
 #pragma unroll
@@ -465,17 +255,17 @@ trsm_rows_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gathe
         sreg[q] = r_at(R, ldr32, ri < k ? ri : k - 1, cj < k ? cj : k - 1);
       }
     };
-    auto store_strip = [&](int t, double* Rs) {
+    auto store_strip = [&](int t, TC* Rs) {
 #pragma unroll
       for (int q = 0; q < kLoads; ++q)
         Rs[(cb + 16 * q) * kWLd + rb] =
-            r_entry<double>(sreg[q], c0o + 16 * t + rb, c0o + cb + 16 * q, k);
+            r_entry<TC>(sreg[q], c0o + 16 * t + rb, c0o + cb + 16 * q, k);
     };
     double bt[2][4];
     auto load_b = [&](int t) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int g = gcols[16 * t + lq + 4 * r];
+        const int g = gcols[16 * t + acc_row<TC>(lq, r)];
 #pragma unroll
         for (int a = 0; a < 2; ++a) bt[a][r] = B[rowc[a] + (int64_t)g * ldb];
       }
@@ -487,47 +277,67 @@ trsm_rows_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gathe
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       if (t < nt) {
-        double* Rs = (t & 1) ? Rs1 : Rs0;
-        double* Rn = (t & 1) ? Rs0 : Rs1;
+        TC* Rs = (t & 1) ? Rs1 : Rs0;
+        TC* Rn = (t & 1) ? Rs0 : Rs1;
         // T_t = B_t - acc[t] (columns past k: B is taken as zero).
-        double tv[2][4];
+        TC tv[2][4];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            tv[a][r] = (c0o + 16 * t + lq + 4 * r < k ? bt[a][r] : 0.0) - acc[t][a][r];
+            tv[a][r] = (c0o + 16 * t + acc_row<TC>(lq, r) < k ? (TC)bt[a][r] : (TC)0) -
+                       acc[t][a][r];
+        // Operand order: K index 4 s + lq in slot s.
+        auto regroup = [&](TC (&v)[2][4]) __attribute__((always_inline)) {
+          if constexpr (kRegroup) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) Wl[(16 * a + l16) * 17 + acc_row<TC>(lq, r)] = v[a][r];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+              for (int sq = 0; sq < 4; ++sq) v[a][sq] = Wl[(16 * a + l16) * 17 + 4 * sq + lq];
+          }
+        };
+        regroup(tv);
         if (t + 1 < nt) {
           load_strip(t + 1);
           load_b(t + 1);
         }
         // X_t^T = inv(R_tt)^T T_t^T.
         const double* pi = inv + (size_t)((c0o >> 4) + t) * kInvPack;
-        d4_t xt[2] = {d4_t{0, 0, 0, 0}, d4_t{0, 0, 0, 0}};
+        acc_t xt[2] = {acc_t{0, 0, 0, 0}, acc_t{0, 0, 0, 0}};
 #pragma unroll
         for (int sq = 0; sq < 4; ++sq) {
-          const double vf = pi[sq * 64 + lane];
+          const TC vf = (TC)pi[sq * 64 + lane];
 #pragma unroll
           for (int a = 0; a < 2; ++a) xt[a] = mfma(vf, tv[a][sq], xt[a]);
         }
-        // X_t to memory: element (row 32 w + 16 a + l16, column 16 t + lq + 4 r).
+        // X_t to memory: element (row 32 w + 16 a + l16, column 16 t + acc_row(lq, r)).
+        TC xv[2][4];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) xv[a][r] = xt[a][r];
           if (rowl[a] < m) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const int col = c0o + 16 * t + lq + 4 * r;
-              if (col < k) X[rowl[a] + (int64_t)col * ldx] = xt[a][r];
+              const int col = c0o + 16 * t + acc_row<TC>(lq, r);
+              if (col < k) X[rowl[a] + (int64_t)col * ldx] = (TX)xv[a][r];
             }
           }
+        }
+        regroup(xv);
         // acc[b][a] += R[tile t, tile b]^T X_t^T for the later tiles b.
 #pragma unroll
         for (int b = t + 1; b < 8; ++b) {
           if (b < nt) {
 #pragma unroll
             for (int sq = 0; sq < 4; ++sq) {
-              const double rf = Rs[(16 * b + l16) * kWLd + 4 * sq + lq];
+              const TC rf = Rs[(16 * b + l16) * kWLd + 4 * sq + lq];
 #pragma unroll
-              for (int a = 0; a < 2; ++a) acc[b][a] = mfma(rf, xt[a][sq], acc[b][a]);
+              for (int a = 0; a < 2; ++a) acc[b][a] = mfma(rf, xv[a][sq], acc[b][a]);
             }
           }
         }
@@ -552,24 +362,12 @@ hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX*
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t grid = (m + kRT - 1) / kRT;
-  if constexpr (std::is_same<TB, double>::value && std::is_same<TX, double>::value &&
-                std::is_same<TC, double>::value) {
-    // FP64: the row-owned kernel (its diagonal phase needs the FP64 MFMA
-    // register order; the FP32 instruction interleaves rows differently).
-    const void* fn = (const void*)trsm_rows_kernel;
-    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)grid), dim3(kTThreads), lds, s, B, ldb,
-                       gather, X, ldx, R, ldr, m, kdev, inv, info, enable);
-    return hipGetLastError();
-  } else {
-    const void* fn = (const void*)trsm_kernel<TB, TX, TC>;
-    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((trsm_kernel<TB, TX, TC>), dim3((unsigned)grid), dim3(kTThreads), lds, s,
-                       B, ldb, gather, X, ldx, R, ldr, m, kdev, inv, info, enable);
-    return hipGetLastError();
-  }
+  const void* fn = (const void*)trsm_rows_kernel<TX, TC>;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((trsm_rows_kernel<TX, TC>), dim3((unsigned)grid), dim3(kTThreads), lds, s,
+                     B, ldb, gather, X, ldx, R, ldr, m, kdev, inv, info, enable);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -581,7 +379,8 @@ hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX*
 // matrix-core product. A workgroup owns kRT rows and walks the 128-column
 // panels from the last to the first, so M may alias Q: panel c reads the
 // columns below c + 128 only, which later (lower) panels have not written.
-// The K loop is the solve's (two register stages over double-buffered LDS);
+// The K loop stages M and W tiles through double-buffered LDS with two
+// register stages of prefetch;
 // a wave skips the K steps below its columns' diagonal. The accumulators
 // hold the transposed tile (rows on the N index), so the stores of 16
 // consecutive lanes cover 16 consecutive rows.
