@@ -314,6 +314,21 @@ def test_factor_implicit_q(P, label, m, n, d, nnz, kind, cond, tol):
         f"orth {orth:.2e}")
 
 
+def test_factor_implicit_degenerate(P):
+    """Implicit Q on A = 0 (rank 0: M, R_pre and R all zero) and on an input
+    holding a NaN (reported as non-finite, like the explicit entry)."""
+    say("factor implicit zero / nonfinite")
+    Z = np.zeros((400, 12))
+    Mg, Rpg, Rg, Jg, info = P.factor_implicit(to_gpu(Z), 15, 4, 1, 1e-14)
+    assert info.rank == 0 and info.status == 0
+    assert not to_np(Mg).any() and not to_np(Rpg).any() and not to_np(Rg).any()
+    rng = np.random.Generator(np.random.PCG64(2))
+    B = rng.standard_normal((400, 12))
+    B[5, 7] = np.inf
+    with pytest.raises(P.CqrrptError):
+        P.factor_implicit(to_gpu(B), 15, 4, 1, 1e-14)
+
+
 # ---------------------------------------------------------------------------
 # Mixed precision (FP32 preconditioning solve, FP64 elsewhere) with the
 # adaptive CholeskyQR2 re-pass. Pivots and the first-stage rank come from the
