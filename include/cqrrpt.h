@@ -148,8 +148,11 @@ int cqrrpt_qrcp(double* X, int64_t ldx, int64_t d, int64_t n,
  *       non-negative diagonal, R[rank:, :] = 0.
  * J:    int64[n] output, 0-based pivots, always the full permutation.
  * rank: HOST pointer receiving k.
- * Synchronous; allocates and frees its own workspace. A rank of 0 (A = 0)
- * is a valid result. A Cholesky failure is not an error: it truncates the
+ * Synchronous, on the null stream. Its workspace is kept by the library per
+ * device between calls: the first call on a device, and a call that needs
+ * more than any earlier one, allocates it (growing, never shrinking; held
+ * until the process ends); other calls allocate nothing. Calls from several
+ * threads on one device are serialised. A rank of 0 (A = 0) is a valid result. A Cholesky failure is not an error: it truncates the
  * rank. Returns CQRRPT_ENONFINITE when A holds a NaN or Inf. */
 int cqrrpt_factor(const double* A, int64_t lda, int64_t m, int64_t n,
                   int64_t d, int32_t nnz, uint64_t seed, double tol,

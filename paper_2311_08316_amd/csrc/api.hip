@@ -141,6 +141,21 @@ CallMarks begin_marks(hipStream_t s) {
   return c;
 }
 
+// Workspace of the synchronous entry point, kept per device between calls
+// (grown when a call needs more, never shrunk; released at process exit by
+// the runtime).
+constexpr int kMaxDevices = 64;
+struct SyncCache {
+  std::mutex mu;
+  void* ws = nullptr;
+  size_t bytes = 0;
+  cqrrpt_info_t* info = nullptr;
+};
+SyncCache& sync_cache(int dev) {
+  static SyncCache caches[kMaxDevices];
+  return caches[dev];
+}
+
 #define CQ_TRY(expr)                       \
   do {                                     \
     hipError_t _e = (expr);                \
@@ -429,25 +444,38 @@ int cqrrpt_factor(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d,
   if (ldr < n) return -12;
   if (!J) return -13;
   if (!rank) return -14;
+  *rank = 0;
   if (n > kMaxN || d > kMaxD || !cqh::sketch_fits((int)d, nnz)) return CQRRPT_ELIMIT;
   const size_t wsb = make_layout(m, n, d, nnz, CQRRPT_FP64).total;
-  void* ws = nullptr;
-  cqrrpt_info_t* info = nullptr;
-  if (hipMalloc(&ws, wsb) != hipSuccess) return CQRRPT_EHIP;
-  if (hipMalloc((void**)&info, sizeof(cqrrpt_info_t)) != hipSuccess) {
-    hipFree(ws);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return CQRRPT_EHIP;
+  // One call at a time per device owns the cached workspace; the call is
+  // synchronous, so the lock is held until its results are on the host.
+  SyncCache& cache = sync_cache(dev);
+  std::lock_guard<std::mutex> lock(cache.mu);
+  if (!cache.info && hipMalloc((void**)&cache.info, sizeof(cqrrpt_info_t)) != hipSuccess) {
+    cache.info = nullptr;
     return CQRRPT_EHIP;
   }
-  int rc = cqrrpt_factor_ex(A, lda, m, n, d, nnz, seed, tol, Q, ldq, R, ldr, J, CQRRPT_FP64, ws,
-                            wsb, nullptr, info);
+  if (cache.bytes < wsb) {
+    // Grow only: later calls of this size or smaller reuse the buffer.
+    if (cache.ws) (void)hipFree(cache.ws);
+    cache.ws = nullptr;
+    cache.bytes = 0;
+    if (hipMalloc(&cache.ws, wsb) != hipSuccess) {
+      cache.ws = nullptr;
+      return CQRRPT_EHIP;
+    }
+    cache.bytes = wsb;
+  }
+  int rc = cqrrpt_factor_ex(A, lda, m, n, d, nnz, seed, tol, Q, ldq, R, ldr, J, CQRRPT_FP64,
+                            cache.ws, cache.bytes, nullptr, cache.info);
   cqrrpt_info_t h{};
   if (rc == CQRRPT_OK) {
-    if (hipMemcpy(&h, info, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) rc = CQRRPT_EHIP;
+    if (hipMemcpy(&h, cache.info, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) rc = CQRRPT_EHIP;
     else if (h.status != 0) rc = h.status;
   }
   *rank = h.rank;
-  hipFree(info);
-  hipFree(ws);
   return rc;
 }
 
