@@ -202,6 +202,31 @@ int cqrrpt_factor_implicit_ex(const double* A, int64_t lda, int64_t m, int64_t n
                               void* ws, size_t ws_bytes, void* stream,
                               cqrrpt_info_t* info);
 
+/* Allocation-free form of cqrrpt_factor_ex, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc). Same arguments and results as cqrrpt_factor_ex
+ * without ws/ws_bytes: the workspace is a static device array of
+ * CQRRPT_NOALLOC_SCRATCH_BYTES bytes inside the library (one per device,
+ * held until the process ends). The call allocates nothing and returns
+ * CQRRPT_EWORKSPACE, launching nothing, when cqrrpt_workspace_bytes(m, n, d,
+ * nnz, mode) exceeds that size (the workspace is dominated by the Gram's
+ * split partial sums, about 8 n^2 bytes per split: 30000 x 384 in FP64
+ * needs about 34 MiB, 131072 x 1024 about 355 MiB; the mixed modes add
+ * 4 m n bytes for the FP32 M_pre). Every call on
+ * one device shares that device's array: calls that overlap on one device
+ * (different streams or threads without ordering between them) race and
+ * must not be issued; calls ordered on one stream are safe. Results are
+ * bit-identical to cqrrpt_factor_ex's for the same arguments.
+ * Argument order: A lda m n d nnz seed tol Q ldq R ldr J mode stream info.
+ * Errors (nothing is launched): -1..-14 as cqrrpt_factor_ex, -16 info NULL,
+ * CQRRPT_ELIMIT, CQRRPT_EWORKSPACE, CQRRPT_EHIP (symbol lookup failed). */
+#define CQRRPT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int cqrrpt_factor_noalloc(const double* A, int64_t lda, int64_t m, int64_t n,
+                          int64_t d, int32_t nnz, uint64_t seed, double tol,
+                          double* Q, int64_t ldq, double* R, int64_t ldr,
+                          int64_t* J, cqrrpt_mode_t mode, void* stream,
+                          cqrrpt_info_t* info);
+
 /* ------------------------------------------------------------------------
  * Stage timing (diagnostics)
  * ------------------------------------------------------------------------

@@ -58,6 +58,9 @@ _SIGS = {
     "cqrrpt_factor_implicit_ex": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i32, _u64,
                                                  _dbl, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
                                                  _vp, _sz, _vp, _vp]),
+    "cqrrpt_factor_noalloc": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i32, _u64, _dbl,
+                                             _vp, _i64, _vp, _i64, _vp, ctypes.c_int, _vp,
+                                             _vp]),
     "cqrrpt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "cqrrpt_stage_timing": (ctypes.c_int, [ctypes.c_int]),
     "cqrrpt_stage_times": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
@@ -263,6 +266,29 @@ def factor_implicit(A, d, nnz, seed, tol):
     if info.status != 0:
         _check(info.status, "cqrrpt_factor_implicit_ex")
     return f.Q, f.Rpre, f.R, f.J, info
+
+
+# Size of the library's static workspace for cqrrpt_factor_noalloc
+# (CQRRPT_NOALLOC_SCRATCH_BYTES in include/cqrrpt.h).
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def factor_noalloc_into(A, d, nnz, seed, tol, Q, R, J, info_buf, mode=CQRRPT_FP64):
+    """``cqrrpt_factor_noalloc`` into caller-allocated outputs (Q m x n and
+    R n x n column-major FP64, J int64[n], info_buf uint8[sizeof info]) on
+    the current stream; the library allocates nothing."""
+    A = colmajor(A)
+    m, n = A.shape
+    for t, name in ((Q, "Q"), (R, "R"), (J, "J"), (info_buf, "info")):
+        _on_gpu(t, name)
+    if Q.shape != (m, n) or Q.stride(0) != 1 or R.shape != (n, n) or R.stride(0) != 1:
+        raise CqrrptError("Q and R must be column-major m x n and n x n")
+    if J.dtype != torch.int64 or J.numel() != n or info_buf.numel() < INFO_BYTES:
+        raise CqrrptError("J must be int64[n] and info_buf hold a cqrrpt_info_t")
+    rc = lib().cqrrpt_factor_noalloc(A.data_ptr(), _ld(A), m, n, d, nnz, seed, tol,
+                                     Q.data_ptr(), _ld(Q), R.data_ptr(), _ld(R), J.data_ptr(),
+                                     mode, _stream_handle(A.device), info_buf.data_ptr())
+    _check(rc, "cqrrpt_factor_noalloc")
 
 
 def factor_sync(A, d, nnz, seed, tol):

@@ -156,6 +156,38 @@ SyncCache& sync_cache(int dev) {
   return caches[dev];
 }
 
+}  // namespace
+
+// Device memory of cqrrpt_factor_noalloc: the factorization workspace of
+// callers that cannot allocate. Every device the library runs on holds its
+// own copy until the process ends. In host code `scratch` is only the
+// runtime's handle for the symbol; its device address comes from
+// hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[CQRRPT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+struct ScratchAddrs {
+  std::mutex mu;
+  void* ptr[kMaxDevices] = {};
+};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device, with that device current).
+int scratch_address(void** out) {
+  static ScratchAddrs a;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return CQRRPT_EHIP;
+  std::lock_guard<std::mutex> lock(a.mu);
+  if (!a.ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CQRRPT_EHIP;
+    a.ptr[dev] = p;
+  }
+  *out = a.ptr[dev];
+  return CQRRPT_OK;
+}
+
 #define CQ_TRY(expr)                       \
   do {                                     \
     hipError_t _e = (expr);                \
@@ -431,6 +463,29 @@ int cqrrpt_factor_implicit_ex(const double* A, int64_t lda, int64_t m, int64_t n
   if (!info) return -19;
   return factor_core(A, lda, m, n, d, nnz, seed, tol, M, ldm, R, ldr, J, CQRRPT_FP64, ws,
                      ws_bytes, stream, info, Rpre, ldrp);
+}
+
+int cqrrpt_factor_noalloc(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d,
+                          int32_t nnz, uint64_t seed, double tol, double* Q, int64_t ldq,
+                          double* R, int64_t ldr, int64_t* J, cqrrpt_mode_t mode, void* stream,
+                          cqrrpt_info_t* info) {
+  const int c = check_common(A, lda, m, n, d, nnz, tol);
+  if (c) return c;
+  if (!Q) return -9;
+  if (ldq < m) return -10;
+  if (!R) return -11;
+  if (ldr < n) return -12;
+  if (!J) return -13;
+  if (mode != CQRRPT_FP64 && mode != CQRRPT_MIXED && mode != CQRRPT_MIXED_CHECKED) return -14;
+  if (!info) return -16;
+  if (n > kMaxN || d > kMaxD || !cqh::sketch_fits((int)d, nnz)) return CQRRPT_ELIMIT;
+  const size_t need = make_layout(m, n, d, nnz, mode).total;
+  if (need > (size_t)CQRRPT_NOALLOC_SCRATCH_BYTES) return CQRRPT_EWORKSPACE;
+  void* ws = nullptr;
+  const int rc = scratch_address(&ws);
+  if (rc != CQRRPT_OK) return rc;
+  return factor_core(A, lda, m, n, d, nnz, seed, tol, Q, ldq, R, ldr, J, mode, ws, need, stream,
+                     info, nullptr, 0);
 }
 
 int cqrrpt_factor(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, int32_t nnz,
