@@ -1,23 +1,37 @@
-"""GPU parity at full workload sizes, in the launch configuration bench.py
-times (the same Factorization object and stream), where the oracle cannot
-run the whole path in seconds. Checked instead:
+"""GPU parity at the measured sizes, in the launch configuration bench.py
+times (a Factorization object on the current stream), against the whole
+oracle run on the host copy of the same input:
 
-  * the sketch against the oracle's sketch of the same input, within the
-    componentwise rounding bound of a p-term sum (p = largest row count of S);
-  * the pivots against the oracle's QRCP of that sketch (identical over the
-    planted rank, a permutation beyond);
-  * properties that hold at any size and pin the factors by their
-    definition: rank, ||Q^T Q - I||_2 and ||A[:,J] - Q R||_F / ||A||_F on the
-    device, R upper triangular with a positive diagonal, Q and R zero past the
-    rank, R^T R against A[:,J]^T A[:,J], and sampled rows of Q equal to the
-    corresponding rows of A[:,J] R^{-1} (solved on the host one row at a time).
+  * 131,072 x 1,024, planted rank 512 plus noise (d = 1280, nnz = 8) at the
+    two first-stage tolerances (1e-14: rank 1024, full work; 1e-9: the
+    planted rank 512), explicit and implicit Q;
+  * 1,048,576 x 512, cond 1e10 (d = 640, nnz = 8) in FP64 and in both mixed
+    modes.
+
+Element-wise bars (the oracle's factorization is the reference):
+  * ranks of both stages identical;
+  * pivots identical up to the first position where the two differ, which
+    must not come before the planted rank: past it the residual columns are
+    noise whose norms the sketch resolves only to rounding (reading 17), and
+    the rest of J must still be a permutation;
+  * R, rows 0..p-1 (p = that position) in original column order: row i of
+    the QR factor of A[:, J] depends only on J[:i+1], so these rows are
+    defined by the shared pivots. Two correct FP64 computations differ in a
+    row by about u ||A|| / ||R[i, :]|| (column-wise rounding of Householder
+    QR, large for the small trailing rows of a graded R); each row must agree
+    with the oracle to 10 times the largest row difference, over rows 0..i,
+    between the oracle and an independent Householder QR of A[:, J] (and to
+    1e-12 where that is smaller), and the whole block to 1e-12 in Frobenius
+    norm or 10 times the same reference;
+  * Q[:, :p] to max(1e-12, 100 u cond(R[:p, :p])) in Frobenius norm, and
+    column by column to 10 times the running reference difference;
+  * ||Q^T Q - I||_2 and ||A[:,J] - Q R||_F / ||A||_F on the device.
 """
 
 import sys
 
 import numpy as np
 import pytest
-import scipy.linalg as sla
 
 torch = pytest.importorskip("torch")
 
@@ -25,6 +39,8 @@ from oracle import cqrrpt_oracle as O
 from paper_2311_08316_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
 
 
 @pytest.fixture(scope="module")
@@ -46,79 +62,98 @@ def device_quality(A, Q, R, J, k):
     G = Qk.t() @ Qk
     G -= torch.eye(k, dtype=torch.float64, device=G.device)
     orth = float(torch.linalg.matrix_norm(G, ord=2)) if k else 0.0
-    AJ = A[:, J]
-    recon = float(torch.linalg.norm(AJ - Q @ R) / torch.linalg.norm(A))
-    gram = AJ[:, :k].t() @ AJ[:, :k]
-    Rk = R[:k, :k]
-    dgram = float(torch.linalg.norm(Rk.t() @ Rk - gram) / torch.linalg.norm(A) ** 2)
-    return orth, recon, dgram, AJ
+    recon = float(torch.linalg.norm(A[:, J] - Q @ R) / torch.linalg.norm(A))
+    return orth, recon
 
 
-def check_factor(A, f, k, label, orth_max=1e-12, recon_max=1e-12, rows=48):
-    Q, R, J = f.Q, f.R, f.J
-    Jn = J.cpu().numpy()
-    n = R.shape[0]
-    assert sorted(Jn.tolist()) == list(range(n)), f"{label}: J is not a permutation"
-    orth, recon, dgram, AJ = device_quality(A, Q, R, J, k)
-    Rn = R.cpu().numpy()
-    assert np.array_equal(Rn, np.triu(Rn)) and np.all(np.diag(Rn)[:k] > 0), label
-    assert not Rn[k:, :].any(), label
-    assert not bool(Q[:, k:].abs().max() > 0) if k < n else True, label
-    assert orth <= orth_max, f"{label}: orth {orth:.2e}"
-    assert recon <= recon_max, f"{label}: recon {recon:.2e}"
-    assert dgram <= 1e-12, f"{label}: R^T R vs Gram {dgram:.2e}"
-    # Sampled rows of Q against A[r, J[:k]] R[:k,:k]^{-1}.
-    rng = np.random.Generator(np.random.PCG64(7))
-    m = A.shape[0]
-    idx = np.sort(rng.choice(m, size=min(rows, m), replace=False))
-    it = torch.as_tensor(idx, device=A.device)
-    a_rows = AJ[it, :k].cpu().numpy()
-    q_rows = Q[it, :k].cpu().numpy()
-    Rk = Rn[:k, :k]
-    ref = sla.solve_triangular(Rk, a_rows.T, trans="T", lower=False).T
-    kap = np.linalg.cond(Rk)
-    dq = np.linalg.norm(q_rows - ref) / np.linalg.norm(ref)
-    assert dq <= max(1e-12, 100 * 2.0 ** -53 * kap), f"{label}: sampled Q rows {dq:.2e}"
-    say(f"  {label}: rank {k} orth {orth:.2e} recon {recon:.2e} gram {dgram:.2e} "
-        f"rowsQ {dq:.2e}")
+def by_original_column(R, J):
+    """R with its columns put back in the original column order."""
+    out = np.empty_like(R)
+    out[:, J] = R
+    return out
 
 
-def test_fullsize_131072x1024_planted(P):
-    """Benchmark workload: planted rank 512 + noise, d = 1280, nnz = 8."""
-    say("full size 131072 x 1024")
+def running_envelope(x):
+    return np.maximum.accumulate(np.asarray(x, dtype=np.float64))
+
+
+def compare_with_oracle(A_host, Qg, Rg, Jg, info, orc, label, min_shared, recon_max=1e-12):
+    """Element-wise comparison of a GPU factorization with the oracle's."""
+    m, n = A_host.shape
+    k = orc["rank"]
+    assert info.status == 0, f"{label}: status {info.status}"
+    assert info.rank == k, f"{label}: rank {info.rank} vs oracle {k}"
+    assert info.rank_stage1 == orc["rank_stage1"], f"{label}: stage-1 rank"
+    Jo = np.asarray(orc["J"])
+    assert np.array_equal(np.sort(Jg), np.arange(n)), f"{label}: J is not a permutation"
+    diff = np.flatnonzero(Jg != Jo)
+    p = int(diff[0]) if diff.size else n
+    p = min(p, k)
+    assert p >= min(min_shared, k), f"{label}: pivots differ at {p} (before {min_shared})"
+    # Reference: an independent Householder QR of A[:, J_oracle[:k]].
+    Qh, Rh = O.factor_given_pivots(A_host, Jo, k)
+    Ro = by_original_column(orc["R"], Jo)[:p]
+    Rr = by_original_column(Rh, Jo)[:p]
+    Rgp = by_original_column(Rg, Jg)[:p]
+    rn = np.linalg.norm(Ro, axis=1)
+    ref_rows = running_envelope(np.linalg.norm(Ro - Rr, axis=1) / rn)
+    row_err = np.linalg.norm(Rgp - Ro, axis=1) / rn
+    row_bound = np.maximum(1e-12, 10 * ref_rows)
+    worst = int(np.argmax(row_err / row_bound))
+    assert np.all(row_err <= row_bound), \
+        f"{label}: R row {worst}: {row_err[worst]:.2e} > {row_bound[worst]:.2e}"
+    fro_ref = np.linalg.norm(Ro - Rr) / np.linalg.norm(Ro)
+    fro = np.linalg.norm(Rgp - Ro) / np.linalg.norm(Ro)
+    assert fro <= max(1e-12, 10 * fro_ref), f"{label}: R {fro:.2e} (reference {fro_ref:.2e})"
+    Qo = orc["Q"][:, :p]
+    Qgp = Qg[:, :p]
+    kap = np.linalg.cond(orc["R"][:p, :p])
+    dQ = np.linalg.norm(Qgp - Qo) / np.linalg.norm(Qo)
+    assert dQ <= max(1e-12, 100 * U64 * kap), f"{label}: Q {dQ:.2e} (cond {kap:.2e})"
+    ref_cols = running_envelope(np.linalg.norm(Qo - Qh[:, :p], axis=0))
+    col_err = np.linalg.norm(Qgp - Qo, axis=0)
+    col_bound = np.maximum(1e-12, 10 * ref_cols)
+    worst = int(np.argmax(col_err / col_bound))
+    assert np.all(col_err <= col_bound), \
+        f"{label}: Q column {worst}: {col_err[worst]:.2e} > {col_bound[worst]:.2e}"
+    if k < n:
+        assert not Qg[:, k:].any() and not Rg[k:, :].any(), f"{label}: not zero past the rank"
+    assert np.array_equal(Rg, np.triu(Rg)) and np.all(np.diag(Rg)[:k] > 0), label
+    say(f"  {label}: rank {k} (stage 1 {info.rank_stage1}), pivots shared {p}, "
+        f"R fro {fro:.2e} (ref {fro_ref:.2e}), worst row ratio "
+        f"{float(np.max(row_err / row_bound)):.2e}, Q {dQ:.2e} (cond {kap:.2e})")
+    return p
+
+
+def test_fullsize_131072x1024_vs_oracle(P):
+    """The 131,072 x 1,024 planted-rank workload at both tolerances."""
+    say("full size 131072 x 1024 against the oracle")
     A, w = W.make_workload_gpu("fp64_131072x1024_rank512", seed=0)
     m, n, d, nnz = w["m"], w["n"], w["d"], w["nnz"]
-    # Sketch and pivots against the oracle on the same input.
-    Ah = P.sketch(A, d, nnz, 0)
-    A_host = A.cpu().numpy()
-    rows, signs = O.saso_sample(m, d, nnz, 0)
-    Ah_o = O.sketch(A_host, rows, signs, d)
-    Ah_g = Ah.cpu().numpy()
-    p = int(np.bincount(rows.ravel(), minlength=d).max())
-    absS = O.sketch(np.abs(A_host), rows, np.ones_like(signs), d)
-    bound = (2 * p + 4) * 2.0 ** -53 * absS
-    assert np.all(np.abs(Ah_g - Ah_o) <= bound + 1e-300)
-    del A_host, absS, bound
-    J_o = O.qrcp(Ah_o)[0]
-    # At the planted rank the reconstruction cannot beat the noise that the
-    # truncation drops: ||noise||_F / ||A||_F with ||noise||_F about
-    # std sqrt(m n); allow 20 times that floor.
-    floor = w["noise"] * np.sqrt(m * n) / float(torch.linalg.norm(A))
-    for tol, k_expect, recon_max in ((1e-14, n, 1e-12), (1e-9, 512, 20 * floor)):
+    A_host = np.asfortranarray(A.cpu().numpy())
+    for tol, k_expect in ((1e-14, n), (1e-9, 512)):
+        orc = O.cqrrpt(A_host, d, nnz, 0, tol)
+        assert orc["rank"] == k_expect, (tol, orc["rank"])
         f = P.Factorization(m, n, d, nnz, P.CQRRPT_FP64)
         f.run(A, 0, tol)
         info = f.info()
-        assert info.status == 0 and info.rank == k_expect, (tol, info.rank)
-        Jg = f.J.cpu().numpy()
-        assert np.array_equal(Jg[:512], np.asarray(J_o)[:512]), f"pivots differ (tol {tol})"
-        check_factor(A, f, int(info.rank), f"131072x1024 tol {tol:g}", recon_max=recon_max)
-        # Implicit Q at the same size: R and J bit-identical to the explicit
-        # call, M zero past the rank, and M_pre = Q R_pre (a product, so it
-        # holds to rounding at any size; R_pre is well conditioned).
+        Qg, Rg, Jg = f.Q.cpu().numpy(), f.R.cpu().numpy(), f.J.cpu().numpy()
+        compare_with_oracle(A_host, Qg, Rg, Jg, info, orc, f"131072x1024 tol {tol:g}", 512)
+        k = int(info.rank)
+        orth, recon = device_quality(A, f.Q, f.R, f.J, k)
+        _, recon_o = device_quality(A, torch.from_numpy(orc["Q"]).to(A.device),
+                                    torch.from_numpy(orc["R"]).to(A.device),
+                                    torch.from_numpy(np.asarray(orc["J"])).to(A.device), k)
+        say(f"  orth {orth:.2e} recon {recon:.2e} (oracle recon {recon_o:.2e})")
+        assert orth <= 1e-12
+        # At the planted rank both residuals are the dropped noise, and they
+        # differ by the rounding of Q and R (2e-6 relative seen): 0.1% margin.
+        assert recon <= max(1e-12, recon_o * (1 + 1e-3))
+        # Implicit Q: R and J the same bits as the explicit call, M zero past
+        # the rank, M_pre = Q R_pre to rounding (R_pre is well conditioned).
         fi = P.Factorization(m, n, d, nnz, P.CQRRPT_FP64, implicit=True)
         fi.run(A, 0, tol)
         ii = fi.info()
-        k = int(info.rank)
         assert ii.status == 0 and ii.rank == k
         assert torch.equal(fi.R, f.R) and torch.equal(fi.J, f.J)
         if k < n:
@@ -127,46 +162,55 @@ def test_fullsize_131072x1024_planted(P):
         dM = float(torch.linalg.norm(fi.Q[:, :k] - f.Q[:, :k] @ Rp) /
                    torch.linalg.norm(fi.Q[:, :k]))
         assert dM <= 1e-12, f"M_pre vs Q R_pre {dM:.2e} (tol {tol})"
-        say(f"  implicit tol {tol:g}: rank {k} ||M - Q R_pre|| / ||M|| {dM:.2e}")
-        del f, fi
+        say(f"  implicit tol {tol:g}: ||M - Q R_pre|| / ||M|| {dM:.2e}")
+        del f, fi, orc
 
 
-def test_fullsize_1048576x512_mixed_and_fp64(P):
-    """Mixed against FP64 on the 1,048,576 x 512 cond-1e10 workload."""
-    say("full size 1048576 x 512")
+def test_fullsize_1048576x512_vs_oracle(P):
+    """The 1,048,576 x 512, cond 1e10 workload: FP64 element-wise against the
+    oracle; both mixed modes with the oracle's pivots and rank, the FP64
+    orthogonality bar and FP32-level R and reconstruction (the preconditioning
+    solve runs in FP32; Theorem "simple stability")."""
+    say("full size 1048576 x 512 against the oracle")
     A, w = W.make_workload_gpu("mixed_1048576x512_cond1e10", seed=0)
     m, n, d, nnz, tol = w["m"], w["n"], w["d"], w["nnz"], w["tol"]
+    A_host = np.asfortranarray(A.cpu().numpy())
+    orc = O.cqrrpt(A_host, d, nnz, 0, tol)
+    assert orc["rank"] == n
     f64 = P.Factorization(m, n, d, nnz, P.CQRRPT_FP64)
     f64.run(A, 0, tol)
     i64 = f64.info()
-    assert i64.rank == n
-    check_factor(A, f64, n, "1048576x512 fp64", rows=32)
-    J64, R64 = f64.J.cpu().numpy(), f64.R.cpu().numpy()
+    compare_with_oracle(A_host, f64.Q.cpu().numpy(), f64.R.cpu().numpy(), f64.J.cpu().numpy(),
+                        i64, orc, "1048576x512 fp64", n)
+    orth, recon = device_quality(A, f64.Q, f64.R, f64.J, n)
+    say(f"  fp64: orth {orth:.2e} recon {recon:.2e}")
+    assert orth <= 1e-12 and recon <= 1e-12
     del f64
+    Ro = orc["R"]
     for mode, label in ((P.CQRRPT_MIXED, "mixed"), (P.CQRRPT_MIXED_CHECKED, "mixed checked")):
         fmx = P.Factorization(m, n, d, nnz, mode)
         fmx.run(A, 0, tol)
         imx = fmx.info()
-        # One pass reaches about 5e-14 here (R_sk is graded after pivoting and
-        # the Gram is summed with compensation): the checked mode re-passes
-        # only if its device estimate says otherwise.
-        assert imx.rank == n
+        assert imx.status == 0 and imx.rank == orc["rank"]
+        assert imx.rank_stage1 == orc["rank_stage1"]
+        assert np.array_equal(fmx.J.cpu().numpy(), orc["J"])  # FP64 sketch and QRCP
         if mode == P.CQRRPT_MIXED:
             assert imx.cholqr2_passes == 0
         else:
             assert imx.cholqr2_passes == (1 if imx.orth_est > 5e-13 else 0)
-        assert np.array_equal(fmx.J.cpu().numpy(), J64)  # same FP64 sketch and QRCP
-        orth, recon, _, _ = device_quality(A, fmx.Q, fmx.R, fmx.J, n)
-        dR = np.linalg.norm(fmx.R.cpu().numpy() - R64) / np.linalg.norm(R64)
+        orth, recon = device_quality(A, fmx.Q, fmx.R, fmx.J, n)
+        dR = np.linalg.norm(fmx.R.cpu().numpy() - Ro) / np.linalg.norm(Ro)
         say(f"  {label}: passes {imx.cholqr2_passes} orth_est {imx.orth_est:.2e} "
-            f"orth {orth:.2e} recon {recon:.2e} dR vs fp64 {dR:.2e}")
+            f"orth {orth:.2e} recon {recon:.2e} dR vs oracle {dR:.2e}")
         assert orth <= 1e-12 and recon <= 1e-5 and dR <= 1e-4
         del fmx
 
 
 def test_fullsize_share_524288x2048(P):
     """One GPU's share (m/8 rows) of the 4,194,304 x 2,048 planted-rank
-    workload: d = 2560 exercises the widest register QRCP variant."""
+    workload, by properties (the oracle's QRCP of its 2560 x 2048 sketch
+    alone takes minutes; the QRCP variant this shape selects is compared
+    with the oracle on a stored case in test_gpu_parity.py)."""
     say("share 524288 x 2048")
     A, w = W.make_workload_gpu("fp64_4194304x2048_rank1536", seed=0, m=524_288)
     m, n, d, nnz, tol = w["m"], w["n"], w["d"], w["nnz"], w["tol"]
@@ -175,4 +219,10 @@ def test_fullsize_share_524288x2048(P):
     info = f.info()
     say(f"  rank {info.rank} (stage 1 {info.rank_stage1})")
     assert info.status == 0 and info.rank == n
-    check_factor(A, f, n, "524288x2048", rows=24)
+    Jn = f.J.cpu().numpy()
+    assert np.array_equal(np.sort(Jn), np.arange(n))
+    Rn = f.R.cpu().numpy()
+    assert np.array_equal(Rn, np.triu(Rn)) and np.all(np.diag(Rn) > 0)
+    orth, recon = device_quality(A, f.Q, f.R, f.J, n)
+    say(f"  orth {orth:.2e} recon {recon:.2e}")
+    assert orth <= 1e-12 and recon <= 1e-12

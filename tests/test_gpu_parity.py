@@ -122,6 +122,16 @@ def test_sketch_parity(P, m, n, d, nnz):
     assert np.all(np.abs(S1 - So) <= bound + 1e-300)
 
 
+# Sketch shapes reaching every kernel variant: register walks with 8, 10, 12
+# and 16 target rows per thread (d up to 2048, 2560, 3072, 4096) and the LDS
+# variant past 4096 rows.
+@pytest.mark.parametrize("m,n,d,nnz", [(30000, 40, 1800, 8), (30000, 37, 2560, 8),
+                                       (20000, 33, 3000, 8), (40000, 20, 4096, 8),
+                                       (30000, 24, 5000, 8), (25000, 9, 9000, 4)])
+def test_sketch_parity_wide(P, m, n, d, nnz):
+    test_sketch_parity(P, m, n, d, nnz)
+
+
 @pytest.mark.parametrize("d,n", [(13, 10), (125, 100), (170, 130), (300, 257), (640, 512),
                                  (1500, 300), (2000, 150), (2600, 40)])
 def test_qrcp_parity_separated(P, d, n):
@@ -133,6 +143,36 @@ def test_qrcp_parity_separated(P, d, n):
     assert np.array_equal(Jg, Jo)
     assert np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro) <= 1e-13
     assert np.array_equal(Rg, np.triu(Rg))
+
+
+def test_qrcp_parity_2560x2048_stored(P):
+    """The sketch shape of the 4,194,304 x 2,048 workload (d = 2560, the widest
+    register-resident QRCP variant) against the oracle's QRCP stored in
+    tests/golden/qrcp_2560x2048_sep105.txt (written by make_qrcp_golden.py,
+    which calls only the oracle; the oracle takes minutes on this shape):
+    pivots identical, diagonal and first superdiagonal of R to 1e-12
+    relative to |R[0,0]|, and R^T R = X[:, J]^T X[:, J] on the device."""
+    import os
+    say("qrcp 2560 x 2048 (stored oracle result)")
+    path = os.path.join(os.path.dirname(__file__), "golden", "qrcp_2560x2048_sep105.txt")
+    rows = [ln.split() for ln in open(path) if not ln.startswith("#")]
+    Jo = np.array([int(r[1]) for r in rows])
+    diag_o = np.array([float.fromhex(r[2]) for r in rows])
+    sup_o = np.array([float.fromhex(r[3]) for r in rows])
+    d, n = 2560, 2048
+    X = W.column_scaled_well_separated(d, n, seed=d * 7 + n, ratio=1.05)
+    Xg = to_gpu(X)
+    Jg, Rg = P.qrcp(Xg)
+    assert np.array_equal(to_np(Jg), Jo)
+    Rn = to_np(Rg)
+    scale = abs(diag_o[0])
+    assert np.max(np.abs(np.diag(Rn) - diag_o)) <= 1e-12 * scale
+    assert np.max(np.abs(np.append(np.diag(Rn, 1), 0.0) - sup_o)) <= 1e-12 * scale
+    XJ = Xg[:, Jg]
+    dg = float(torch.linalg.norm(Rg.t() @ Rg - XJ.t() @ XJ) / torch.linalg.norm(Xg) ** 2)
+    say(f"  pivots identical, ||R^T R - X_J^T X_J|| / ||X||^2 = {dg:.2e}")
+    assert dg <= 1e-13
+    assert np.array_equal(Rn, np.triu(Rn))
 
 
 def test_qrcp_ties_zero_and_identity(P):
@@ -396,3 +436,38 @@ def test_fp64_mode_runs_no_repass(P):
     A = W.spectrum_matrix(5000, 64, W.logspaced_spectrum(64, 1e8), seed=12)
     _, _, _, info = P.factor(to_gpu(A), 80, 4, 3, 1e-14)
     assert info.cholqr2_passes == 0 and info.orth_est == 0.0
+
+
+@pytest.mark.parametrize("mode_name", ["mixed", "mixed_checked"])
+def test_mixed_rank_matches_oracle(P, mode_name):
+    """Mixed modes on inputs whose rank is decided by the rank stages: the
+    planted-rank input (first stage) and the coherent input whose Gram loses
+    positive definiteness (Cholesky failure, then the second stage). Pivots
+    and the first stage come from the FP64 sketch QRCP; the final rank must
+    equal the FP64 oracle's, and the returned Q must meet the FP64
+    orthogonality bar."""
+    mode = {"mixed": P.CQRRPT_MIXED, "mixed_checked": P.CQRRPT_MIXED_CHECKED}[mode_name]
+    s = np.zeros(96)
+    s[:40] = W.logspaced_spectrum(40, 1e3)
+    cases = [("planted", W.spectrum_matrix(6000, 96, s, seed=3), 120, 8, 9, 1e-11),
+             ("planted-loose", W.spectrum_matrix(6000, 96, s, seed=3), 120, 8, 9, 1e-6),
+             ("cholesky-failure", W.high_coherence_matrix(8000, 128, 4, boost=1e10), 128, 1, 0,
+              1e-14)]
+    for label, A, d, nnz, seed, tol in cases:
+        say(f"{mode_name} {label}")
+        orc = O.cqrrpt(A, d, nnz, seed=seed, tol=tol)
+        Qg, Rg, Jg, info = P.factor(to_gpu(A), d, nnz, seed, tol, mode=mode)
+        k = orc["rank"]
+        Qn, Rn, Jn = to_np(Qg), to_np(Rg), to_np(Jg)
+        say(f"  rank {info.rank} (oracle {k}), stage 1 {info.rank_stage1} "
+            f"(oracle {orc['rank_stage1']}), chol fail {info.chol_fail_col} "
+            f"(oracle {orc['chol_fail_col']}), passes {info.cholqr2_passes}")
+        assert info.status == 0 and info.rank_stage1 == orc["rank_stage1"]
+        assert info.rank == k, f"{label}: rank {info.rank} vs oracle {k}"
+        assert np.array_equal(Jn[:k], orc["J"][:k])
+        recon, orth = metrics(A, Qn, Rn, Jn, k)
+        recon_o, _ = metrics(A, orc["Q"], orc["R"], orc["J"], k)
+        say(f"  orth {orth:.2e} recon {recon:.2e} (oracle {recon_o:.2e})")
+        assert orth <= 1e-12
+        assert recon <= max(1e-5, 10 * recon_o)
+        assert not Qn[:, k:].any() and not Rn[k:, :].any()

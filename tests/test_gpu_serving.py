@@ -91,3 +91,28 @@ def test_server_budget_and_argument_errors(P):
     with pytest.raises(P.CqrrptError):
         srv.submit(A, 100, 4, 1, 1e-14)  # d < n
     srv.close()
+
+
+def test_server_reports_device_status(P):
+    """A request whose input holds a NaN finishes with the non-finite status
+    (copied from the device when the request retires) while the requests
+    around it succeed; the failed request's Q and R are zero."""
+    srv = P.Server(1 << 30, slots=2)
+    good = [W.serving_matrix_gpu(9000, 64, seed=21 + i) for i in range(2)]
+    bad = W.serving_matrix_gpu(9000, 64, seed=30).clone()
+    bad[123, 7] = float("nan")
+    t0 = srv.submit(good[0], 80, 4, 1, 1e-14)
+    tb = srv.submit(bad, 80, 4, 1, 1e-14)
+    t1 = srv.submit(good[1], 80, 4, 1, 1e-14)
+    with pytest.raises(P.CqrrptError, match="non-finite"):
+        srv.drain()
+    with pytest.raises(P.CqrrptError, match="non-finite"):
+        srv.poll(tb)
+    _, Qb, Rb, _, infob = srv._out[tb]
+    ib = P.CqrrptInfo.from_buffer_copy(bytes(infob.cpu().numpy().tobytes()))
+    assert ib.status == 1 and ib.rank == 0
+    assert not bool(Qb.abs().max() > 0) and not bool(Rb.abs().max() > 0)
+    for t in (t0, t1):
+        _, _, _, info = srv.result(t)
+        assert info.status == 0 and info.rank == 64
+    srv.close()
