@@ -60,8 +60,13 @@ extern "C" {
  *                         chol(G2), Q <- Q R2^{-1}, R <- R2 R) runs; the
  *                         decision is taken on the device.
  * In both mixed modes the second-stage rank bound on the diagonal of R_pre
- * is 1e6 instead of 10 (the FP32 solve can leave cond(M_pre) near
- * u_fp32 cond(A), mostly as grading that CholeskyQR tolerates). */
+ * is 1e6 instead of 10: the Sec. 3.3 bound sqrt(eps_tol/u) with u = 2^-53
+ * (the CholeskyQR lines run in FP64) and eps_tol = 1e-4, the first-pass
+ * orthogonality loss that the CholeskyQR2 re-pass still repairs. The FP32
+ * solve alone spreads diag(R_pre) to about u_fp32 cond(R_sk), which the
+ * FP64 bound 10 would cut. Hence CQRRPT_MIXED guarantees only
+ * ||Q^T Q - I||_2 <~ 1e-4 in the worst case; CQRRPT_MIXED_CHECKED guarantees
+ * the FP64 orthogonality bar. */
 typedef enum { CQRRPT_FP64 = 0, CQRRPT_MIXED = 1, CQRRPT_MIXED_CHECKED = 2 } cqrrpt_mode_t;
 
 /* Per-call diagnostics, written to DEVICE memory by cqrrpt_factor_ex and
@@ -262,8 +267,9 @@ const char* cqrrpt_stage_name(int i);
  *     out of range, -2 NULL buffer, -17 NULL ticket, -1 NULL/closing server.
  *   cqrrpt_server_poll(ticket, *done): *done = 1 once the request's work is
  *     complete on the device (its Q, R, J, info may then be read); returns
- *     the request's status (cqrrpt_factor_ex's code) once done, -2 unknown
- *     ticket.
+ *     the request's status once done: cqrrpt_factor_ex's return code, or,
+ *     if that was 0, the device-side info->status (CQRRPT_ENONFINITE,
+ *     CQRRPT_EBARRIER); -2 unknown ticket.
  *   cqrrpt_server_ticket_times(ticket, ms[3]): host steady-clock times (ms)
  *     of submission, admission and observed completion.
  *   cqrrpt_server_release(ticket): forgets a finished ticket (-3 if not

@@ -100,13 +100,14 @@ const char* const kStageNames[kStages] = {"sketch",   "qrcp",    "rank_stage1",
 // exceeds this: half the orthogonality target of 1e-12, which leaves room
 // for the estimate falling short of the norm and for rounding in G2.
 constexpr double kCholQR2Threshold = 5e-13;
-// Second-stage bound on max|diag R_pre| / min|diag R_pre| (Sec. 3.3): the
-// paper's sqrt(100) for a single FP64 CholeskyQR pass. With an FP32
-// preconditioning solve, cond(M_pre) can reach about u_fp32 cond(A) even
-// when the sketch resolves A; most of that growth follows the grading of
-// the pivoted R_sk, which CholeskyQR on an accurate FP64 Gram tolerates (the
-// checked mode re-passes where it does not), so the mixed modes accept up
-// to 1e6.
+// Second-stage bound on max|diag R_pre| / min|diag R_pre| (Sec. 3.3):
+// sqrt(eps_tol / u) with u the unit roundoff of the CholeskyQR lines and
+// eps_tol the orthogonality loss allowed there. FP64: the paper's eps_tol =
+// 100u, bound 10. Mixed modes: the CholeskyQR lines run in FP64 and form the
+// first pass of CholeskyQR2, which the re-pass repairs while that pass keeps
+// ||Q^T Q - I||_2 well below 1; eps_tol = 1e-4 gives sqrt(1e-4 / 2^-53) =
+// 9.5e5, used as 1e6. (The FP32 solve alone spreads diag(R_pre) to about
+// u_fp32 cond(R_sk), hundreds at cond 1e10, which 10 would cut.)
 constexpr double kStage2CondFp64 = 10.0;
 constexpr double kStage2CondMixed = 1e6;
 struct StageTimer {
@@ -399,9 +400,9 @@ int factor_core(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, i
   }
   mk.mark(7);
   // S10: R = R_pre R_sk[:k, :]; zero Q past the rank.
-  CQ_TRY(cqh::launch_trmm_r(G, n, Rsk, n, R, ldr, ni, k_dev, s));
-  CQ_TRY(cqh::launch_zero_cols(Q, ldq, m, ni, k_dev, s));
-  if (Rpre) CQ_TRY(cqh::launch_copy_upper(G, n, Rpre, ldrp, ni, k_dev, s));
+  CQ_TRY(cqh::launch_trmm_r(G, n, Rsk, n, R, ldr, ni, k_dev, info, s));
+  CQ_TRY(cqh::launch_zero_cols(Q, ldq, m, ni, k_dev, info, s));
+  if (Rpre) CQ_TRY(cqh::launch_copy_upper(G, n, Rpre, ldrp, ni, k_dev, info, s));
   mk.mark(8);
   if (mode == CQRRPT_MIXED_CHECKED) {
     // S11: adaptive CholeskyQR2 pass, decided on the device. G2 = Q^T Q
@@ -418,7 +419,7 @@ int factor_core(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, i
                                 INFINITY, false, pass));
     CQ_TRY(cqh::launch_cholqr2_commit(pass, k_dev, k2_dev, apply, R, ldr, Rsk, n, ni, info, s));
     CQ_TRY(cqh::launch_qform_f64(Q, ldq, Q, ldq, Winv, n, m, k_dev, info, s, apply));
-    CQ_TRY(cqh::launch_trmm_r(G, n, Rsk, n, R, ldr, ni, k_dev, s, apply));
+    CQ_TRY(cqh::launch_trmm_r(G, n, Rsk, n, R, ldr, ni, k_dev, info, s, apply));
   }
   mk.mark(9);
   return CQRRPT_OK;

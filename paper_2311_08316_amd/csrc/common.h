@@ -378,9 +378,10 @@ hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int km
                            cqrrpt_info_t* info, hipStream_t s, double cond_max = 10.0,
                            bool record = true, const int* enable = nullptr);
 
+// Kernels from here on treat k as 0 once info->status is set.
 hipError_t launch_trmm_r(const double* Rpre, int64_t ldp, const double* Rsk, int64_t ldk,
-                         double* R, int64_t ldr, int n, const int64_t* kdev, hipStream_t s,
-                         const int* enable = nullptr);
+                         double* R, int64_t ldr, int n, const int64_t* kdev,
+                         const cqrrpt_info_t* info, hipStream_t s, const int* enable = nullptr);
 // CholeskyQR2 re-pass helpers: *pass = (estimate of ||G2 - I||_2 >
 // threshold), the estimate by power iteration on the k x k upper triangle of
 // G2 (vec: 2 n doubles of scratch); then *apply = *pass and chol(G2) kept all
@@ -392,9 +393,9 @@ hipError_t launch_cholqr2_commit(const int* pass, const int64_t* k_dev, const in
                                  int* apply, const double* R, int64_t ldr, double* Rcopy,
                                  int64_t ldc, int n, cqrrpt_info_t* info, hipStream_t s);
 hipError_t launch_zero_cols(double* Q, int64_t ldq, int64_t m, int n, const int64_t* kdev,
-                            hipStream_t s);
+                            const cqrrpt_info_t* info, hipStream_t s);
 // out[:k, :k] = upper triangle of G[:k, :k], zero elsewhere in the n x n out.
 hipError_t launch_copy_upper(const double* G, int64_t ldg, double* out, int64_t ldo, int n,
-                             const int64_t* kdev, hipStream_t s);
+                             const int64_t* kdev, const cqrrpt_info_t* info, hipStream_t s);
 
 }  // namespace cqh

@@ -106,6 +106,9 @@ struct cqrrpt_server {
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> done_ev;
   std::vector<Request*> slot_req;
+  // Per slot, pinned host copy of the running request's device status word
+  // (info->status), copied on the slot's stream before its completion event.
+  int32_t* status_host = nullptr;
 
   std::mutex mu;
   std::condition_variable cv;       // wakes the scheduler
@@ -130,6 +133,9 @@ bool cqrrpt_server::retire_locked() {
     const hipError_t q = hipEventQuery(done_ev[s]);
     if (q == hipErrorNotReady) continue;
     if (q != hipSuccess && r->rc == 0) r->rc = CQRRPT_EHIP;
+    // Device-side failures (non-finite input, barrier timeout) become the
+    // request's status.
+    if (q == hipSuccess && r->rc == 0 && status_host[s] != 0) r->rc = status_host[s];
     r->t_done = now_ms();
     r->state = 2;
     arena->release(r->ws_off, r->ws_bytes);
@@ -156,9 +162,14 @@ void cqrrpt_server::admit_locked() {
     r->ws_off = off;
     r->slot = slot;
     r->t_admit = now_ms();
+    status_host[slot] = 0;
     r->rc = cqrrpt_factor_ex(r->A, r->lda, r->m, r->n, r->d, r->nnz, r->seed, r->tol, r->Q,
                              r->ldq, r->R, r->ldr, r->J, mode, base + off, r->ws_bytes,
                              streams[slot], r->info);
+    if (r->rc == CQRRPT_OK &&
+        hipMemcpyAsync(&status_host[slot], &r->info->status, sizeof(int32_t),
+                       hipMemcpyDeviceToHost, streams[slot]) != hipSuccess)
+      r->rc = CQRRPT_EHIP;
     if (r->rc == CQRRPT_OK && hipEventRecord(done_ev[slot], streams[slot]) != hipSuccess)
       r->rc = CQRRPT_EHIP;
     if (r->rc != CQRRPT_OK) {
@@ -213,6 +224,11 @@ cqrrpt_server_t* cqrrpt_server_create(size_t hbm_budget_bytes, int32_t max_slots
     delete sv;
     return nullptr;
   }
+  if (hipHostMalloc((void**)&sv->status_host, sizeof(int32_t) * max_slots, 0) != hipSuccess) {
+    (void)hipFree(sv->base);
+    delete sv;
+    return nullptr;
+  }
   sv->arena = new Arena(sv->budget);
   sv->streams.resize(max_slots);
   sv->done_ev.resize(max_slots);
@@ -225,6 +241,7 @@ cqrrpt_server_t* cqrrpt_server_create(size_t hbm_budget_bytes, int32_t max_slots
         if (sv->done_ev[t]) (void)hipEventDestroy(sv->done_ev[t]);
       }
       (void)hipFree(sv->base);
+      (void)hipHostFree(sv->status_host);
       delete sv->arena;
       delete sv;
       return nullptr;
@@ -333,6 +350,7 @@ void cqrrpt_server_destroy(cqrrpt_server_t* sv) {
     (void)hipEventDestroy(sv->done_ev[s]);
   }
   (void)hipFree(sv->base);
+  (void)hipHostFree(sv->status_host);
   for (auto& kv : sv->all) delete kv.second;
   delete sv->arena;
   delete sv;

@@ -604,8 +604,19 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
   }
 }
 
-__global__ void chol_reset_kernel(unsigned* w, int nw) {
+// Clears the barrier words and the rank output: a launch that leaves early
+// (barrier timeout) then leaves k = 0 behind, not an earlier call's value.
+__global__ void chol_reset_kernel(unsigned* w, int nw, int64_t* kout) {
   for (int i = threadIdx.x; i < nw; i += blockDim.x) w[i] = 0u;
+  if (threadIdx.x == 0) kout[0] = 0;
+}
+
+// Rank used by the kernels after the Cholesky step: 0 once the call has
+// failed (status set), and never outside [0, n].
+CQ_INLINE int64_t live_rank(const int64_t* kdev, const cqrrpt_info_t* info, int n) {
+  int64_t k = *kdev;
+  if (info && cq::ld_agent(&info->status) != 0) k = 0;
+  return k < 0 ? 0 : (k > n ? n : k);
 }
 
 // ---------------------------------------------------------------------------
@@ -617,11 +628,12 @@ __global__ void chol_reset_kernel(unsigned* w, int nw) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads)
 trmm_kernel(const double* __restrict__ P, int64_t ldp, const double* __restrict__ S, int64_t lds,
-            double* __restrict__ R, int64_t ldr, int n, const int64_t* kdev, const int* enable) {
+            double* __restrict__ R, int64_t ldr, int n, const int64_t* kdev, const int* enable,
+            const cqrrpt_info_t* info) {
   __shared__ double TA[kB * kLd];
   __shared__ double TB[kB * kLd];
   if (enable && *enable == 0) return;
-  const int64_t k = *kdev;
+  const int64_t k = live_rank(kdev, info, n);
   const int I = blockIdx.x, J = blockIdx.y;
   const int64_t i0 = (int64_t)I * kB;
   const int64_t j0 = (int64_t)J * kB;
@@ -800,8 +812,9 @@ copy_square_kernel(const double* __restrict__ src, int64_t lds, double* __restri
 // Columns k..n-1 of Q, each taken by gridDim.y-strided workgroup rows (the
 // grid does not depend on k, which is known on the device only).
 __global__ void __launch_bounds__(kThreads)
-zero_cols_kernel(double* Q, int64_t ldq, int64_t m, int n, const int64_t* kdev) {
-  for (int64_t c = *kdev + blockIdx.y; c < n; c += gridDim.y) {
+zero_cols_kernel(double* Q, int64_t ldq, int64_t m, int n, const int64_t* kdev,
+                 const cqrrpt_info_t* info) {
+  for (int64_t c = live_rank(kdev, info, n) + blockIdx.y; c < n; c += gridDim.y) {
     double* col = Q + c * ldq;
     for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < m;
          r += (int64_t)gridDim.x * kThreads)
@@ -814,9 +827,9 @@ zero_cols_kernel(double* Q, int64_t ldq, int64_t m, int n, const int64_t* kdev) 
 // workgroup per output column.
 __global__ void __launch_bounds__(kThreads)
 copy_upper_kernel(const double* __restrict__ G, int64_t ldg, double* __restrict__ out,
-                  int64_t ldo, int n, const int64_t* kdev) {
+                  int64_t ldo, int n, const int64_t* kdev, const cqrrpt_info_t* info) {
   const int64_t j = blockIdx.x;
-  const int64_t k = *kdev;
+  const int64_t k = live_rank(kdev, info, n);
   for (int64_t i = threadIdx.x; i < n; i += kThreads)
     out[i + j * ldo] = (i <= j && j < k) ? G[i + j * ldg] : 0.0;
 }
@@ -836,7 +849,7 @@ hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int km
                            const int* enable) {
   (void)kmax;
   unsigned* w = static_cast<unsigned*>(ws);
-  hipLaunchKernelGGL(chol_reset_kernel, dim3(1), dim3(64), 0, s, w, 8);
+  hipLaunchKernelGGL(chol_reset_kernel, dim3(1), dim3(64), 0, s, w, 8, k_dev);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   CholArgs a;
@@ -872,11 +885,11 @@ hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int km
 }
 
 hipError_t launch_trmm_r(const double* Rpre, int64_t ldp, const double* Rsk, int64_t ldk,
-                         double* R, int64_t ldr, int n, const int64_t* kdev, hipStream_t s,
-                         const int* enable) {
+                         double* R, int64_t ldr, int n, const int64_t* kdev,
+                         const cqrrpt_info_t* info, hipStream_t s, const int* enable) {
   const int nt = (n + kB - 1) / kB;
   hipLaunchKernelGGL(trmm_kernel, dim3(nt, nt), dim3(kThreads), 0, s, Rpre, ldp, Rsk, ldk, R, ldr,
-                     n, kdev, enable);
+                     n, kdev, enable, info);
   return hipGetLastError();
 }
 
@@ -911,19 +924,19 @@ hipError_t launch_cholqr2_commit(const int* pass, const int64_t* k_dev, const in
 }
 
 hipError_t launch_zero_cols(double* Q, int64_t ldq, int64_t m, int n, const int64_t* kdev,
-                            hipStream_t s) {
+                            const cqrrpt_info_t* info, hipStream_t s) {
   int64_t gx = (m + kThreads - 1) / kThreads;
   if (gx > 64) gx = 64;
   const int gy = n < 64 ? n : 64;
   hipLaunchKernelGGL(zero_cols_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(kThreads), 0, s, Q,
-                     ldq, m, n, kdev);
+                     ldq, m, n, kdev, info);
   return hipGetLastError();
 }
 
 hipError_t launch_copy_upper(const double* G, int64_t ldg, double* out, int64_t ldo, int n,
-                             const int64_t* kdev, hipStream_t s) {
+                             const int64_t* kdev, const cqrrpt_info_t* info, hipStream_t s) {
   hipLaunchKernelGGL(copy_upper_kernel, dim3((unsigned)n), dim3(kThreads), 0, s, G, ldg, out, ldo,
-                     n, kdev);
+                     n, kdev, info);
   return hipGetLastError();
 }
 
