@@ -1,19 +1,23 @@
 #!/usr/bin/env python3
-"""Benchmark: CQRRPT on one MI355X, FP64 (and mixed precision), reported as
-GFLOP/s normalised by 2 m n^2 with orthogonality, reconstruction and per-step
+"""Benchmark: CQRRPT on one MI355X, FP64 and mixed precision side by side,
+reported as GFLOP/s normalised by 2 m n^2 with orthogonality
+||Q^T Q - I||_2, reconstruction ||A[:,J] - Q R||_F / ||A||_F and per-step
 latency percentiles.
 
-Workload (default): m = 131,072, n = 1,024, A = U diag(s) V^T with Haar U, V,
-s geometric from 1 to 1e-10 over the first 512 entries and 0 after, plus iid
-Gaussian noise of std 1e-15; sketch d = 1,280 rows with 8 nonzeros per column;
-first-stage tolerance 1e-14 (the noise floor makes the numerical rank 1,024,
-so every step does its full work). A second run at tol = 1e-9 recovers the
-planted rank 512 and is reported beside it.
+Headline workload (default): the largest configuration that fits one GPU,
+m = 4,194,304, n = 2,048 (68.7 GB of FP64 input), A = U diag(s) V^T with Haar
+U, V, s geometric from 1 to 1e-12 over the first 1,536 entries and 0 after,
+plus iid Gaussian noise of std 1e-16; sketch d = 2,560 rows with 8 nonzeros
+per column; first-stage tolerance 1e-14 (the planted rank sits at the noise
+floor, so the numerical rank is 2,048 and every step does its full work).
+The input is built on the device block by block (CholeskyQR2 of a Gaussian
+for U), untimed.
 
 One step = one full factorization (sketch, QRCP, both rank stages,
-preconditioning solve, Gram, Cholesky, Q solve, R product) of the resident
-input. The timed region holds exactly --steps back-to-back steps bracketed by
-device synchronisation; inputs and buffers are resident in HBM beforehand.
+preconditioning solve, Gram, Cholesky, Q, R product) of the resident input,
+plus the copy of its rank to the host. The timed region holds exactly
+--steps back-to-back steps bracketed by device synchronisation, with the
+library's per-stage events off; stage times come from a separate run.
 
 Prints ONE JSON line.
 """
@@ -36,7 +40,23 @@ METRIC = ("CQRRPT GFLOP/s (2mn² norm.) FP64 vs mixed @ ‖QᵀQ−I‖; "
 PEAK_FP64_MFMA = 78.6e12
 PEAK_FP32_MFMA = 157.3e12
 PEAK_HBM = 8.0e12
-DOMINANT = "trsm_rows_kernel"
+HEADLINE = "fp64_4194304x2048_rank1536"
+
+# Matrix-core stages: (stage, kernel, algorithmic flops per launch from
+# (m, k_o, k)).
+MFMA_STAGES = (
+    ("precondition", "trsm_rows_kernel<double, double>", lambda m, ko, k: m * ko * ko),
+    ("gram", "syrk_kernel<double> + syrk_reduce_kernel", lambda m, ko, k: m * ko * (ko + 1)),
+    ("q_solve", "qform_kernel<double, double, double>", lambda m, ko, k: m * k * k),
+)
+MIXED_STAGES = (
+    ("precondition", "trsm_rows_kernel<float, float>", lambda m, ko, k: m * ko * ko,
+     PEAK_FP32_MFMA),
+    ("gram", "syrk_kernel<float> + syrk_reduce_kernel", lambda m, ko, k: m * ko * (ko + 1),
+     PEAK_FP64_MFMA),
+    ("q_solve", "qform_kernel<float, double, double>", lambda m, ko, k: m * k * k,
+     PEAK_FP64_MFMA),
+)
 
 
 def log(msg):
@@ -46,51 +66,65 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fp64_131072x1024_rank512")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=HEADLINE)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-runs", action="store_true",
-                    help="skip the planted-rank and mixed-precision runs")
-    ap.add_argument("--cpu-rows", type=int, default=131072,
-                    help="rows of the bounded sample the CPU oracle factors (the default is "
-                         "the whole 131072-row benchmark input: about 10-20 s on the host)")
-    ap.add_argument("--gaussian-input", action="store_true",
-                    help="iid Gaussian input of the workload's shape (full rank; for "
-                         "counter runs, where the QR-based generator is slow)")
-    ap.add_argument("--no-quality", action="store_true",
-                    help="skip the orthogonality/reconstruction evaluation")
-    ap.add_argument("--serving-requests", type=int, default=64,
-                    help="requests in the serving-stream run (0 skips it)")
+                    help="only the headline workload (FP64 and mixed)")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed headline run")
+    ap.add_argument("--cpu-rows", type=int, default=65536)
+    ap.add_argument("--cpu-cols", type=int, default=1024)
+    ap.add_argument("--serving-requests", type=int, default=4096,
+                    help="requests in the serving-stream runs (0 skips them)")
     ap.add_argument("--copy-calib", action="store_true",
-                    help="also run a plain 1 GiB device copy (three times), the "
-                         "reference kernel for scaling HBM byte counters")
+                    help="also run three plain 1 GiB device copies (reference kernel for "
+                         "scaling HBM byte counters)")
     return ap.parse_args()
 
 
-def quality(torch, A, f, k):
-    """||Q^T Q - I||_2 and ||A[:, J] - Q R||_F / ||A||_F, evaluated on the GPU
-    in FP64 outside the timed region."""
-    Q = f.Q[:, :k]
-    G = Q.t() @ Q
-    G -= torch.eye(k, dtype=torch.float64, device=G.device)
-    orth = float(np.max(np.abs(np.linalg.eigvalsh(G.cpu().numpy())))) if k else 0.0
-    AJ = A[:, f.J]
-    E = AJ - f.Q @ f.R
-    recon = float(torch.linalg.norm(E) / torch.linalg.norm(A))
-    return orth, recon
+# ---------------------------------------------------------------------------
+# Quality, evaluated on the GPU in FP64 outside the timed region, by row
+# blocks (the largest inputs leave no room for m x n temporaries).
+# ---------------------------------------------------------------------------
+
+def quality(torch, A, Q, R, J, k, block=1 << 18):
+    m, n = A.shape
+    dev = A.device
+    G = torch.zeros((k, k), dtype=torch.float64, device=dev)
+    e2 = torch.zeros((), dtype=torch.float64, device=dev)
+    a2 = torch.zeros((), dtype=torch.float64, device=dev)
+    for r0 in range(0, m, block):
+        r1 = min(m, r0 + block)
+        Qb = Q[r0:r1]
+        if k:
+            G += Qb[:, :k].t() @ Qb[:, :k]
+        Ab = A[r0:r1]
+        e2 += torch.linalg.norm(Ab[:, J] - Qb @ R) ** 2
+        a2 += torch.linalg.norm(Ab) ** 2
+    orth = 0.0
+    if k:
+        G -= torch.eye(k, dtype=torch.float64, device=dev)
+        orth = float(np.max(np.abs(np.linalg.eigvalsh(G.cpu().numpy()))))
+    return orth, float(torch.sqrt(e2 / a2))
 
 
-def run_mode(P, torch, A, w, mode, tol, seed, steps, warmup, want_stages=True,
-             want_quality=True, implicit=False):
+# ---------------------------------------------------------------------------
+# Timed runs
+# ---------------------------------------------------------------------------
+
+def timed(P, torch, A, w, mode, tol, seed, steps, warmup, implicit=False, f=None):
+    """--steps back-to-back factorizations, each with the copy of its rank to
+    pinned host memory, between two synchronisations; per-step HIP events on
+    the library's stream (torch's current stream) give the percentiles."""
     m, n, d, nnz = w["m"], w["n"], w["d"], w["nnz"]
-    f = P.Factorization(m, n, d, nnz, mode, implicit=implicit)
+    if f is None:
+        f = P.Factorization(m, n, d, nnz, mode, implicit=implicit)
+    rank_host = torch.empty((max(steps, 1), 1), dtype=torch.int64, pin_memory=True)
     for _ in range(warmup):
         f.run(A, seed, tol)
     torch.cuda.synchronize()
-    if want_stages:
-        P.stage_timing(steps)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
     t_start = torch.cuda.Event(enable_timing=True)
@@ -101,56 +135,61 @@ def run_mode(P, torch, A, w, mode, tol, seed, steps, warmup, want_stages=True,
     for i in range(steps):
         ev[i][0].record()
         f.run(A, seed, tol)
+        rank_host[i].copy_(f.info_buf[:8].view(torch.int64), non_blocking=True)
         ev[i][1].record()
     t_end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = t_start.elapsed_time(t_end)
     per = np.array([a.elapsed_time(b) for a, b in ev])
-    stages = None
-    if want_stages:
-        rows = [P.stage_times(i) for i in range(steps)]
-        stages = {k: float(np.mean([r[k] for r in rows])) for k in P.STAGES}
-        stages_all = rows
-        P.stage_timing(0)
-    else:
-        stages_all = None
     info = f.info()
-    k = int(info.rank)
-    orth, recon = quality(torch, A, f, k) if want_quality else (None, None)
+    assert int(rank_host[steps - 1, 0]) == int(info.rank)
     ms = total_ms / steps
     return dict(f=f, ms=ms, wall_s=wall, p50=float(np.percentile(per, 50)),
-                p99=float(np.percentile(per, 99)), min=float(per.min()), rank=k,
-                rank_stage1=int(info.rank_stage1), orth=orth, recon=recon, stages=stages,
-                stages_all=stages_all, gflops=2.0 * m * n * n / (ms * 1e-3) / 1e9,
-                passes=int(info.cholqr2_passes))
+                p99=float(np.percentile(per, 99)), min=float(per.min()),
+                max=float(per.max()), rank=int(info.rank),
+                rank_stage1=int(info.rank_stage1), passes=int(info.cholqr2_passes),
+                orth_est=float(info.orth_est), gflops=2.0 * m * n * n / (ms * 1e-3) / 1e9)
 
 
-def roofline(res, w):
-    """Dominant kernel: the FP64 triangular solve of the preconditioning step
-    (one launch per step). Algorithmic flops per launch: m k_o^2; duration
-    from the HIP events recorded around the launch on the library's stream.
-    The other matrix-core kernels are reported beside it in "others": the Q
-    product (m k^2 flops, the triangular product with R_pre^{-1}) and the
-    Gram (m k_o (k_o + 1) flops: the upper triangle with its diagonal)."""
-    m = w["m"]
-    rows = res["stages_all"]
-    ko, k = res["rank_stage1"], res["rank"]
+def stage_run(P, torch, A, f, seed, tol, steps):
+    """Per-stage HIP events (recorded by the library on its stream) over a
+    separate run of ``steps`` factorizations; mean ms per stage."""
+    torch.cuda.synchronize()
+    P.stage_timing(steps)
+    for _ in range(steps):
+        f.run(A, seed, tol)
+    rows = [P.stage_times(i) for i in range(steps)]
+    P.stage_timing(0)
+    return {k: float(np.mean([r[k] for r in rows])) for k in P.STAGES}
 
-    def rate(stage, flops):
-        t = float(np.mean([r[stage] for r in rows])) * 1e-3
-        return {"achieved": flops / t / 1e12, "frac": flops / t / PEAK_FP64_MFMA,
-                "avg_launch_ms": t * 1e3, "algorithmic_flops_per_launch": float(flops)}
 
-    main = rate("precondition", float(m) * ko * ko)
-    traffic = measured_traffic()
-    return {"kernel": DOMINANT, "bound": "mfma", "achieved": main["achieved"],
-            "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s", "frac": main["frac"],
-            "traffic": traffic, "avg_launch_ms": main["avg_launch_ms"],
-            "algorithmic_flops_per_launch": main["algorithmic_flops_per_launch"],
-            "others": {"qform_kernel<double,double,double>": rate("q_solve", float(m) * k * k),
-                       "syrk_kernel<double> + syrk_reduce_kernel":
-                           rate("gram", float(m) * ko * (ko + 1))}}
+def rooflines(stages, w, ko, k, mixed=False):
+    """Per-kernel rooflines from the stage times: algorithmic work of one
+    launch over its mean duration. Matrix-core stages in TFLOP/s against the
+    peak of their instruction type; the sketch in GB/s against HBM (it reads
+    A once: 8 m n bytes, plus 8 d n written per row chunk, not counted)."""
+    m, n, d = w["m"], w["n"], w["d"]
+    out = {}
+    table = MIXED_STAGES if mixed else tuple(s + (PEAK_FP64_MFMA,) for s in MFMA_STAGES)
+    for stage, kernel, work, peak in table:
+        t = stages[stage] * 1e-3
+        flops = float(work(m, ko, k))
+        out[stage] = {"kernel": kernel, "bound": "mfma", "unit": "TFLOP/s",
+                      "achieved": flops / t / 1e12, "peak": peak / 1e12,
+                      "frac": flops / t / peak, "avg_launch_ms": t * 1e3,
+                      "algorithmic_flops_per_launch": flops}
+    t = stages["sketch"] * 1e-3
+    byts = 8.0 * m * n
+    out["sketch"] = {"kernel": "saso_index_kernel + saso_partial_reg_kernel + saso_reduce_kernel",
+                     "bound": "hbm", "unit": "GB/s", "achieved": byts / t / 1e9,
+                     "peak": PEAK_HBM / 1e9, "frac": byts / t / PEAK_HBM,
+                     "avg_launch_ms": t * 1e3, "algorithmic_bytes_per_launch": byts}
+    qr_flops = 2.0 * d * n * n - 2.0 * n ** 3 / 3.0
+    out["qrcp"] = {"kernel": "qrcp_reg_kernel", "bound": "latency",
+                   "avg_launch_ms": stages["qrcp"], "flops": qr_flops,
+                   "achieved_tflops": qr_flops / (stages["qrcp"] * 1e-3) / 1e12}
+    return out
 
 
 def kernel_source_hash():
@@ -158,10 +197,13 @@ def kernel_source_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(stage):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, if it was taken on the current kernel source; else None."""
-    path = os.path.join(HERE, "profiles", "trsm_fp64_131072x1024_traffic.txt")
+    name = {"precondition": "trsm", "gram": "syrk", "q_solve": "qform"}.get(stage)
+    if name is None:
+        return None
+    path = os.path.join(HERE, "profiles", f"{name}_fp64_4194304x2048_traffic.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -178,12 +220,63 @@ def measured_traffic():
         return None
 
 
+def headline_roofline(roofs):
+    """The dominant kernel: the matrix-core stage with the longest launch."""
+    stage = max(("precondition", "gram", "q_solve"), key=lambda s: roofs[s]["avg_launch_ms"])
+    r = roofs[stage]
+    return {"kernel": r["kernel"], "stage": stage, "bound": "mfma", "achieved": r["achieved"],
+            "peak": r["peak"], "unit": "TFLOP/s", "frac": r["frac"],
+            "traffic": measured_traffic(stage), "avg_launch_ms": r["avg_launch_ms"],
+            "algorithmic_flops_per_launch": r["algorithmic_flops_per_launch"],
+            "others": {s: v for s, v in roofs.items() if s != stage}}
+
+
+# ---------------------------------------------------------------------------
+# Measured ceilings
+# ---------------------------------------------------------------------------
+
+def measured_peaks(P, torch):
+    n = 1 << 27  # 1 GiB of FP64
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = 0.0
+    for _ in range(5):
+        torch.cuda.synchronize()
+        e0.record()
+        P.probe_copy(src, dst)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 16.0 * n / (e0.elapsed_time(e1) * 1e-3))
+    del src, dst
+    out = torch.empty(1 << 20, dtype=torch.float64, device="cuda")
+    res = {"copy_GBps": best / 1e9, "copy_frac_of_datasheet": best / PEAK_HBM}
+    for fp64, key, peak in ((True, "mfma_f64_TFLOPs", PEAK_FP64_MFMA),
+                            (False, "mfma_f32_TFLOPs", PEAK_FP32_MFMA)):
+        rate = 0.0
+        for _ in range(3):
+            torch.cuda.synchronize()
+            e0.record()
+            fl = P.probe_mfma(out, 4000, fp64=fp64)
+            e1.record()
+            torch.cuda.synchronize()
+            rate = max(rate, fl / (e0.elapsed_time(e1) * 1e-3))
+        res[key] = rate / 1e12
+        res[key.replace("TFLOPs", "frac_of_datasheet")] = rate / peak
+    return res
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline and serving
+# ---------------------------------------------------------------------------
+
 def cpu_baseline(A_host_sample, w, seed, tol):
-    """The oracle as it stands, on a bounded row sample of the same workload."""
+    """The oracle as it stands, on a bounded sample of the headline input."""
     from oracle import cqrrpt_oracle as O
-    ms, n = A_host_sample.shape
+    ms, ns = A_host_sample.shape
+    ds = math.ceil(1.25 * ns)
     t0 = time.perf_counter()
-    out = O.cqrrpt(A_host_sample, w["d"], w["nnz"], seed, tol)
+    out = O.cqrrpt(A_host_sample, ds, w["nnz"], seed, tol)
     t = time.perf_counter() - t0
     try:
         cores = len(os.sched_getaffinity(0))
@@ -192,53 +285,72 @@ def cpu_baseline(A_host_sample, w, seed, tol):
     omp = os.environ.get("OMP_NUM_THREADS")
     if omp and omp.isdigit():
         cores = min(cores, int(omp))
-    return {"value": 2.0 * ms * n * n / t / 1e9, "unit": "GFLOP/s", "cores": cores,
+    return {"value": 2.0 * ms * ns * ns / t / 1e9, "unit": "GFLOP/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"one full oracle factorization of the first {ms} rows of the "
-                      f"benchmark input (n={n}, d={w['d']}, nnz={w['nnz']}, tol={tol}); "
-                      f"{t:.1f} s; GFLOP/s normalised by 2*{ms}*n^2",
+            "sample": f"one full oracle factorization of the leading {ms} x {ns} block of the "
+                      f"headline input (d={ds}, nnz={w['nnz']}, tol={tol}); {t:.1f} s; "
+                      f"GFLOP/s normalised by 2*{ms}*{ns}^2",
             "seconds": t, "rank": int(out["rank"])}
 
 
-def serving_run(P, torch, W, count, mode, seed, slots=4, budget_gib=64.0):
-    """Serving stream (Poisson arrivals at the recipe's rate): each request's
-    matrix is generated on the device at its arrival time and submitted to a
-    server; latency is completion minus submission (host steady clock, the
-    server's own timestamps), throughput is requests and 2mn^2 flops over
-    the span from the first submission to the last completion."""
+def serving_run(P, torch, W, count, mode, seed, slots=4, budget_gib=64.0, inflight_gib=96.0):
+    """Serving stream: Poisson arrivals at the recipe's rate; each request's
+    matrix is generated on the device at its arrival time and submitted. The
+    client holds at most ``inflight_gib`` of inputs and outputs on the
+    device; a request that arrives while the client is at that cap waits in
+    the client's queue, and its latency still counts from its scheduled
+    arrival. Latency = completion (the server's clock) - scheduled arrival;
+    throughput = requests and 2mn^2 flops over the span from the first
+    arrival to the last completion."""
     stream = W.serving_stream(count, seed=seed)
     srv = P.Server(int(budget_gib * 2 ** 30), slots=slots, mode=mode)
     live, done = [], []
+    held = [0]
 
     def collect(block):
         keep = []
-        for tk, r in live:
-            if block or srv.poll(tk):
-                if block:
-                    while not srv.poll(tk):
-                        time.sleep(1e-4)
+        for tk, r, nbytes, t_arr in live:
+            fin = srv.poll(tk)
+            if not fin and block:
+                while not srv.poll(tk):
+                    time.sleep(1e-4)
+                fin = True
+            if fin:
                 ts, ta, td = srv.times(tk)
                 _, _, _, info = srv.result(tk)
-                done.append((ts, ta, td, r, int(info.rank)))
+                done.append((t_arr, ts, ta, td, r, int(info.rank)))
+                held[0] -= nbytes
             else:
-                keep.append((tk, r))
+                keep.append((tk, r, nbytes, t_arr))
         live[:] = keep
 
     t0 = time.perf_counter()
+    clock0 = None
     for r in stream:
         wait = r["t"] - (time.perf_counter() - t0)
         if wait > 0:
             time.sleep(wait)
+        nbytes = 16 * r["m"] * r["n"]
+        while held[0] + nbytes > inflight_gib * 2 ** 30 and live:
+            collect(False)
+            time.sleep(2e-4)
         A = W.serving_matrix_gpu(r["m"], r["n"], r["seed"])
-        live.append((srv.submit(A, r["d"], r["nnz"], r["seed"], r["tol"]), r))
+        py_submit = time.perf_counter()
+        tk = srv.submit(A, r["d"], r["nnz"], r["seed"], r["tol"])
+        ts = srv.times(tk)[0]
+        if clock0 is None:
+            # Offset between the server's steady clock and perf_counter.
+            clock0 = ts - py_submit * 1e3
+        live.append((tk, r, nbytes, clock0 + (t0 + r["t"]) * 1e3))
+        held[0] += nbytes
         del A
         collect(False)
     srv.drain()
     collect(True)
     srv.close()
-    lat = np.array([td - ts for ts, ta, td, r, k in done])
-    queue = np.array([ta - ts for ts, ta, td, r, k in done])
-    span_s = (max(d[2] for d in done) - min(d[0] for d in done)) * 1e-3
+    lat = np.array([td - t_arr for t_arr, ts, ta, td, r, k in done])
+    queue = np.array([ta - t_arr for t_arr, ts, ta, td, r, k in done])
+    span_s = (max(d[3] for d in done) - min(d[0] for d in done)) * 1e-3
     flops = sum(2.0 * r["m"] * r["n"] ** 2 for *_, r, k in done)
     full_rank = sum(1 for *_, r, k in done if k == r["n"])
     return {"requests": len(done), "slots": slots,
@@ -251,13 +363,41 @@ def serving_run(P, torch, W, count, mode, seed, slots=4, budget_gib=64.0):
             "full_rank_results": full_rank}
 
 
+def summary(r):
+    keys = ("gflops", "ms", "p50", "p99", "min", "max", "rank", "rank_stage1", "passes",
+            "orth", "recon", "orth_est")
+    return {k: r[k] for k in keys if k in r}
+
+
+def run_config(P, torch, W, name, seed, steps, modes, stage_steps=2, tols=None):
+    A, w = W.make_workload_gpu(name, seed=seed)
+    torch.cuda.synchronize()
+    res = {}
+    for mode_name, mode in modes:
+        for tol in (tols or (w["tol"],)):
+            r = timed(P, torch, A, w, mode, tol, seed, steps, 1)
+            f = r.pop("f")
+            r["orth"], r["recon"] = quality(torch, A, f.Q, f.R, f.J, r["rank"])
+            st = stage_run(P, torch, A, f, seed, tol, stage_steps)
+            r["stages_ms"] = st
+            r["rooflines"] = rooflines(st, w, r["rank_stage1"], r["rank"],
+                                       mixed=mode != P.CQRRPT_FP64)
+            key = mode_name if tols is None else f"{mode_name}_tol{tol:g}"
+            res[key] = r
+            log(f"  {name} {key}: {json.dumps(summary(r))}")
+            del f
+    del A
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the factorization would shard by row blocks).",
-              file=sys.stderr)
+              "(the factorization would shard by row blocks with two all-reduces, "
+              "as DESIGN.md describes).", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2311_08316_amd as P
@@ -268,92 +408,85 @@ def main():
         sys.exit(2)
     P.lib()
     t0 = time.perf_counter()
-    if args.gaussian_input:
-        w = dict(W.WORKLOADS[args.workload])
-        gen = torch.Generator(device="cuda")
-        gen.manual_seed(args.seed)
-        A = torch.randn((w["n"], w["m"]), dtype=torch.float64, device="cuda",
-                        generator=gen).t()
-    else:
-        A, w = W.make_workload_gpu(args.workload, seed=args.seed)
+    A, w = W.make_workload_gpu(args.workload, seed=args.seed)
     torch.cuda.synchronize()
     log(f"generated {args.workload} in {time.perf_counter() - t0:.1f} s")
     m, n, d, nnz, tol = w["m"], w["n"], w["d"], w["nnz"], w["tol"]
 
-    main_res = run_mode(P, torch, A, w, P.CQRRPT_FP64, tol, args.seed, args.steps, args.warmup,
-                        want_quality=not args.no_quality)
-    log(f"fp64 tol={tol}: {main_res['ms']:.3f} ms/step, rank {main_res['rank']}, "
-        f"orth {main_res['orth']}, recon {main_res['recon']}, "
-        f"stages {json.dumps({k: round(v, 3) for k, v in main_res['stages'].items()})}")
-    roof = roofline(main_res, w)
-    log(f"roofline: {roof}")
+    # Headline: FP64.
+    main_res = timed(P, torch, A, w, P.CQRRPT_FP64, tol, args.seed, args.steps, args.warmup)
+    f = main_res.pop("f")
+    log(f"fp64: {main_res['ms']:.3f} ms/step, {main_res['gflops']:.0f} GFLOP/s, "
+        f"rank {main_res['rank']}")
+    main_res["orth"], main_res["recon"] = quality(torch, A, f.Q, f.R, f.J, main_res["rank"])
+    stages = stage_run(P, torch, A, f, args.seed, tol, 2)
+    roofs = rooflines(stages, w, main_res["rank_stage1"], main_res["rank"])
+    roof = headline_roofline(roofs)
+    log(f"fp64 quality orth {main_res['orth']:.2e} recon {main_res['recon']:.2e}; "
+        f"stages {json.dumps({k: round(v, 3) for k, v in stages.items()})}")
+    log(f"roofline: {json.dumps({k: v for k, v in roof.items() if k != 'others'})}")
+    del f
+    torch.cuda.empty_cache()
+
+    # Mixed precision on the same input.
+    mixed = None
+    if not args.no_mixed:
+        mr = timed(P, torch, A, w, P.CQRRPT_MIXED, tol, args.seed, args.steps, args.warmup)
+        fm = mr.pop("f")
+        mr["orth"], mr["recon"] = quality(torch, A, fm.Q, fm.R, fm.J, mr["rank"])
+        mst = stage_run(P, torch, A, fm, args.seed, tol, 2)
+        mixed = summary(mr)
+        mixed.update({"mode": "mixed (FP32 preconditioning solve, FP64 CholeskyQR lines)",
+                      "speedup_vs_fp64": main_res["ms"] / mr["ms"], "stages_ms": mst,
+                      "rooflines": rooflines(mst, w, mr["rank_stage1"], mr["rank"], mixed=True)})
+        log(f"mixed: {json.dumps(summary(mr))}")
+        del fm
+        torch.cuda.empty_cache()
 
     extra = {}
-    if not args.no_extra_runs:
-        steps2 = max(3, min(args.steps, 10))
-        pr = run_mode(P, torch, A, w, P.CQRRPT_FP64, 1e-9, args.seed, steps2, 1)
-        extra["planted_rank_tol1e-9"] = {
-            "gflops_2mn2": pr["gflops"], "ms_per_step": pr["ms"], "p50_ms": pr["p50"],
-            "p99_ms": pr["p99"], "rank": pr["rank"], "orth": pr["orth"], "recon": pr["recon"]}
-        log(f"planted-rank run: {extra['planted_rank_tol1e-9']}")
-        # Implicit Q (M_pre and R_pre returned, Q solve skipped) on the same
-        # input; its correctness is covered by the parity tests.
-        ir = run_mode(P, torch, A, w, P.CQRRPT_FP64, tol, args.seed, steps2, 1,
-                      want_quality=False, implicit=True)
-        extra["implicit_q_tol1e-14"] = {
-            "gflops_2mn2": ir["gflops"], "ms_per_step": ir["ms"], "p50_ms": ir["p50"],
-            "p99_ms": ir["p99"], "rank": ir["rank"],
-            "speedup_vs_explicit": main_res["ms"] / ir["ms"], "stages_ms": ir["stages"]}
-        log(f"implicit-Q run: {extra['implicit_q_tol1e-14']}")
-        del ir
-        # Mixed precision is measured on its own workload (1048576 x 512,
-        # cond 1e10, full rank) next to FP64 on the same matrix.
-        try:
-            del pr
-            A3, w3 = W.make_workload_gpu("mixed_1048576x512_cond1e10", seed=args.seed)
-            torch.cuda.synchronize()
-            runs = {}
-            for name, mode in (("fp64", P.CQRRPT_FP64), ("mixed", P.CQRRPT_MIXED),
-                               ("mixed_checked", P.CQRRPT_MIXED_CHECKED)):
-                r = run_mode(P, torch, A3, w3, mode, w3["tol"], args.seed, steps2, 1)
-                runs[name] = {
-                    "gflops_2mn2": r["gflops"], "ms_per_step": r["ms"], "p50_ms": r["p50"],
-                    "p99_ms": r["p99"], "rank": r["rank"], "orth": r["orth"],
-                    "recon": r["recon"], "cholqr2_passes": r["passes"],
-                    "stages_ms": r["stages"]}
-                del r
-            for name in ("mixed", "mixed_checked"):
-                runs[name]["speedup_vs_fp64"] = (runs["fp64"]["ms_per_step"] /
-                                                 runs[name]["ms_per_step"])
-            extra["mixed_vs_fp64_1048576x512_cond1e10"] = runs
-            log(f"mixed vs fp64 (1048576x512): {runs}")
-            del A3
-        except P.CqrrptError as exc:
-            extra["mixed_vs_fp64_1048576x512_cond1e10"] = {"error": str(exc)}
+    if not args.no_extra_runs and not args.no_mixed:
+        mc = timed(P, torch, A, w, P.CQRRPT_MIXED_CHECKED, tol, args.seed, 2, 1)
+        fc = mc.pop("f")
+        mc["orth"], mc["recon"] = quality(torch, A, fc.Q, fc.R, fc.J, mc["rank"])
+        extra["headline_mixed_checked"] = summary(mc)
+        extra["headline_mixed_checked"]["speedup_vs_fp64"] = main_res["ms"] / mc["ms"]
+        log(f"mixed checked: {json.dumps(summary(mc))}")
+        del fc
+        torch.cuda.empty_cache()
+
+    sample = None
+    if not args.no_cpu_baseline:
+        sample = np.asfortranarray(A[:min(args.cpu_rows, m), :min(args.cpu_cols, n)]
+                                   .cpu().numpy())
+    del A
+    torch.cuda.empty_cache()
+
+    peaks = measured_peaks(P, torch)
+    log(f"measured peaks: {peaks}")
 
     if not args.no_extra_runs:
-        # One GPU's share (m/8 rows) of the 4,194,304 x 2,048 workload.
-        try:
-            A5, w5 = W.make_workload_gpu("fp64_4194304x2048_rank1536", seed=args.seed,
-                                         m=524_288)
-            torch.cuda.synchronize()
-            r = run_mode(P, torch, A5, w5, P.CQRRPT_FP64, w5["tol"], args.seed, 3, 1)
-            extra["share_524288x2048_fp64"] = {
-                "gflops_2mn2": r["gflops"], "ms_per_step": r["ms"], "p50_ms": r["p50"],
-                "rank": r["rank"], "orth": r["orth"], "recon": r["recon"],
-                "stages_ms": r["stages"]}
-            log(f"share 524288x2048: {extra['share_524288x2048_fp64']}")
-            del r, A5
-        except P.CqrrptError as exc:
-            extra["share_524288x2048_fp64"] = {"error": str(exc)}
-
-    if not args.no_extra_runs and args.serving_requests > 0:
-        srv_res = {}
-        for name, mode in (("fp64", P.CQRRPT_FP64), ("mixed", P.CQRRPT_MIXED),
-                           ("mixed_checked", P.CQRRPT_MIXED_CHECKED)):
-            srv_res[name] = serving_run(P, torch, W, args.serving_requests, mode, args.seed)
-            log(f"serving ({name}): {srv_res[name]}")
-        extra["serving_stream"] = srv_res
+        fp64 = (("fp64", P.CQRRPT_FP64),)
+        all3 = fp64 + (("mixed", P.CQRRPT_MIXED), ("mixed_checked", P.CQRRPT_MIXED_CHECKED))
+        extra["fp64_10000x100_cond1e6"] = run_config(P, torch, W, "fp64_10000x100_cond1e6",
+                                                     args.seed, 200, fp64)
+        extra["fp64_131072x1024_rank512"] = run_config(
+            P, torch, W, "fp64_131072x1024_rank512", args.seed, 20, fp64, tols=(1e-14, 1e-9))
+        extra["mixed_1048576x512_cond1e10"] = run_config(
+            P, torch, W, "mixed_1048576x512_cond1e10", args.seed, 10, all3)
+        # Implicit Q on the 131072 x 1024 input.
+        A2, w2 = W.make_workload_gpu("fp64_131072x1024_rank512", seed=args.seed)
+        ir = timed(P, torch, A2, w2, P.CQRRPT_FP64, w2["tol"], args.seed, 10, 1, implicit=True)
+        ir.pop("f")
+        extra["implicit_q_131072x1024"] = summary(ir)
+        log(f"implicit Q: {json.dumps(summary(ir))}")
+        del A2
+        torch.cuda.empty_cache()
+        if args.serving_requests > 0:
+            srv = {}
+            for name, mode in (("fp64", P.CQRRPT_FP64), ("mixed", P.CQRRPT_MIXED)):
+                srv[name] = serving_run(P, torch, W, args.serving_requests, mode, args.seed)
+                log(f"serving ({name}): {srv[name]}")
+            extra["serving_stream"] = srv
 
     if args.copy_calib:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -366,11 +499,8 @@ def main():
         del src, dst
 
     cpu = None
-    if not args.no_cpu_baseline:
-        rows = min(args.cpu_rows, m)
-        A_s = A[:rows].cpu().numpy()
-        A_s = np.asfortranarray(A_s)
-        cpu = cpu_baseline(A_s, w, args.seed, tol)
+    if sample is not None:
+        cpu = cpu_baseline(sample, w, args.seed, tol)
         log(f"cpu baseline: {cpu}")
 
     out = {
@@ -385,17 +515,20 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic-gaussian" if args.gaussian_input else "synthetic",
+        "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "d": d, "nnz": nnz, "tol": tol,
                    "seed": args.seed, "mode": "fp64"},
         "p50_ms": main_res["p50"],
         "p99_ms": main_res["p99"],
         "min_ms": main_res["min"],
+        "max_ms": main_res["max"],
         "rank": main_res["rank"],
         "orth": main_res["orth"],
         "recon": main_res["recon"],
-        "stages_ms": main_res["stages"],
+        "stages_ms": stages,
         "roofline": roof,
+        "mixed": mixed,
+        "measured_peaks": peaks,
         "cpu_baseline": cpu,
         "extra_runs": extra,
     }

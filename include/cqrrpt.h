@@ -293,6 +293,24 @@ int cqrrpt_server_release(cqrrpt_server_t* server, uint64_t ticket);
 int cqrrpt_server_drain(cqrrpt_server_t* server);
 void cqrrpt_server_destroy(cqrrpt_server_t* server);
 
+/* ------------------------------------------------------------------------
+ * Hardware ceilings (diagnostics for roofline figures; not part of the
+ * factorization)
+ * ------------------------------------------------------------------------
+ * cqrrpt_probe_copy: dst[i] = src[i], i < n (n even, both device, 16-byte
+ *   aligned), a streaming copy: 16 n bytes of HBM traffic. Stream-ordered.
+ *   Errors: -1/-2 NULL, -3 n odd or < 2.
+ * cqrrpt_probe_mfma: a loop of independent 16x16x4 matrix-core instructions
+ *   (fp64 != 0: FP64, else FP32 inputs and accumulation) on 8 workgroups of
+ *   4 waves per compute unit, iters rounds of 8 per wave; one value per wave
+ *   goes to the device array out (out_len >= 32 x compute units); *flops
+ *   (host) receives the launch's floating-point operation count.
+ *   Stream-ordered. Errors: -2 iters < 1, -3 NULL out, -4 out too short,
+ *   -5 NULL flops. */
+int cqrrpt_probe_copy(const double* src, double* dst, int64_t n, void* stream);
+int cqrrpt_probe_mfma(int fp64, int iters, double* out, int64_t out_len, int64_t* flops,
+                      void* stream);
+
 /* Human-readable name of a return code. */
 const char* cqrrpt_status_string(int code);
 

@@ -61,6 +61,9 @@ _SIGS = {
     "cqrrpt_factor_noalloc": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i32, _u64, _dbl,
                                              _vp, _i64, _vp, _i64, _vp, ctypes.c_int, _vp,
                                              _vp]),
+    "cqrrpt_probe_copy": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
+    "cqrrpt_probe_mfma": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _vp, _i64,
+                                         ctypes.POINTER(_i64), _vp]),
     "cqrrpt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "cqrrpt_stage_timing": (ctypes.c_int, [ctypes.c_int]),
     "cqrrpt_stage_times": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
@@ -186,6 +189,29 @@ def stage_times(slot):
     buf = (ctypes.c_double * len(STAGES))()
     _check(lib().cqrrpt_stage_times(slot, buf), "cqrrpt_stage_times")
     return dict(zip(STAGES, list(buf)))
+
+
+def probe_copy(src, dst):
+    """Streaming device copy dst <- src (FP64, same length) on the current
+    stream (the library's bandwidth probe)."""
+    _on_gpu(src, "src")
+    _on_gpu(dst, "dst")
+    if src.numel() != dst.numel() or src.dtype != torch.float64 or dst.dtype != torch.float64:
+        raise CqrrptError("src and dst must be FP64 of the same length")
+    _check(lib().cqrrpt_probe_copy(src.data_ptr(), dst.data_ptr(), src.numel(),
+                                   _stream_handle(src.device)), "cqrrpt_probe_copy")
+
+
+def probe_mfma(out, iters, fp64=True):
+    """Matrix-core throughput loop on the current stream; returns its flop
+    count. ``out`` is an FP64 device scratch array of at least 32 values
+    per compute unit."""
+    _on_gpu(out, "out")
+    flops = ctypes.c_int64(0)
+    _check(lib().cqrrpt_probe_mfma(1 if fp64 else 0, iters, out.data_ptr(), out.numel(),
+                                   ctypes.byref(flops), _stream_handle(out.device)),
+           "cqrrpt_probe_mfma")
+    return flops.value
 
 
 def workspace_bytes(m, n, d, nnz, mode=CQRRPT_FP64):

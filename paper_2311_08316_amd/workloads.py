@@ -144,8 +144,60 @@ def spectrum_matrix_gpu(m, n, s, seed, noise_std=0.0, device="cuda"):
     return A.t().contiguous().t()
 
 
+def spectrum_matrix_gpu_blocked(m, n, s, seed, noise_std=0.0, device="cuda",
+                                block_rows=1 << 18):
+    """``spectrum_matrix_gpu`` for matrices too large for a device QR next to
+    their own copies: the same distribution, built in the output buffer one
+    row block at a time. U is the Q factor of a Gaussian G by CholeskyQR2
+    (G = U R with R = R2 R1, R1 = chol(G^T G), R2 = chol(U1^T U1),
+    U1 = G R1^{-1}); R has a positive diagonal, so U is Haar distributed
+    (the positive-diagonal QR of a Gaussian). Then A = U (diag(s) V^T), V Haar
+    from the host, plus noise. Every row block draws its Gaussians from its
+    own seeded generator; the n x n factorizations run on the host in FP64.
+    Peak device memory: the m x n output plus one block."""
+    import torch
+
+    A = torch.empty((n, m), dtype=torch.float64, device=device).t()
+    blocks = [(r, min(m, r + block_rows)) for r in range(0, m, block_rows)]
+    gen = torch.Generator(device=device)
+    for b, (r0, r1) in enumerate(blocks):
+        gen.manual_seed(int(seed) * 1_000_003 + b)
+        A[r0:r1] = torch.randn((n, r1 - r0), dtype=torch.float64, device=device,
+                               generator=gen).t()
+
+    def gram():
+        G = torch.zeros((n, n), dtype=torch.float64, device=device)
+        for r0, r1 in blocks:
+            X = A[r0:r1]
+            G += X.t() @ X
+        return G.cpu().numpy()
+
+    def right_multiply(W):
+        Wd = torch.as_tensor(W, device=device)
+        for r0, r1 in blocks:
+            A[r0:r1] = A[r0:r1] @ Wd
+
+    for _ in range(2):
+        G = gram()
+        R = np.linalg.cholesky((G + G.T) * 0.5).T  # upper, positive diagonal
+        right_multiply(np.linalg.inv(R))
+    V = haar_orthonormal(_rng(seed + 7_919), n, n)
+    right_multiply(np.asarray(s, dtype=np.float64)[:, None] * V.T)
+    if noise_std:
+        for b, (r0, r1) in enumerate(blocks):
+            gen.manual_seed(int(seed) * 1_000_003 + len(blocks) + b)
+            A[r0:r1] += noise_std * torch.randn((n, r1 - r0), dtype=torch.float64,
+                                                device=device, generator=gen).t()
+    return A
+
+
+# Above this many elements the device workloads are built block by block.
+BLOCKED_ELEMENTS = 1 << 31
+
+
 def make_workload_gpu(name, seed=0, m=None, device="cuda"):
-    """Named workload built on the device (see ``spectrum_matrix_gpu``)."""
+    """Named workload built on the device (``spectrum_matrix_gpu``, or the
+    block-by-block ``spectrum_matrix_gpu_blocked`` for the largest sizes)."""
     w = dict(WORKLOADS[name])
     if m is not None:
         w["m"] = m
@@ -154,6 +206,8 @@ def make_workload_gpu(name, seed=0, m=None, device="cuda"):
         s = logspaced_spectrum(n, w["cond"])
     else:
         s = planted_spectrum(n, w["rank"], w["cond"])
+    if w["m"] * n > BLOCKED_ELEMENTS:
+        return spectrum_matrix_gpu_blocked(w["m"], n, s, seed, w["noise"], device), w
     return spectrum_matrix_gpu(w["m"], n, s, seed, w["noise"], device), w
 
 
