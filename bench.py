@@ -46,7 +46,7 @@ HEADLINE = "fp64_4194304x2048_rank1536"
 # (m, k_o, k)).
 MFMA_STAGES = (
     ("precondition", "trsm_rows_kernel<double, double>", lambda m, ko, k: m * ko * ko),
-    ("gram", "syrk_kernel<double> + syrk_reduce_kernel", lambda m, ko, k: m * ko * (ko + 1)),
+    ("gram", "gram128_kernel + gram128_reduce_kernel", lambda m, ko, k: m * ko * (ko + 1)),
     ("q_solve", "qform_kernel<double, double, double>", lambda m, ko, k: m * k * k),
 )
 MIXED_STAGES = (
@@ -200,7 +200,7 @@ def kernel_source_hash():
 def measured_traffic(stage):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, if it was taken on the current kernel source; else None."""
-    name = {"precondition": "trsm", "gram": "syrk", "q_solve": "qform"}.get(stage)
+    name = {"precondition": "trsm", "gram": "gram128", "q_solve": "qform"}.get(stage)
     if name is None:
         return None
     path = os.path.join(HERE, "profiles", f"{name}_fp64_4194304x2048_traffic.txt")

@@ -377,7 +377,7 @@ int factor_core(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, i
     CQ_TRY(cqh::launch_trsm_f64(A, lda, J, Q, ldq, Rsk, n, m, ko_dev, ni, tpack, info, s));
     mk.mark(4);
     // S6: G = M_pre^T M_pre.
-    CQ_TRY(cqh::launch_syrk<double>(Q, ldq, m, ko_dev, ni, Gp, G, n, info, s));
+    CQ_TRY(cqh::launch_gram_f64(Q, ldq, m, ko_dev, ni, Gp, G, n, info, s));
   } else {
     float* M32 = reinterpret_cast<float*>(base + L.off_mpre32);
     CQ_TRY(cqh::launch_trsm_mixed(A, lda, J, M32, m, Rsk, n, m, ko_dev, ni, tpack, info, s));

@@ -361,6 +361,12 @@ hipError_t launch_qform_f32in(const float* M, int64_t ldm, double* Q, int64_t ld
                               const cqrrpt_info_t* info, hipStream_t s);
 
 int syrk_splits(int64_t m, int kmax);
+int gram_splits(int64_t m, int kmax);
+// FP64 Gram G = X^T X (upper triangle, leading k x k) with 128 x 128 tiles
+// and plain FP64 sums (the FP64 mode's Gram); partials as for launch_syrk.
+hipError_t launch_gram_f64(const double* X, int64_t ldx, int64_t m, const int64_t* kdev,
+                           int kmax, double* partials, double* G, int64_t ldg,
+                           const cqrrpt_info_t* info, hipStream_t s);
 size_t syrk_ws_bytes(int64_t m, int kmax);
 template <typename T>
 hipError_t launch_syrk(const T* X, int64_t ldx, int64_t m, const int64_t* kdev, int kmax,

@@ -245,7 +245,6 @@ saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, in
   for (int i = 0; i < T; ++i)
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[i][c] = 0.0;
-
   // Sub-chunk sb's tile of A, segment table and entry list are loaded into
   // registers one sub-chunk ahead (all loads of a sub-chunk issued back to
   // back), then stored to LDS after the previous walk. Fixed per-thread load
@@ -313,29 +312,43 @@ saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, in
     __syncthreads();
     if (sb + 1 < sb1) prefetch(sb + 1);
 
-    // Walk this thread's T target segments in lock step: at slot e every
-    // target with more than e entries adds its e-th entry (ascending source
-    // row), so the T targets' LDS reads overlap and no target switch needs a
-    // branch.
-    int base[T], len[T];
-    int lmax = 0;
+    // Walk this thread's T target segments as one flat list (segment after
+    // segment, each in ascending source row): slot e belongs to target i,
+    // the segment holding position e, found without branches. Every slot
+    // does useful work in every lane until the lane's list ends, and each
+    // row read serves one target: the row is added with weight +-1 to target
+    // i and with weight 0 to the others (fma with a zero weight leaves an
+    // accumulator unchanged), so the accumulators stay in registers with
+    // static indices.
+    int base[T], pre[T + 1];
+    pre[0] = 0;
 #pragma unroll
     for (int i = 0; i < T; ++i) {
       const int r = tid + kThreads * i;
       base[i] = r < d ? sseg[r] : 0;
-      len[i] = r < d ? sseg[r + 1] - base[i] : 0;
-      lmax = len[i] > lmax ? len[i] : lmax;
+      pre[i + 1] = pre[i] + (r < d ? sseg[r + 1] - base[i] : 0);
     }
-    for (int e = 0; e < lmax; ++e) {
+    const int total = pre[T];
+    for (int e = 0; e < total; ++e) {
+      int seg_i = 0;
+      int off = base[0] + e;
+#pragma unroll
+      for (int q = 1; q < T; ++q) {
+        const bool past = e >= pre[q];
+        seg_i += past ? 1 : 0;
+        off = past ? base[q] + (e - pre[q]) : off;
+      }
+      const unsigned v = slst[off];
+      const double* row = tile + (v >> 1) * kRowPitch;
+      const double sg = (v & 1u) ? -1.0 : 1.0;
+      double rv[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) rv[c] = row[c];
 #pragma unroll
       for (int i = 0; i < T; ++i) {
-        if (e < len[i]) {
-          const unsigned v = slst[base[i] + e];
-          const double* row = tile + (v >> 1) * kRowPitch;
-          const double sg = (v & 1u) ? -1.0 : 1.0;
+        const double w = i == seg_i ? sg : 0.0;
 #pragma unroll
-          for (int c = 0; c < NC; ++c) acc[i][c] += sg * row[c];
-        }
+        for (int c = 0; c < NC; ++c) acc[i][c] = fma(w, rv[c], acc[i][c]);
       }
     }
   }

@@ -65,7 +65,10 @@ constexpr int kTileSz = kKB * kSLd;
 // matrix) and the operand reads (K = lane / 16, column = lane % 16) then
 // spread over the banks; a [K][column] layout at a pitch of kSLd put the
 // stores on one bank in eight.
-constexpr int kWLd = 20;
+#ifndef CQ_WLD
+#define CQ_WLD 20
+#endif
+constexpr int kWLd = CQ_WLD;
 constexpr int kWTile = kPW * kWLd;
 constexpr int kQStage = kTileSz + kWTile;  // one staging buffer: B/X tile, then R tile
 constexpr int kTrsmLds = 2 * kQStage;
@@ -712,6 +715,187 @@ syrk_reduce_kernel(const double* __restrict__ P, int nsplit, int tiles, const in
   G[i + j * ldg] = s + c;
 }
 
+// ---------------------------------------------------------------------------
+// FP64 Gram with 128 x 128 output tiles (the FP64 mode's Gram). Four waves of
+// 64 x 64 (4 x 4 tiles of 16 x 16 on the matrix cores, two operand reads per
+// four instructions), 16 rows per staging step in double-buffered LDS with
+// one register stage of prefetch, split over row ranges numbered so that
+// the tiles of one split share an XCD and its L2 (as the 64 x 64 kernel).
+// Plain FP64 accumulation over the split's rows (no compensated chunks): in
+// FP64 mode the Gram's rounding is not amplified past the 1e-12 bars
+// (measured orthogonality ~1e-14). On diagonal tiles the wave owning the
+// strictly lower 64 x 64 block does no products. Partial tiles are written
+// row-major (16 consecutive lanes store 128 contiguous bytes).
+// ---------------------------------------------------------------------------
+constexpr int kGT = 128;          // output tile
+constexpr int kGK = 16;           // rows per staging step
+constexpr int kGLd = kGK + 1;     // LDS pitch of a staged column
+constexpr int kGStage = kGT * kGLd;
+constexpr size_t kGramLdsBytes = (size_t)4 * kGStage * 8;  // 2 buffers x (I, J)
+
+__global__ void __launch_bounds__(kThreads, 2)
+gram128_kernel(const double* __restrict__ X, int64_t ldx, int64_t m, const int64_t* kdev,
+               int64_t rows_per_split, int tiles, double* __restrict__ P,
+               const cqrrpt_info_t* info) {
+  extern __shared__ double gsm[];
+  if (info->status != 0) return;
+  const int64_t k = *kdev;
+#ifndef CQ_GRAM_ORDER
+#define CQ_GRAM_ORDER 0
+#endif
+#if CQ_GRAM_ORDER == 0
+  const int xcd = blockIdx.x % kXcds;
+  const int slot = blockIdx.x / kXcds;
+  const int split = (slot / tiles) * kXcds + xcd;
+  const int t = slot % tiles;
+#else
+  const int split = blockIdx.x / tiles;
+  const int t = blockIdx.x % tiles;
+#endif
+  int J = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((J + 1) * (J + 2) / 2 <= t) ++J;
+  while (J * (J + 1) / 2 > t) --J;
+  const int I = t - J * (J + 1) / 2;
+  const int64_t i0 = (int64_t)I * kGT;
+  const int64_t j0 = (int64_t)J * kGT;
+  if (j0 >= k) return;
+  const bool diag = I == J;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int l16 = lane & 15;
+  const int lq = lane >> 4;
+  const int wr = wave >> 1;
+  const int wc = wave & 1;
+  // On a diagonal tile the (1, 0) wave's block lies below the diagonal.
+  const bool idle = diag && wr > wc;
+  const int64_t r0 = (int64_t)split * rows_per_split;
+  const int64_t r1 = (r0 + rows_per_split) < m ? (r0 + rows_per_split) : m;
+
+  d4_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = d4_t{0, 0, 0, 0};
+
+  // Thread (row rr, column cl + 16 q): 16 consecutive lanes read the 16
+  // rows (128 contiguous bytes) of one column.
+  const int rr = tid & (kGK - 1);
+  const int cl = tid >> 4;
+  double vi[8], vj[8];
+  bool rok = true;
+  auto load = [&](int64_t rs) {
+    const int64_t row = rs + rr;
+    rok = row < r1;
+    const double* xr = X + (rok ? row : r1 - 1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t ci = i0 + cl + 16 * q;
+      vi[q] = xr[(ci < k ? ci : k - 1) * ldx];
+    }
+    if (!diag) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t cj = j0 + cl + 16 * q;
+        vj[q] = xr[(cj < k ? cj : k - 1) * ldx];
+      }
+    }
+  };
+  auto store = [&](int buf) {
+    double* XI = gsm + (2 * buf) * kGStage;
+    double* XJ = XI + kGStage;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int c = cl + 16 * q;
+      XI[c * kGLd + rr] = (rok && i0 + c < k) ? vi[q] : 0.0;
+    }
+    if (!diag) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int c = cl + 16 * q;
+        XJ[c * kGLd + rr] = (rok && j0 + c < k) ? vj[q] : 0.0;
+      }
+    }
+  };
+  auto multiply = [&](int buf) {
+    const double* XI = gsm + (2 * buf) * kGStage;
+    const double* XJ = diag ? XI : XI + kGStage;
+#pragma unroll
+    for (int s = 0; s < kGK / 4; ++s) {
+      double af[4], bf[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) af[a] = XI[(64 * wr + 16 * a + l16) * kGLd + 4 * s + lq];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bf[b] = XJ[(64 * wc + 16 * b + l16) * kGLd + 4 * s + lq];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = mfma(af[a], bf[b], acc[a][b]);
+    }
+  };
+
+  if (r0 < r1) {
+    load(r0);
+    store(0);
+    __syncthreads();
+    int it = 0;
+    for (int64_t rs = r0; rs < r1; rs += kGK, ++it) {
+      const int buf = it & 1;
+      const bool more = rs + kGK < r1;
+      if (more) load(rs + kGK);
+      if (!idle) multiply(buf);
+      if (more) store(buf ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // Partial tile (split, t), 128 x 128 row-major.
+  double* Pout = P + ((int64_t)split * tiles + t) * (kGT * kGT);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int li = 64 * wr + 16 * a + acc_row<double>(lq, r);
+        const int lj = 64 * wc + 16 * b + l16;
+        Pout[li * kGT + lj] = acc[a][b][r];
+      }
+}
+
+// G[i, j] (i <= j < k) = sum over splits, in split order, of the partial
+// tiles. One workgroup row per tile; lj runs fastest, so the reads of a
+// split are coalesced.
+__global__ void __launch_bounds__(kThreads)
+gram128_reduce_kernel(const double* __restrict__ P, int nsplit, int tiles, const int64_t* kdev,
+                      double* __restrict__ G, int64_t ldg, const cqrrpt_info_t* info) {
+  if (info->status != 0) return;
+  const int64_t k = *kdev;
+  const int t = blockIdx.y;
+  int J = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((J + 1) * (J + 2) / 2 <= t) ++J;
+  while (J * (J + 1) / 2 > t) --J;
+  const int I = t - J * (J + 1) / 2;
+  const int loc = blockIdx.x * kThreads + threadIdx.x;
+  const int li = loc / kGT, lj = loc % kGT;
+  const int64_t i = (int64_t)I * kGT + li;
+  const int64_t j = (int64_t)J * kGT + lj;
+  if (i > j || j >= k) return;
+  const int64_t stride = (int64_t)tiles * (kGT * kGT);
+  const double* p = P + (int64_t)t * (kGT * kGT) + loc;
+  double s = 0.0;
+  int q = 0;
+  for (; q + 8 <= nsplit; q += 8) {
+    double y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) y[u] = p[(int64_t)(q + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += y[u];
+  }
+  for (; q < nsplit; ++q) s += p[(int64_t)q * stride];
+  G[i + j * ldg] = s;
+}
+
 }  // namespace
 
 namespace cqh {
@@ -774,9 +958,55 @@ int syrk_splits(int64_t m, int kmax) {
   return best;
 }
 
+// Splits of the 128 x 128 Gram: as syrk_splits for its tile count and
+// workgroup size, partials within 1.5 GB.
+int gram_splits(int64_t m, int kmax) {
+  const int nt = (kmax + kGT - 1) / kGT;
+  const int64_t tiles = (int64_t)nt * (nt + 1) / 2;
+  const int64_t slots = 2 * (int64_t)device_info().num_cu / kXcds;
+  const int64_t tile_bytes = (int64_t)kGT * kGT * 8;
+  int best = kXcds;
+  double best_cost = 0.0;
+  for (int ns = kXcds; ns <= 64; ns += kXcds) {
+    if (ns > kXcds && ((m + ns - 1) / ns < 1024 || ns * tiles * tile_bytes > (1536ll << 20)))
+      break;
+    const int64_t items = tiles * ns / kXcds;
+    const double cost = (double)((items + slots - 1) / slots) / ns;
+    if (ns == kXcds || cost < best_cost * 0.999) {
+      best = ns;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
 size_t syrk_ws_bytes(int64_t m, int kmax) {
   const int nt = (kmax + kST - 1) / kST;
-  return (size_t)syrk_splits(m, kmax) * nt * (nt + 1) / 2 * kST * kST * 8;
+  const size_t small = (size_t)syrk_splits(m, kmax) * nt * (nt + 1) / 2 * kST * kST * 8;
+  const int ng = (kmax + kGT - 1) / kGT;
+  const size_t big = (size_t)gram_splits(m, kmax) * ng * (ng + 1) / 2 * kGT * kGT * 8;
+  return small > big ? small : big;
+}
+
+hipError_t launch_gram_f64(const double* X, int64_t ldx, int64_t m, const int64_t* kdev,
+                           int kmax, double* partials, double* G, int64_t ldg,
+                           const cqrrpt_info_t* info, hipStream_t s) {
+  const int nsplit = gram_splits(m, kmax);
+  int64_t rps = (m + nsplit - 1) / nsplit;
+  rps = (rps + kGK - 1) / kGK * kGK;
+  const int nt = (kmax + kGT - 1) / kGT;
+  const int tiles = nt * (nt + 1) / 2;
+  hipError_t e = hipFuncSetAttribute((const void*)gram128_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)kGramLdsBytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gram128_kernel, dim3((unsigned)(tiles * nsplit)), dim3(kThreads),
+                     kGramLdsBytes, s, X, ldx, m, kdev, rps, tiles, partials, info);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gram128_reduce_kernel, dim3(kGT * kGT / kThreads, (unsigned)tiles),
+                     dim3(kThreads), 0, s, partials, nsplit, tiles, kdev, G, ldg, info);
+  return hipGetLastError();
 }
 
 template <typename T>
