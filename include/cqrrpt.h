@@ -207,6 +207,27 @@ int cqrrpt_factor_implicit_ex(const double* A, int64_t lda, int64_t m, int64_t n
                               void* ws, size_t ws_bytes, void* stream,
                               cqrrpt_info_t* info);
 
+/* The unpivoted precursor of CQRRPT (Sec. 1.3, "Randomized preconditioning
+ * for CholeskyQR"): sketch Ahat = S A with the SASO above, unpivoted
+ * Householder QR Ahat = Q_sk R_sk, M_pre = A R_sk^{-1}, R_pre = chol(M_pre^T
+ * M_pre), Q = M_pre R_pre^{-1}, R = R_pre R_sk. FP64. Like plain
+ * CholeskyQR it needs A of full rank: there is no pivoting and no rank
+ * detection; a Cholesky failure (A numerically rank deficient) truncates the
+ * result at the failing column, reported in info->chol_fail_col and
+ * info->rank (Q and R zero past it); an exactly zero trailing block of R_sk
+ * is dropped the same way.
+ * Arguments as cqrrpt_factor_ex without tol, J and mode (workspace:
+ * cqrrpt_workspace_bytes(m, n, d, nnz, CQRRPT_FP64)). Argument order:
+ * A lda m n d nnz seed Q ldq R ldr ws ws_bytes stream info.
+ * Errors (nothing is launched): -1..-6 as cqrrpt_factor_ex, -8 Q NULL,
+ * -9 ldq < m, -10 R NULL, -11 ldr < n, -12 ws NULL, -15 info NULL,
+ * CQRRPT_ELIMIT, CQRRPT_EWORKSPACE. */
+int cqrrpt_sketched_cholqr_ex(const double* A, int64_t lda, int64_t m, int64_t n,
+                              int64_t d, int32_t nnz, uint64_t seed,
+                              double* Q, int64_t ldq, double* R, int64_t ldr,
+                              void* ws, size_t ws_bytes, void* stream,
+                              cqrrpt_info_t* info);
+
 /* Allocation-free form of cqrrpt_factor_ex, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, hosts
  * that forbid hipMalloc). Same arguments and results as cqrrpt_factor_ex

@@ -29,6 +29,9 @@ What is computed, step by step, in the paper's order (Algorithm 2,
   S9  Q = M_pre[:, :k] R_pre[:k, :k]^{-1}                          (Alg. 2, Q-factor)
   S10 R = R_pre[:k, :k] R_sk[:k, :]                                (Alg. 2, undo preconditioning)
 
+Also here: the unpivoted precursor of Sec. 1.3 (``sketched_cholqr``): sketch,
+unpivoted QR of the sketch, precondition, CholeskyQR, for full-rank inputs.
+
 Readings where the paper is silent (each is listed in the design doc as well):
   * random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the seed,
     one counter stream per column of S; Floyd's subset sampler (Bentley and
@@ -430,3 +433,74 @@ def factor_given_pivots(A, J, k):
     Q = np.zeros((m, n))
     Q[:, :k] = Qk
     return Q, R
+
+
+# ---------------------------------------------------------------------------
+# The unpivoted precursor (Sec. 1.3, "Randomized preconditioning for
+# CholeskyQR"): sketch, QR of the sketch, precondition, CholeskyQR.
+# ---------------------------------------------------------------------------
+
+def _positive_diag_r(X):
+    """Upper-triangular factor of an unpivoted QR of X (d x n, d >= n) with
+    a non-negative diagonal: LAPACK's Householder QR (numpy, a library
+    primitive) with the rows of negative diagonal negated, which makes it the
+    unique R of a full-rank X."""
+    R = np.linalg.qr(np.asarray(X, dtype=np.float64), mode="r")
+    n = X.shape[1]
+    R = np.triu(R[:n, :n])
+    flip = np.diag(R) < 0.0
+    R[flip, :] = -R[flip, :]
+    return R
+
+
+def sketched_cholqr_core(A, S):
+    """The five steps of Sec. 1.3 with an explicit sketching operator S:
+    M_sk = S M; [Q_sk, R_sk] = qr(M_sk); M_pre = M R_sk^{-1};
+    G = M_pre^T M_pre, R_pre = chol(G); Q = M_pre R_pre^{-1}, R = R_pre R_sk.
+    M must have full rank. A Cholesky failure at 0-based column j truncates
+    the result to j columns (Q and R zero past them; rank = j); an exactly
+    zero trailing block of R_sk (first-stage bound with tolerance 0) is
+    dropped before the solve.
+    Returns dict(Q, R, rank, rank_stage1, chol_fail_col, Rsk, Rpre, status)."""
+    A = np.asarray(A, dtype=np.float64)
+    return _sketched_cholqr_from_sketch(A, np.asarray(S @ A, dtype=np.float64))
+
+
+def _sketched_cholqr_from_sketch(A, Ahat):
+    m, n = A.shape
+    out = dict(Q=np.zeros((m, n)), R=np.zeros((n, n)), rank=0, rank_stage1=0,
+               chol_fail_col=-1, status=STATUS_OK, Rsk=None, Rpre=None)
+    if not np.all(np.isfinite(Ahat)):
+        out["status"] = STATUS_NONFINITE
+        return out
+    Rsk = _positive_diag_r(Ahat)
+    out["Rsk"] = Rsk
+    k_o = rank_stage1(Rsk, 0.0)
+    out["rank_stage1"] = k_o
+    if k_o == 0:
+        return out
+    Mpre = scipy.linalg.solve_triangular(Rsk[:k_o, :k_o], A[:, :k_o].T,
+                                         trans="T", lower=False).T
+    G = Mpre.T @ Mpre
+    Rpre, k = cholesky_upper(G)
+    if k < k_o:
+        out["chol_fail_col"] = k
+    out["rank"] = k
+    if k == 0:
+        return out
+    Rp = Rpre[:k, :k]
+    out["Q"][:, :k] = scipy.linalg.solve_triangular(Rp, Mpre[:, :k].T, trans="T",
+                                                    lower=False).T
+    out["R"][:k, :] = Rp @ Rsk[:k, :]
+    out["Rpre"] = Rp
+    return out
+
+
+def sketched_cholqr(A, d, nnz, seed):
+    """The precursor with the SASO of ``cqrrpt`` (same rows and signs)."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    if not (1 <= n <= m and n <= d <= m):
+        raise ValueError("need 1 <= n <= d <= m")
+    rows, signs = saso_sample(m, d, nnz, seed)
+    return _sketched_cholqr_from_sketch(A, sketch(A, rows, signs, d))

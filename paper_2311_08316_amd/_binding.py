@@ -61,6 +61,8 @@ _SIGS = {
     "cqrrpt_factor_noalloc": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i32, _u64, _dbl,
                                              _vp, _i64, _vp, _i64, _vp, ctypes.c_int, _vp,
                                              _vp]),
+    "cqrrpt_sketched_cholqr_ex": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i32, _u64,
+                                                 _vp, _i64, _vp, _i64, _vp, _sz, _vp, _vp]),
     "cqrrpt_probe_copy": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
     "cqrrpt_probe_mfma": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _vp, _i64,
                                          ctypes.POINTER(_i64), _vp]),
@@ -315,6 +317,28 @@ def factor_noalloc_into(A, d, nnz, seed, tol, Q, R, J, info_buf, mode=CQRRPT_FP6
                                      Q.data_ptr(), _ld(Q), R.data_ptr(), _ld(R), J.data_ptr(),
                                      mode, _stream_handle(A.device), info_buf.data_ptr())
     _check(rc, "cqrrpt_factor_noalloc")
+
+
+def sketched_cholqr(A, d, nnz, seed):
+    """The unpivoted precursor of Sec. 1.3 (``cqrrpt_sketched_cholqr_ex``):
+    returns (Q, R, info) with A = Q R for full-rank A (no pivoting)."""
+    A = colmajor(A)
+    m, n = A.shape
+    Q = empty_colmajor(m, n, A.device)
+    R = empty_colmajor(n, n, A.device)
+    wsb = workspace_bytes(m, n, d, nnz, CQRRPT_FP64)
+    if wsb == 0:
+        raise CqrrptError("unsupported sizes")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=A.device)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
+    rc = lib().cqrrpt_sketched_cholqr_ex(A.data_ptr(), _ld(A), m, n, d, nnz, seed, Q.data_ptr(),
+                                         m, R.data_ptr(), n, ws.data_ptr(), wsb,
+                                         _stream_handle(A.device), info.data_ptr())
+    _check(rc, "cqrrpt_sketched_cholqr_ex")
+    inf = CqrrptInfo.from_buffer_copy(bytes(info.cpu().numpy().tobytes()))
+    if inf.status != 0:
+        _check(inf.status, "cqrrpt_sketched_cholqr_ex")
+    return Q, R, inf
 
 
 def factor_sync(A, d, nnz, seed, tol):

@@ -50,7 +50,7 @@ struct Layout {
   cqh::SketchPlan sk;
   cqh::QrcpPlan qr;
   size_t off_ahat, off_sketch, off_qrcp, off_rsk, off_rn2, off_bmax, off_k, off_syrkp, off_g,
-      off_winv, off_chol, off_tpack, off_mpre32, total;
+      off_winv, off_chol, off_tpack, off_jtmp, off_mpre32, total;
 };
 
 Layout make_layout(int64_t m, int64_t n, int64_t d, int nnz, cqrrpt_mode_t mode) {
@@ -70,6 +70,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, int nnz, cqrrpt_mode_t mode)
   L.off_winv = o; o += align256((size_t)n * n * 8);
   L.off_chol = o; o += align256(cqh::chol_ws_bytes((int)n));
   L.off_tpack = o; o += align256(cqh::trsm_pack_bytes((int)n));
+  L.off_jtmp = o; o += align256((size_t)n * 8);
   L.off_mpre32 = o;
   if (mode != CQRRPT_FP64) o += align256((size_t)m * n * 4);
   L.total = o;
@@ -338,7 +339,7 @@ namespace {
 int factor_core(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, int32_t nnz,
                 uint64_t seed, double tol, double* Q, int64_t ldq, double* R, int64_t ldr,
                 int64_t* J, cqrrpt_mode_t mode, void* ws, size_t ws_bytes, void* stream,
-                cqrrpt_info_t* info, double* Rpre, int64_t ldrp) {
+                cqrrpt_info_t* info, double* Rpre, int64_t ldrp, bool precursor = false) {
   if (n > kMaxN || d > kMaxD || !cqh::sketch_fits((int)d, nnz)) return CQRRPT_ELIMIT;
   const Layout L = make_layout(m, n, d, nnz, mode);
   if (ws_bytes < L.total) return CQRRPT_EWORKSPACE;
@@ -366,11 +367,15 @@ int factor_core(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, i
   CQ_TRY(cqh::launch_sketch(L.sk, A, lda, m, n, (int)d, nnz, seed, Ahat, d, base + L.off_sketch,
                             info, s));
   mk.mark(1);
-  // S3: QRCP of the sketch -> J, R_sk.
-  CQ_TRY(cqh::launch_qrcp(L.qr, Ahat, d, (int)d, ni, J, Rsk, n, base + L.off_qrcp, info, s));
+  // S3: QRCP of the sketch -> J, R_sk (the precursor of Sec. 1.3: plain
+  // Householder QR, J = identity, kept in the workspace).
+  if (precursor) J = reinterpret_cast<int64_t*>(base + L.off_jtmp);
+  CQ_TRY(cqh::launch_qrcp(L.qr, Ahat, d, (int)d, ni, J, Rsk, n, base + L.off_qrcp, info, s,
+                          precursor));
   mk.mark(2);
-  // S4: first-stage rank k_o.
-  CQ_TRY(cqh::launch_rank_stage1(Rsk, n, ni, tol, rn2, bmax, ko_dev, info, s));
+  // S4: first-stage rank k_o (the precursor assumes full rank: tolerance 0
+  // only drops an exactly zero trailing block).
+  CQ_TRY(cqh::launch_rank_stage1(Rsk, n, ni, precursor ? 0.0 : tol, rn2, bmax, ko_dev, info, s));
   mk.mark(3);
   if (mode == CQRRPT_FP64) {
     // S5: M_pre = A[:, J[:k_o]] R_sk^{-1}, written into Q.
@@ -386,8 +391,10 @@ int factor_core(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, i
   }
   mk.mark(5);
   // S7-S8: R_pre = chol(G) in place, second-stage rank k; Winv = R_pre^{-1}.
+  // The precursor has no second stage (a Cholesky failure still truncates).
   CQ_TRY(cqh::launch_cholesky(G, n, ko_dev, ni, k_dev, Winv, n, base + L.off_chol, info, s,
-                              mode == CQRRPT_FP64 ? kStage2CondFp64 : kStage2CondMixed));
+                              precursor ? INFINITY
+                              : mode == CQRRPT_FP64 ? kStage2CondFp64 : kStage2CondMixed));
   mk.mark(6);
   // S9: Q = M_pre[:, :k] R_pre^{-1}, as the product with Winv[:k, :k].
   if (Rpre) {
@@ -464,6 +471,22 @@ int cqrrpt_factor_implicit_ex(const double* A, int64_t lda, int64_t m, int64_t n
   if (!info) return -19;
   return factor_core(A, lda, m, n, d, nnz, seed, tol, M, ldm, R, ldr, J, CQRRPT_FP64, ws,
                      ws_bytes, stream, info, Rpre, ldrp);
+}
+
+int cqrrpt_sketched_cholqr_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d,
+                              int32_t nnz, uint64_t seed, double* Q, int64_t ldq, double* R,
+                              int64_t ldr, void* ws, size_t ws_bytes, void* stream,
+                              cqrrpt_info_t* info) {
+  const int c = check_common(A, lda, m, n, d, nnz, 0.0);
+  if (c) return c;
+  if (!Q) return -8;
+  if (ldq < m) return -9;
+  if (!R) return -10;
+  if (ldr < n) return -11;
+  if (!ws) return -12;
+  if (!info) return -15;
+  return factor_core(A, lda, m, n, d, nnz, seed, 0.0, Q, ldq, R, ldr, nullptr, CQRRPT_FP64, ws,
+                     ws_bytes, stream, info, nullptr, 0, true);
 }
 
 int cqrrpt_factor_noalloc(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d,

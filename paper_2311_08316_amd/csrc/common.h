@@ -328,8 +328,10 @@ struct QrcpPlan {
 };
 QrcpPlan plan_qrcp(int d, int n);
 size_t qrcp_ws_bytes(const QrcpPlan& p);
+// nopivot: column i at step i (unpivoted Householder QR, J = identity).
 hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, int64_t* J,
-                       double* R, int64_t ldr, void* ws, cqrrpt_info_t* info, hipStream_t s);
+                       double* R, int64_t ldr, void* ws, cqrrpt_info_t* info, hipStream_t s,
+                       bool nopivot = false);
 
 hipError_t launch_rank_stage1(const double* R, int64_t ldr, int n, double tol, double* rn2,
                               double* bmax, int64_t* kdev, cqrrpt_info_t* info, hipStream_t s);

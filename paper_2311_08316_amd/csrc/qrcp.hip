@@ -57,6 +57,7 @@ struct QrcpArgs {
   uint64_t* fcand;   // register variant: [2][G][4] flagged words
   int* abort;
   cqrrpt_info_t* info;
+  int nopivot;       // 1: column i at step i (unpivoted Householder QR)
 };
 
 // Spin until *tag == want (acquire). Bounded: on timeout raise *abort.
@@ -144,11 +145,13 @@ __global__ void __launch_bounds__(kThreads) qrcp_kernel(QrcpArgs a) {
       bv = s_norm[lane];
       bs = lane;
     }
+    // Without pivoting the smallest alive slot (= smallest column) wins.
+    const bool np = a.nopivot != 0;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
       const double ov = __shfl_xor(bv, off, cq::kWave);
       const int os = __shfl_xor(bs, off, cq::kWave);
-      if (ov > bv || (ov == bv && os < bs)) {
+      if (np ? os < bs : (ov > bv || (ov == bv && os < bs))) {
         bv = ov;
         bs = os;
       }
@@ -218,6 +221,11 @@ __global__ void __launch_bounds__(kThreads) qrcp_kernel(QrcpArgs a) {
         nup = s_rv[w];
         p = s_rc[w];
       }
+    }
+    if (a.nopivot) {
+      // Column i, published by its owner with its norm.
+      p = i;
+      nup = cq::ld_agent(&a.cand_val[par * G + i % G]);
     }
     const int owner = p % G;
     const int len = d - i;
@@ -399,9 +407,10 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
     const uint32_t flag = (uint32_t)stp + 1u;
     double bv = -1.0;
     int bc = INT_MAX;
+    const bool np = a.nopivot != 0;
 #pragma unroll
     for (int k = 0; k < CPW; ++k)
-      if (alive[k] && cq::beats(nrm[k], colid[k], bv, bc)) {
+      if (alive[k] && (np ? colid[k] < bc : cq::beats(nrm[k], colid[k], bv, bc))) {
         bv = nrm[k];
         bc = colid[k];
       }
@@ -410,16 +419,30 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
       s_rc[wave] = bc;
     }
     __syncthreads();
-    // Workgroup best: lanes 0..W-1 take the W wave bests and combine them
-    // with lane permutes (a total order, so the pairing does not matter).
-    double wv = lane < W ? s_rv[lane] : -2.0;
-    int wc = lane < W ? s_rc[lane] : INT_MAX;
-    cq::argmax_step<0xB1>(wv, wc);
-    if constexpr (W > 2) cq::argmax_step<0x4E>(wv, wc);
-    if constexpr (W > 4) cq::argmax_step<0x141>(wv, wc);
-    if constexpr (W > 8) cq::argmax_step<0x140>(wv, wc);
-    wv = cq::readlane_d(wv, 0);
-    wc = __builtin_amdgcn_readlane(wc, 0);
+    double wv;
+    int wc;
+    if (np) {
+      // Without pivoting: the workgroup's smallest alive column.
+      wv = -1.0;
+      wc = INT_MAX;
+      for (int w = 0; w < W; ++w)
+        if (s_rc[w] < wc) {
+          wc = s_rc[w];
+          wv = s_rv[w];
+        }
+    } else {
+      // Workgroup best: lanes 0..W-1 take the W wave bests and combine them
+      // with lane permutes (a total order, so the pairing does not matter).
+      wv = lane < W ? s_rv[lane] : -2.0;
+      wc = lane < W ? s_rc[lane] : INT_MAX;
+      cq::argmax_step<0xB1>(wv, wc);
+      if constexpr (W > 2) cq::argmax_step<0x4E>(wv, wc);
+      if constexpr (W > 4) cq::argmax_step<0x141>(wv, wc);
+      if constexpr (W > 8) cq::argmax_step<0x140>(wv, wc);
+      wv = cq::readlane_d(wv, 0);
+      wc = __builtin_amdgcn_readlane(wc, 0);
+    }
+
     // The candidate goes out first: readers poll the staged rows' own flags,
     // so the order of the two does not matter for correctness, and the
     // candidate does not queue behind the rows.
@@ -516,6 +539,17 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
         }
       }
       cq::wave_argmax_dpp(bv, bc);
+      if (a.nopivot) {
+        // Column i, from the slot of its owner workgroup.
+        const int os = i % G;
+        const int ol = os % cq::kWave, oq = os / cq::kWave;
+        double ov = 0.0;
+#pragma unroll
+        for (int s2 = 0; s2 < KS; ++s2)
+          if (s2 == oq) ov = cq::join_halves(cw[s2][0], cw[s2][1]);
+        bv = cq::readlane_d(ov, ol);
+        bc = i;
+      }
       if (bad) s_bad = 1;
       if (lane == 0) {
         s_nup = bv;
@@ -877,7 +911,8 @@ size_t qrcp_ws_bytes(const QrcpPlan& p) {
 }
 
 hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, int64_t* J,
-                       double* R, int64_t ldr, void* ws, cqrrpt_info_t* info, hipStream_t s) {
+                       double* R, int64_t ldr, void* ws, cqrrpt_info_t* info, hipStream_t s,
+                       bool nopivot) {
   if (!p.reg && (p.cols_per_block > kMaxCols || p.nblocks > kThreads))
     return hipErrorInvalidValue;
   const int G = p.nblocks;
@@ -901,6 +936,7 @@ hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, 
   a.fcand = reinterpret_cast<uint64_t*>(base + p.stage_bytes);
   a.abort = reinterpret_cast<int*>(base + p.stage_bytes + p.cand_bytes + p.beta_bytes);
   a.info = info;
+  a.nopivot = nopivot ? 1 : 0;
 
   // Zero the exchange words (all flagged words, or the tags) and the abort
   // word before the cooperative launch.

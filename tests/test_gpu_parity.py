@@ -471,3 +471,43 @@ def test_mixed_rank_matches_oracle(P, mode_name):
         assert orth <= 1e-12
         assert recon <= max(1e-5, 10 * recon_o)
         assert not Qn[:, k:].any() and not Rn[k:, :].any()
+
+
+# ---------------------------------------------------------------------------
+# The unpivoted precursor of Sec. 1.3 (cqrrpt_sketched_cholqr_ex) against the
+# oracle's five steps: no pivots, R to 1e-12, Q to the cond-scaled bound.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n,d,nnz,cond", [(3000, 60, 75, 4, 1e6), (20003, 200, 250, 8, 1e8),
+                                            (12001, 700, 875, 4, 1e6), (500, 1, 2, 1, 1.0),
+                                            (40000, 1024, 1280, 8, 1e10)])
+def test_sketched_cholqr_parity(P, m, n, d, nnz, cond):
+    say(f"precursor m={m} n={n} d={d} nnz={nnz} cond={cond:.0e}")
+    A = W.spectrum_matrix(m, n, W.logspaced_spectrum(n, cond), seed=m % 89)
+    orc = O.sketched_cholqr(A, d, nnz, seed=4)
+    Qg, Rg, info = P.sketched_cholqr(to_gpu(A), d, nnz, 4)
+    Qn, Rn = to_np(Qg), to_np(Rg)
+    assert info.rank == orc["rank"] == n and info.rank_stage1 == n
+    assert info.chol_fail_col == -1
+    dR = np.linalg.norm(Rn - orc["R"]) / np.linalg.norm(orc["R"])
+    kap = np.linalg.cond(orc["R"])
+    dQ = np.linalg.norm(Qn - orc["Q"]) / np.linalg.norm(orc["Q"])
+    recon = np.linalg.norm(A - Qn @ Rn) / np.linalg.norm(A)
+    orth = np.linalg.norm(Qn.T @ Qn - np.eye(n), 2)
+    say(f"  dR {dR:.2e} dQ {dQ:.2e} (cond {kap:.1e}) recon {recon:.2e} orth {orth:.2e}")
+    assert dR <= 1e-12 and dQ <= max(1e-12, 100 * U64 * kap)
+    assert recon <= 1e-12 and orth <= 1e-12
+    assert np.array_equal(Rn, np.triu(Rn)) and np.all(np.diag(Rn) > 0)
+
+
+def test_sketched_cholqr_zero_column(P):
+    """An exactly zero last column: rank n - 1 from the zero trailing block,
+    as in the oracle, with Q and R zero past it."""
+    A = W.spectrum_matrix(2000, 20, W.logspaced_spectrum(20, 1e2), seed=8)
+    A[:, 19] = 0.0
+    orc = O.sketched_cholqr(A, 25, 4, seed=1)
+    Qg, Rg, info = P.sketched_cholqr(to_gpu(A), 25, 4, 1)
+    Qn, Rn = to_np(Qg), to_np(Rg)
+    assert info.rank == orc["rank"] == 19 and info.rank_stage1 == 19
+    assert not Qn[:, 19:].any() and not Rn[19:, :].any()
+    assert np.linalg.norm(Rn - orc["R"]) / np.linalg.norm(orc["R"]) <= 1e-12

@@ -458,3 +458,80 @@ def test_path_stage2_truncates_ill_conditioned_preconditioner():
     Q, R, J = out["Q"], out["R"], out["J"]
     assert np.linalg.norm(A[:, J] - Q @ R) / np.linalg.norm(A) < 1e-14
     assert np.linalg.norm(Q[:, :7].T @ Q[:, :7] - np.eye(7), 2) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# The unpivoted precursor (Sec. 1.3)
+# ---------------------------------------------------------------------------
+
+def test_precursor_with_signed_permutation_is_plain_qr():
+    # S a signed permutation: the sketch is an orthogonal image of A, so its
+    # R factor is A's own (positive diagonal), M_pre is orthonormal and
+    # R_pre = I; the result is the positive-diagonal Householder QR of A,
+    # computed here by modified Gram-Schmidt applied twice (a different
+    # method that reaches the same unique factors).
+    rng = np.random.Generator(np.random.PCG64(21))
+    A = W.spectrum_matrix(150, 25, W.logspaced_spectrum(25, 1e3), seed=22)
+    perm = rng.permutation(150)
+    sg = rng.choice([-1.0, 1.0], size=150)
+    S = np.zeros((150, 150))
+    S[perm, np.arange(150)] = sg
+    out = O.sketched_cholqr_core(A, S)
+    assert out["rank"] == 25 and out["chol_fail_col"] == -1
+    assert np.allclose(out["Rpre"], np.eye(25), atol=1e-13)
+    Q = A.copy()
+    R = np.zeros((25, 25))
+    for _ in range(2):
+        Rp = np.zeros((25, 25))
+        for j in range(25):
+            for i in range(j):
+                Rp[i, j] = Q[:, i] @ Q[:, j]
+                Q[:, j] -= Rp[i, j] * Q[:, i]
+            Rp[j, j] = np.linalg.norm(Q[:, j])
+            Q[:, j] /= Rp[j, j]
+        R = Rp @ R if R.any() else Rp
+    assert np.allclose(out["R"], R, rtol=0, atol=1e-13 * np.abs(R).max())
+    assert np.allclose(out["Q"], Q, rtol=0, atol=1e-11)
+
+
+def test_precursor_definition_and_invariants():
+    # Full rank: Q orthonormal, A = Q R, R upper with a positive diagonal, and
+    # (Q, R) the unique positive-diagonal QR of A (no pivoting: J = identity).
+    A = _c1_small(m=4000, n=50, cond=1e6, seed=7)
+    out = O.sketched_cholqr(A, d=63, nnz=4, seed=3)
+    Q, R = out["Q"], out["R"]
+    assert out["rank"] == 50 and out["status"] == 0
+    assert np.linalg.norm(A - Q @ R) / np.linalg.norm(A) < 1e-14
+    assert np.linalg.norm(Q.T @ Q - np.eye(50), 2) < 1e-13
+    assert np.array_equal(R, np.triu(R)) and np.all(np.diag(R) > 0)
+    Qd, Rd = O.factor_given_pivots(A, np.arange(50), 50)
+    assert np.linalg.norm(R - Rd) / np.linalg.norm(Rd) < 1e-13
+    # M_pre is sketch-orthonormal: its condition number is the sketch's
+    # distortion on range(A), modest for d = 1.25 n (13 here).
+    assert np.linalg.cond(out["Rpre"]) < 30
+
+
+def test_precursor_rank_deficient_inputs():
+    # The precursor needs full rank (Sec. 1.3). An exactly zero last column
+    # gives an exactly zero last row of R_sk, which the zero-tolerance first
+    # stage drops: rank n - 1, Q and R zero past it, the rest exact.
+    A = _c1_small(m=2000, n=20, cond=1e2, seed=8)
+    Z = A.copy()
+    Z[:, 19] = 0.0
+    out = O.sketched_cholqr(Z, d=25, nnz=4, seed=1)
+    assert out["rank_stage1"] == 19 and out["rank"] == 19
+    Q, R = out["Q"], out["R"]
+    assert not Q[:, 19:].any() and not R[19:, :].any()
+    assert np.linalg.norm(Z - Q @ R) / np.linalg.norm(Z) < 1e-14
+    # A duplicated column leaves a rounding-level pivot in R_sk and nothing
+    # detects it: the precursor returns all 20 columns, the 13th of Q being
+    # orthonormalised rounding noise and R[12, 12] at the rounding level,
+    # while CQRRPT's pivoting and rank stages return rank 19.
+    D = A.copy()
+    D[:, 12] = D[:, 5]
+    out = O.sketched_cholqr(D, d=25, nnz=4, seed=1)
+    assert out["rank"] == 20
+    assert np.linalg.norm(D - out["Q"] @ out["R"]) / np.linalg.norm(D) < 1e-13
+    assert abs(out["R"][12, 12]) < 1e-12 * np.abs(out["R"]).max()
+    piv = O.cqrrpt(D, d=25, nnz=4, seed=1, tol=1e-14)
+    assert piv["rank"] == 19
