@@ -57,6 +57,14 @@ MIXED_STAGES = (
     ("q_solve", "qform_kernel<float, double, double>", lambda m, ko, k: m * k * k,
      PEAK_FP64_MFMA),
 )
+FP32_LINES_STAGES = (
+    ("precondition", "trsm_rows_kernel<float, float>", lambda m, ko, k: m * ko * ko,
+     PEAK_FP32_MFMA),
+    ("gram", "gram128_kernel<float, float> + gram128_reduce_kernel",
+     lambda m, ko, k: m * ko * (ko + 1), PEAK_FP32_MFMA),
+    ("q_solve", "qform_kernel<float, double, float>", lambda m, ko, k: m * k * k,
+     PEAK_FP32_MFMA),
+)
 
 
 def log(msg):
@@ -164,14 +172,15 @@ def stage_run(P, torch, A, f, seed, tol, steps):
     return {k: float(np.mean([r[k] for r in rows])) for k in P.STAGES}
 
 
-def rooflines(stages, w, ko, k, mixed=False):
+def rooflines(stages, w, ko, k, mixed=False, fp32_lines=False):
     """Per-kernel rooflines from the stage times: algorithmic work of one
     launch over its mean duration. Matrix-core stages in TFLOP/s against the
     peak of their instruction type; the sketch in GB/s against HBM (it reads
     A once: 8 m n bytes, plus 8 d n written per row chunk, not counted)."""
     m, n, d = w["m"], w["n"], w["d"]
     out = {}
-    table = MIXED_STAGES if mixed else tuple(s + (PEAK_FP64_MFMA,) for s in MFMA_STAGES)
+    table = (FP32_LINES_STAGES if fp32_lines else MIXED_STAGES if mixed else
+             tuple(s + (PEAK_FP64_MFMA,) for s in MFMA_STAGES))
     for stage, kernel, work, peak in table:
         t = stages[stage] * 1e-3
         flops = float(work(m, ko, k))
@@ -363,6 +372,68 @@ def serving_run(P, torch, W, count, mode, seed, slots=4, budget_gib=64.0, inflig
             "full_rank_results": full_rank}
 
 
+def gamma_sweep(P, torch, seed):
+    """Sec. 5.2.1: runtime against the embedding dimension d = gamma n on
+    Gaussian 131,072 x n inputs (nnz = 4, tol 1e-14), for the shapes whose
+    sketch QRCP fits the register-resident kernel (d <= 2560)."""
+    out = {}
+    m = 131_072
+    for n, gammas in ((1024, (1.0, 1.25, 1.5, 2.0, 2.5)), (2048, (1.0, 1.25))):
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed + n)
+        A = torch.randn((n, m), dtype=torch.float64, device="cuda", generator=gen).t()
+        w = dict(m=m, n=n, nnz=4)
+        for g in gammas:
+            w["d"] = math.ceil(g * n)
+            r = timed(P, torch, A, w, P.CQRRPT_FP64, 1e-14, seed, 5, 1)
+            f = r.pop("f")
+            st = stage_run(P, torch, A, f, seed, 1e-14, 1)
+            out[f"{m}x{n}_gamma{g:g}"] = {"d": w["d"], "ms": r["ms"], "rank": r["rank"],
+                                          "sketch_ms": st["sketch"], "qrcp_ms": st["qrcp"]}
+            del f
+        del A
+        torch.cuda.empty_cache()
+    log(f"gamma sweep: {json.dumps(out)}")
+    return out
+
+
+def high_coherence_study(P, torch, W, seed, m=32_768, n=500):
+    """Sec. 4.2 on a smaller instance of the same construction (stacked
+    identities, n rows scaled by 1e10, rotated by a random orthogonal
+    matrix): pivot quality of CQRRPT with (gamma, nnz) = (1, 1) and
+    (1.25, 4): |R[l,l]| / sigma_l (sigma from the singular values of R, which
+    are A's) and ||C_l^GEQP3||_F / ||C_l^ours||_F (trailing blocks of the
+    R factors; GEQP3 from LAPACK on the host), with rank, orthogonality and
+    reconstruction."""
+    import scipy.linalg
+    A_h = W.high_coherence_matrix(m, n, seed + 4, boost=1e10)
+    _, R3, _ = scipy.linalg.qr(A_h, mode="economic", pivoting=True)
+    c3 = np.sqrt(np.cumsum((np.triu(R3) ** 2).sum(axis=1)[::-1])[::-1])
+    A = torch.from_numpy(A_h).to("cuda").t().contiguous().t()
+    out = {}
+    for gamma, nnz in ((1.0, 1), (1.25, 4)):
+        d = math.ceil(gamma * n)
+        Q, R, J, info = P.factor(A, d, nnz, seed, 1e-14)
+        k = int(info.rank)
+        orth, recon = quality(torch, A, Q, R, J, k)
+        Rh = R.cpu().numpy()
+        sv = np.linalg.svd(Rh[:k, :], compute_uv=False)
+        diag = np.abs(np.diag(Rh))[:k]
+        ratio_r = diag / sv[:k]
+        co = np.sqrt(np.cumsum((np.triu(Rh) ** 2).sum(axis=1)[::-1])[::-1])[:k]
+        ratio_c = c3[:k] / np.maximum(co, 1e-300)
+        out[f"gamma{gamma:g}_nnz{nnz}"] = {
+            "d": d, "rank": k, "rank_stage1": int(info.rank_stage1),
+            "chol_fail_col": int(info.chol_fail_col), "orth": orth, "recon": recon,
+            "diag_over_sigma_min": float(ratio_r.min()), "diag_over_sigma_max": float(ratio_r.max()),
+            "trailing_geqp3_over_ours_min": float(ratio_c.min()),
+            "trailing_geqp3_over_ours_max": float(ratio_c.max())}
+    log(f"high coherence: {json.dumps(out)}")
+    del A
+    torch.cuda.empty_cache()
+    return out
+
+
 def summary(r):
     keys = ("gflops", "ms", "p50", "p99", "min", "max", "rank", "rank_stage1", "passes",
             "orth", "recon", "orth_est")
@@ -381,7 +452,8 @@ def run_config(P, torch, W, name, seed, steps, modes, stage_steps=2, tols=None):
             st = stage_run(P, torch, A, f, seed, tol, stage_steps)
             r["stages_ms"] = st
             r["rooflines"] = rooflines(st, w, r["rank_stage1"], r["rank"],
-                                       mixed=mode != P.CQRRPT_FP64)
+                                       mixed=mode != P.CQRRPT_FP64,
+                                       fp32_lines=mode == P.CQRRPT_MIXED_FP32_CHOLQR2)
             key = mode_name if tols is None else f"{mode_name}_tol{tol:g}"
             res[key] = r
             log(f"  {name} {key}: {json.dumps(summary(r))}")
@@ -466,7 +538,8 @@ def main():
 
     if not args.no_extra_runs:
         fp64 = (("fp64", P.CQRRPT_FP64),)
-        all3 = fp64 + (("mixed", P.CQRRPT_MIXED), ("mixed_checked", P.CQRRPT_MIXED_CHECKED))
+        all3 = fp64 + (("mixed", P.CQRRPT_MIXED), ("mixed_checked", P.CQRRPT_MIXED_CHECKED),
+                       ("mixed_fp32_lines_cholqr2", P.CQRRPT_MIXED_FP32_CHOLQR2))
         extra["fp64_10000x100_cond1e6"] = run_config(P, torch, W, "fp64_10000x100_cond1e6",
                                                      args.seed, 200, fp64)
         extra["fp64_131072x1024_rank512"] = run_config(
@@ -481,6 +554,8 @@ def main():
         log(f"implicit Q: {json.dumps(summary(ir))}")
         del A2
         torch.cuda.empty_cache()
+        extra["gamma_sweep"] = gamma_sweep(P, torch, args.seed)
+        extra["high_coherence_32768x500"] = high_coherence_study(P, torch, W, args.seed)
         if args.serving_requests > 0:
             srv = {}
             for name, mode in (("fp64", P.CQRRPT_FP64), ("mixed", P.CQRRPT_MIXED)):

@@ -67,7 +67,19 @@ extern "C" {
  * FP64 bound 10 would cut. Hence CQRRPT_MIXED guarantees only
  * ||Q^T Q - I||_2 <~ 1e-4 in the worst case; CQRRPT_MIXED_CHECKED guarantees
  * the FP64 orthogonality bar. */
-typedef enum { CQRRPT_FP64 = 0, CQRRPT_MIXED = 1, CQRRPT_MIXED_CHECKED = 2 } cqrrpt_mode_t;
+typedef enum {
+  CQRRPT_FP64 = 0,
+  CQRRPT_MIXED = 1,
+  CQRRPT_MIXED_CHECKED = 2,
+  /* FP32 lines + CholeskyQR2: the preconditioning solve, the Gram and the Q
+   * product on FP32 matrix cores with FP32 accumulation (M_pre stored in
+   * FP32), then one FP64 CholeskyQR pass on Q (always run: G2 = Q^T Q,
+   * R2 = chol(G2), Q <- Q R2^{-1}, R <- R2 R). The sketch, its QRCP, the
+   * Cholesky factorizations and R = R_pre R_sk stay FP64. The first pass's
+   * orthogonality is FP32-level, so its second-stage bound is
+   * sqrt(0.5 / 2^-24) = 2896 (the loss the FP64 pass still repairs). */
+  CQRRPT_MIXED_FP32_CHOLQR2 = 3
+} cqrrpt_mode_t;
 
 /* Per-call diagnostics, written to DEVICE memory by cqrrpt_factor_ex and
  * copied to the host by cqrrpt_factor. */

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libcqrrpt.so")
 CQRRPT_FP64 = 0
 CQRRPT_MIXED = 1
 CQRRPT_MIXED_CHECKED = 2
+CQRRPT_MIXED_FP32_CHOLQR2 = 3
 
 STATUS = {
     0: "ok", 1: "non-finite input", 2: "device-memory budget exceeded",

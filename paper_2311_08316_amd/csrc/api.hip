@@ -33,6 +33,10 @@ constexpr int kMaxD = 16384;
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+__global__ void set_flag_kernel(int* p, int v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
 __global__ void info_init_kernel(cqrrpt_info_t* info) {
   if (threadIdx.x == 0) {
     info->rank = 0;
@@ -111,6 +115,11 @@ constexpr double kCholQR2Threshold = 5e-13;
 // u_fp32 cond(R_sk), hundreds at cond 1e10, which 10 would cut.)
 constexpr double kStage2CondFp64 = 10.0;
 constexpr double kStage2CondMixed = 1e6;
+// The FP32-lines arrangement (Gram and Q on FP32 matrix cores with FP32
+// accumulation, then an FP64 CholeskyQR2 pass): the same equation with
+// u = 2^-24 and eps_tol = 1/2, the largest first-pass loss the FP64 pass
+// repairs: sqrt(0.5 / 2^-24) = 2896.
+constexpr double kStage2CondFp32Lines = 2896.0;
 struct StageTimer {
   std::mutex mu;
   int slots = 0;
@@ -387,20 +396,28 @@ int factor_core(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, i
     float* M32 = reinterpret_cast<float*>(base + L.off_mpre32);
     CQ_TRY(cqh::launch_trsm_mixed(A, lda, J, M32, m, Rsk, n, m, ko_dev, ni, tpack, info, s));
     mk.mark(4);
-    CQ_TRY(cqh::launch_syrk<float>(M32, m, m, ko_dev, ni, Gp, G, n, info, s));
+    if (mode == CQRRPT_MIXED_FP32_CHOLQR2)
+      CQ_TRY(cqh::launch_gram_f32(M32, m, m, ko_dev, ni, Gp, G, n, info, s));
+    else
+      CQ_TRY(cqh::launch_syrk<float>(M32, m, m, ko_dev, ni, Gp, G, n, info, s));
   }
   mk.mark(5);
   // S7-S8: R_pre = chol(G) in place, second-stage rank k; Winv = R_pre^{-1}.
   // The precursor has no second stage (a Cholesky failure still truncates).
   CQ_TRY(cqh::launch_cholesky(G, n, ko_dev, ni, k_dev, Winv, n, base + L.off_chol, info, s,
-                              precursor ? INFINITY
-                              : mode == CQRRPT_FP64 ? kStage2CondFp64 : kStage2CondMixed));
+                              precursor                          ? INFINITY
+                              : mode == CQRRPT_FP64              ? kStage2CondFp64
+                              : mode == CQRRPT_MIXED_FP32_CHOLQR2 ? kStage2CondFp32Lines
+                                                                 : kStage2CondMixed));
   mk.mark(6);
   // S9: Q = M_pre[:, :k] R_pre^{-1}, as the product with Winv[:k, :k].
   if (Rpre) {
     // Implicit Q: M_pre stays.
   } else if (mode == CQRRPT_FP64) {
     CQ_TRY(cqh::launch_qform_f64(Q, ldq, Q, ldq, Winv, n, m, k_dev, info, s));
+  } else if (mode == CQRRPT_MIXED_FP32_CHOLQR2) {
+    float* M32 = reinterpret_cast<float*>(base + L.off_mpre32);
+    CQ_TRY(cqh::launch_qform_f32(M32, m, Q, ldq, Winv, n, m, k_dev, info, s));
   } else {
     float* M32 = reinterpret_cast<float*>(base + L.off_mpre32);
     CQ_TRY(cqh::launch_qform_f32in(M32, m, Q, ldq, Winv, n, m, k_dev, info, s));
@@ -411,7 +428,7 @@ int factor_core(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, i
   CQ_TRY(cqh::launch_zero_cols(Q, ldq, m, ni, k_dev, info, s));
   if (Rpre) CQ_TRY(cqh::launch_copy_upper(G, n, Rpre, ldrp, ni, k_dev, info, s));
   mk.mark(8);
-  if (mode == CQRRPT_MIXED_CHECKED) {
+  if (mode == CQRRPT_MIXED_CHECKED || mode == CQRRPT_MIXED_FP32_CHOLQR2) {
     // S11: adaptive CholeskyQR2 pass, decided on the device. G2 = Q^T Q
     // (FP64) replaces R_pre in G, R's old value goes to the R_sk buffer
     // (both are dead after S10).
@@ -419,9 +436,15 @@ int factor_core(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, i
     int* apply = pass + 1;
     int64_t* k2_dev = kv + 2;
     CQ_TRY(cqh::launch_syrk<double>(Q, ldq, m, k_dev, ni, Gp, G, n, info, s));
-    // The partial Gram tiles are dead once G2 is summed: scratch for the
-    // power iteration.
-    CQ_TRY(cqh::launch_orth_check(G, n, k_dev, ni, kCholQR2Threshold, pass, Gp, info, s));
+    if (mode == CQRRPT_MIXED_CHECKED) {
+      // The partial Gram tiles are dead once G2 is summed: scratch for the
+      // power iteration.
+      CQ_TRY(cqh::launch_orth_check(G, n, k_dev, ni, kCholQR2Threshold, pass, Gp, info, s));
+    } else {
+      // FP32 CholeskyQR lines: the second pass always runs.
+      hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(64), 0, s, pass, 1);
+      CQ_TRY(hipGetLastError());
+    }
     CQ_TRY(cqh::launch_cholesky(G, n, k_dev, ni, k2_dev, Winv, n, base + L.off_chol, info, s,
                                 INFINITY, false, pass));
     CQ_TRY(cqh::launch_cholqr2_commit(pass, k_dev, k2_dev, apply, R, ldr, Rsk, n, ni, info, s));
@@ -447,7 +470,9 @@ int cqrrpt_factor_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t
   if (!R) return -11;
   if (ldr < n) return -12;
   if (!J) return -13;
-  if (mode != CQRRPT_FP64 && mode != CQRRPT_MIXED && mode != CQRRPT_MIXED_CHECKED) return -14;
+  if (mode != CQRRPT_FP64 && mode != CQRRPT_MIXED && mode != CQRRPT_MIXED_CHECKED &&
+      mode != CQRRPT_MIXED_FP32_CHOLQR2)
+    return -14;
   if (!ws) return -15;
   if (!info) return -18;
   return factor_core(A, lda, m, n, d, nnz, seed, tol, Q, ldq, R, ldr, J, mode, ws, ws_bytes,
@@ -500,7 +525,9 @@ int cqrrpt_factor_noalloc(const double* A, int64_t lda, int64_t m, int64_t n, in
   if (!R) return -11;
   if (ldr < n) return -12;
   if (!J) return -13;
-  if (mode != CQRRPT_FP64 && mode != CQRRPT_MIXED && mode != CQRRPT_MIXED_CHECKED) return -14;
+  if (mode != CQRRPT_FP64 && mode != CQRRPT_MIXED && mode != CQRRPT_MIXED_CHECKED &&
+      mode != CQRRPT_MIXED_FP32_CHOLQR2)
+    return -14;
   if (!info) return -16;
   if (n > kMaxN || d > kMaxD || !cqh::sketch_fits((int)d, nnz)) return CQRRPT_ELIMIT;
   const size_t need = make_layout(m, n, d, nnz, mode).total;

@@ -369,6 +369,16 @@ int gram_splits(int64_t m, int kmax);
 hipError_t launch_gram_f64(const double* X, int64_t ldx, int64_t m, const int64_t* kdev,
                            int kmax, double* partials, double* G, int64_t ldg,
                            const cqrrpt_info_t* info, hipStream_t s);
+// The same Gram of FP32 data on FP32 matrix cores with FP32 accumulation
+// (partials and G in FP64 storage).
+hipError_t launch_gram_f32(const float* X, int64_t ldx, int64_t m, const int64_t* kdev,
+                           int kmax, double* partials, double* G, int64_t ldg,
+                           const cqrrpt_info_t* info, hipStream_t s);
+// Q = M W with FP32 M, W converted to FP32, FP32 matrix cores and FP32
+// accumulation, Q stored in FP64.
+hipError_t launch_qform_f32(const float* M, int64_t ldm, double* Q, int64_t ldq,
+                            const double* W, int64_t ldw, int64_t m, const int64_t* kdev,
+                            const cqrrpt_info_t* info, hipStream_t s);
 size_t syrk_ws_bytes(int64_t m, int kmax);
 template <typename T>
 hipError_t launch_syrk(const T* X, int64_t ldx, int64_t m, const int64_t* kdev, int kmax,

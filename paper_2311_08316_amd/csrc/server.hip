@@ -211,7 +211,8 @@ extern "C" {
 cqrrpt_server_t* cqrrpt_server_create(size_t hbm_budget_bytes, int32_t max_slots,
                                       cqrrpt_mode_t mode) {
   if (hbm_budget_bytes == 0 || max_slots < 1 || max_slots > 64) return nullptr;
-  if (mode != CQRRPT_FP64 && mode != CQRRPT_MIXED && mode != CQRRPT_MIXED_CHECKED)
+  if (mode != CQRRPT_FP64 && mode != CQRRPT_MIXED && mode != CQRRPT_MIXED_CHECKED &&
+      mode != CQRRPT_MIXED_FP32_CHOLQR2)
     return nullptr;
   cqrrpt_server_t* sv = new cqrrpt_server_t();
   if (hipGetDevice(&sv->device) != hipSuccess) {

@@ -731,13 +731,15 @@ constexpr int kGT = 128;          // output tile
 constexpr int kGK = 16;           // rows per staging step
 constexpr int kGLd = kGK + 1;     // LDS pitch of a staged column
 constexpr int kGStage = kGT * kGLd;
-constexpr size_t kGramLdsBytes = (size_t)4 * kGStage * 8;  // 2 buffers x (I, J)
 
+template <typename TX, typename TC>
 __global__ void __launch_bounds__(kThreads, 2)
-gram128_kernel(const double* __restrict__ X, int64_t ldx, int64_t m, const int64_t* kdev,
+gram128_kernel(const TX* __restrict__ X, int64_t ldx, int64_t m, const int64_t* kdev,
                int64_t rows_per_split, int tiles, double* __restrict__ P,
                const cqrrpt_info_t* info) {
-  extern __shared__ double gsm[];
+  typedef typename MfmaAcc<TC>::type acc_t;
+  extern __shared__ unsigned char gsm_raw[];
+  TC* gsm = reinterpret_cast<TC*>(gsm_raw);
   if (info->status != 0) return;
   const int64_t k = *kdev;
 #ifndef CQ_GRAM_ORDER
@@ -772,22 +774,22 @@ gram128_kernel(const double* __restrict__ X, int64_t ldx, int64_t m, const int64
   const int64_t r0 = (int64_t)split * rows_per_split;
   const int64_t r1 = (r0 + rows_per_split) < m ? (r0 + rows_per_split) : m;
 
-  d4_t acc[4][4];
+  acc_t acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = d4_t{0, 0, 0, 0};
+    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
   // Thread (row rr, column cl + 16 q): 16 consecutive lanes read the 16
-  // rows (128 contiguous bytes) of one column.
+  // rows (contiguous) of one column.
   const int rr = tid & (kGK - 1);
   const int cl = tid >> 4;
-  double vi[8], vj[8];
+  TX vi[8], vj[8];
   bool rok = true;
   auto load = [&](int64_t rs) {
     const int64_t row = rs + rr;
     rok = row < r1;
-    const double* xr = X + (rok ? row : r1 - 1);
+    const TX* xr = X + (rok ? row : r1 - 1);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int64_t ci = i0 + cl + 16 * q;
@@ -802,27 +804,27 @@ gram128_kernel(const double* __restrict__ X, int64_t ldx, int64_t m, const int64
     }
   };
   auto store = [&](int buf) {
-    double* XI = gsm + (2 * buf) * kGStage;
-    double* XJ = XI + kGStage;
+    TC* XI = gsm + (2 * buf) * kGStage;
+    TC* XJ = XI + kGStage;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int c = cl + 16 * q;
-      XI[c * kGLd + rr] = (rok && i0 + c < k) ? vi[q] : 0.0;
+      XI[c * kGLd + rr] = (rok && i0 + c < k) ? (TC)vi[q] : (TC)0;
     }
     if (!diag) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int c = cl + 16 * q;
-        XJ[c * kGLd + rr] = (rok && j0 + c < k) ? vj[q] : 0.0;
+        XJ[c * kGLd + rr] = (rok && j0 + c < k) ? (TC)vj[q] : (TC)0;
       }
     }
   };
   auto multiply = [&](int buf) {
-    const double* XI = gsm + (2 * buf) * kGStage;
-    const double* XJ = diag ? XI : XI + kGStage;
+    const TC* XI = gsm + (2 * buf) * kGStage;
+    const TC* XJ = diag ? XI : XI + kGStage;
 #pragma unroll
     for (int s = 0; s < kGK / 4; ++s) {
-      double af[4], bf[4];
+      TC af[4], bf[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) af[a] = XI[(64 * wr + 16 * a + l16) * kGLd + 4 * s + lq];
 #pragma unroll
@@ -857,9 +859,9 @@ gram128_kernel(const double* __restrict__ X, int64_t ldx, int64_t m, const int64
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int li = 64 * wr + 16 * a + acc_row<double>(lq, r);
+        const int li = 64 * wr + 16 * a + acc_row<TC>(lq, r);
         const int lj = 64 * wc + 16 * b + l16;
-        Pout[li * kGT + lj] = acc[a][b][r];
+        Pout[li * kGT + lj] = (double)acc[a][b][r];
       }
 }
 
@@ -988,25 +990,45 @@ size_t syrk_ws_bytes(int64_t m, int kmax) {
   return small > big ? small : big;
 }
 
-hipError_t launch_gram_f64(const double* X, int64_t ldx, int64_t m, const int64_t* kdev,
-                           int kmax, double* partials, double* G, int64_t ldg,
-                           const cqrrpt_info_t* info, hipStream_t s) {
+template <typename TX, typename TC>
+hipError_t launch_gram_impl(const TX* X, int64_t ldx, int64_t m, const int64_t* kdev, int kmax,
+                            double* partials, double* G, int64_t ldg, const cqrrpt_info_t* info,
+                            hipStream_t s) {
   const int nsplit = gram_splits(m, kmax);
   int64_t rps = (m + nsplit - 1) / nsplit;
   rps = (rps + kGK - 1) / kGK * kGK;
   const int nt = (kmax + kGT - 1) / kGT;
   const int tiles = nt * (nt + 1) / 2;
-  hipError_t e = hipFuncSetAttribute((const void*)gram128_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)kGramLdsBytes);
+  const size_t lds = (size_t)4 * kGStage * sizeof(TC);
+  hipError_t e = hipFuncSetAttribute((const void*)gram128_kernel<TX, TC>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gram128_kernel, dim3((unsigned)(tiles * nsplit)), dim3(kThreads),
-                     kGramLdsBytes, s, X, ldx, m, kdev, rps, tiles, partials, info);
+  hipLaunchKernelGGL((gram128_kernel<TX, TC>), dim3((unsigned)(tiles * nsplit)), dim3(kThreads),
+                     lds, s, X, ldx, m, kdev, rps, tiles, partials, info);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(gram128_reduce_kernel, dim3(kGT * kGT / kThreads, (unsigned)tiles),
                      dim3(kThreads), 0, s, partials, nsplit, tiles, kdev, G, ldg, info);
   return hipGetLastError();
+}
+
+hipError_t launch_gram_f64(const double* X, int64_t ldx, int64_t m, const int64_t* kdev,
+                           int kmax, double* partials, double* G, int64_t ldg,
+                           const cqrrpt_info_t* info, hipStream_t s) {
+  return launch_gram_impl<double, double>(X, ldx, m, kdev, kmax, partials, G, ldg, info, s);
+}
+
+hipError_t launch_gram_f32(const float* X, int64_t ldx, int64_t m, const int64_t* kdev,
+                           int kmax, double* partials, double* G, int64_t ldg,
+                           const cqrrpt_info_t* info, hipStream_t s) {
+  return launch_gram_impl<float, float>(X, ldx, m, kdev, kmax, partials, G, ldg, info, s);
+}
+
+hipError_t launch_qform_f32(const float* M, int64_t ldm, double* Q, int64_t ldq,
+                            const double* W, int64_t ldw, int64_t m, const int64_t* kdev,
+                            const cqrrpt_info_t* info, hipStream_t s) {
+  return launch_qform_impl<float, double, float>(M, ldm, Q, ldq, W, ldw, m, kdev, info, nullptr,
+                                                 s);
 }
 
 template <typename T>

@@ -511,3 +511,49 @@ def test_sketched_cholqr_zero_column(P):
     assert info.rank == orc["rank"] == 19 and info.rank_stage1 == 19
     assert not Qn[:, 19:].any() and not Rn[19:, :].any()
     assert np.linalg.norm(Rn - orc["R"]) / np.linalg.norm(orc["R"]) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# FP32 CholeskyQR lines + FP64 CholeskyQR2 (CQRRPT_MIXED_FP32_CHOLQR2): the
+# solve, Gram and Q product on FP32 matrix cores with FP32 accumulation, then
+# an FP64 pass that always runs. Pivots and ranks must equal the FP64
+# oracle's; Q must reach the FP64 orthogonality bar after the pass; the
+# reconstruction is FP32-level (stated, not matched).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind,cond", [("logspaced", 1e2), ("logspaced", 1e10),
+                                       ("coherent", 1e10), ("planted", 1e3),
+                                       ("cholesky-failure", 1e10)])
+def test_mixed_fp32_lines_cholqr2(P, kind, cond):
+    say(f"fp32 lines + cholqr2 {kind} {cond:.0e}")
+    if kind == "logspaced":
+        A = W.spectrum_matrix(40000, 256, W.logspaced_spectrum(256, cond), seed=11)
+        d, nnz, seed, tol = 320, 8, 2, 1e-14
+    elif kind == "coherent":
+        A = W.high_coherence_matrix(40000, 256, 5, boost=cond)
+        d, nnz, seed, tol = 320, 8, 2, 1e-14
+    elif kind == "planted":
+        s = np.zeros(96)
+        s[:40] = W.logspaced_spectrum(40, cond)
+        A = W.spectrum_matrix(6000, 96, s, seed=3)
+        d, nnz, seed, tol = 120, 8, 9, 1e-11
+    else:
+        A = W.high_coherence_matrix(8000, 128, 4, boost=cond)
+        d, nnz, seed, tol = 128, 1, 0, 1e-14
+    orc = O.cqrrpt(A, d, nnz, seed=seed, tol=tol)
+    Qg, Rg, Jg, info = P.factor(to_gpu(A), d, nnz, seed, tol, mode=P.CQRRPT_MIXED_FP32_CHOLQR2)
+    Qn, Rn, Jn = to_np(Qg), to_np(Rg), to_np(Jg)
+    k = orc["rank"]
+    say(f"  rank {info.rank} (oracle {k}) stage 1 {info.rank_stage1} passes "
+        f"{info.cholqr2_passes} chol fail {info.chol_fail_col}")
+    assert info.status == 0 and info.rank_stage1 == orc["rank_stage1"]
+    assert info.rank == k
+    assert np.array_equal(Jn[:k], orc["J"][:k])
+    assert info.cholqr2_passes == 1
+    recon, orth = metrics(A, Qn, Rn, Jn, k)
+    recon_o, _ = metrics(A, orc["Q"], orc["R"], orc["J"], k)
+    say(f"  orth {orth:.2e} recon {recon:.2e} (oracle {recon_o:.2e})")
+    assert orth <= 1e-12
+    assert recon <= max(1e-5, 10 * recon_o)
+    assert not Qn[:, k:].any() and not Rn[k:, :].any()
+    assert np.array_equal(Rn, np.triu(Rn)) and np.all(np.diag(Rn)[:k] > 0)

@@ -97,7 +97,7 @@ def test_factor_ex_rejects_bad_arguments_before_any_device_work(L):
     assert call(R=None) == -11
     assert call(ldr=9) == -12
     assert call(J=None) == -13
-    assert call(mode=3) == -14
+    assert call(mode=4) == -14
     assert call(mode=7) == -14
     assert call(ws=None) == -15
     assert call(info=None) == -18
