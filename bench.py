@@ -372,6 +372,30 @@ def serving_run(P, torch, W, count, mode, seed, slots=4, budget_gib=64.0, inflig
             "full_rank_results": full_rank}
 
 
+def dense_sketch_run(P, torch, W, seed, reps=5):
+    """CQRRPT on the 131,072 x 1,024 planted-rank input (tol 1e-14) with the
+    Gaussian and SRHT operators (Sec. 2.3.1; S formed explicitly, the sketch
+    one FP64 matrix-core product) beside the SASO: wall time per call
+    (synchronous form) and rank."""
+    A, w = W.make_workload_gpu("fp64_131072x1024_rank512", seed=seed)
+    out = {}
+    for name, kind in (("gaussian", P.SKETCH_GAUSSIAN), ("srht", P.SKETCH_SRHT)):
+        P.factor_dense(A, w["d"], kind, seed, w["tol"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            Q, R, J, info = P.factor_dense(A, w["d"], kind, seed, w["tol"])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        orth, recon = quality(torch, A, Q, R, J, int(info.rank))
+        out[name] = {"ms_per_call": ms, "rank": int(info.rank), "orth": orth, "recon": recon}
+        del Q, R, J
+    log(f"dense sketches: {json.dumps(out)}")
+    del A
+    torch.cuda.empty_cache()
+    return out
+
+
 def gamma_sweep(P, torch, seed):
     """Sec. 5.2.1: runtime against the embedding dimension d = gamma n on
     Gaussian 131,072 x n inputs (nnz = 4, tol 1e-14), for the shapes whose
@@ -554,6 +578,7 @@ def main():
         log(f"implicit Q: {json.dumps(summary(ir))}")
         del A2
         torch.cuda.empty_cache()
+        extra["dense_sketch_131072x1024"] = dense_sketch_run(P, torch, W, args.seed)
         extra["gamma_sweep"] = gamma_sweep(P, torch, args.seed)
         extra["high_coherence_32768x500"] = high_coherence_study(P, torch, W, args.seed)
         if args.serving_requests > 0:

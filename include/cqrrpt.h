@@ -240,6 +240,36 @@ int cqrrpt_sketched_cholqr_ex(const double* A, int64_t lda, int64_t m, int64_t n
                               void* ws, size_t ws_bytes, void* stream,
                               cqrrpt_info_t* info);
 
+/* CQRRPT with a dense sketching operator instead of the SASO (Sec. 2.3.1):
+ *   CQRRPT_SKETCH_GAUSSIAN: iid N(0, 1/d) entries; entries (2q, j) and
+ *     (2q+1, j) from one Philox4x32-10 block at counter (lo32(j), hi32(j), q,
+ *     "GAUS") by Box-Muller (u1 = (U(w0,w1) + 1) 2^-53, u2 = U(w2,w3) 2^-53,
+ *     U = top 27 bits of the first word and top 26 of the second; cosine for
+ *     the even row, sine for the odd).
+ *   CQRRPT_SKETCH_SRHT: S = sqrt(m/d) Pi[:d,:] H D, H the orthonormal
+ *     Sylvester-Hadamard matrix of order m' = 2^ceil(log2 m) (zero padding),
+ *     D the signs of bit 0 of word 0 at counter (lo32(j), hi32(j), 0, "SRHD"),
+ *     Pi[:d,:] the d rows Floyd's sampler draws from [0, m') with exact
+ *     uniform integers from the word stream at counters (lo32(w/4),
+ *     hi32(w/4), 0, "SRHR"), key (lo32(seed), hi32(seed)) throughout.
+ * S is formed explicitly (S^T in ws, m x d FP64) and Ahat = S A is one product
+ * on the FP64 matrix cores: 2 d m n flops, against the SASO's m n nnz adds.
+ * The SRHT is applied in this dense form, not by a fast transform. The rows
+ * of the SRHT are drawn on the host and copied in, so this call synchronises
+ * the stream once. The rest is cqrrpt_factor_ex in CQRRPT_FP64 mode.
+ * ws: cqrrpt_dense_workspace_bytes(m, n, d) bytes (0: sizes out of range).
+ * Argument order: A lda m n d kind seed tol Q ldq R ldr J ws ws_bytes stream
+ * info. Errors: -1..-5, -8 as cqrrpt_factor_ex, -6 unknown kind, -9 Q NULL,
+ * -10 ldq < m, -11 R NULL, -12 ldr < n, -13 J NULL, -14 ws NULL,
+ * -17 info NULL, CQRRPT_ELIMIT, CQRRPT_EWORKSPACE, CQRRPT_EHIP. */
+#define CQRRPT_SKETCH_GAUSSIAN 1
+#define CQRRPT_SKETCH_SRHT     2
+size_t cqrrpt_dense_workspace_bytes(int64_t m, int64_t n, int64_t d);
+int cqrrpt_factor_dense_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d,
+                           int32_t kind, uint64_t seed, double tol,
+                           double* Q, int64_t ldq, double* R, int64_t ldr, int64_t* J,
+                           void* ws, size_t ws_bytes, void* stream, cqrrpt_info_t* info);
+
 /* Allocation-free form of cqrrpt_factor_ex, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, hosts
  * that forbid hipMalloc). Same arguments and results as cqrrpt_factor_ex

@@ -203,6 +203,125 @@ def saso_matrix(m, d, nnz, seed):
 
 
 # ---------------------------------------------------------------------------
+# Dense sketching operators (Sec. 2.3.1: Gaussian matrices and SRHTs)
+# ---------------------------------------------------------------------------
+
+GAUSS_DOMAIN = 0x47415553       # "GAUS"
+SRHT_SIGN_DOMAIN = 0x53524844   # "SRHD"
+SRHT_ROW_DOMAIN = 0x53524852    # "SRHR"
+
+
+def _u53(hi_word, lo_word):
+    """53-bit integer from the top 27 bits of one word and the top 26 of
+    another."""
+    return (np.asarray(hi_word, dtype=np.uint64) >> np.uint64(5)) * np.uint64(1 << 26) + \
+        (np.asarray(lo_word, dtype=np.uint64) >> np.uint64(6))
+
+
+def gaussian_sketch_matrix(m, d, seed):
+    """S (d x m) with iid N(0, 1/d) entries (Sec. 2.3.1, Gaussian matrices).
+    Entries (2q, j) and (2q + 1, j) come from one Philox4x32-10 block with
+    counter (lo32(j), hi32(j), q, "GAUS"): u1 = (U(w0, w1) + 1) 2^-53 in
+    (0, 1], u2 = U(w2, w3) 2^-53 in [0, 1), where U takes the top 27 bits of
+    its first word and the top 26 of its second; Box-Muller gives
+    sqrt(-2 ln u1) cos(2 pi u2) for the even row and the sine for the odd."""
+    k0, k1 = seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF
+    j = np.arange(m, dtype=np.uint64)[None, :]
+    r = np.arange(d, dtype=np.uint64)[:, None]
+    w0, w1, w2, w3 = philox4x32_10(j & _MASK32, j >> np.uint64(32), r >> np.uint64(1),
+                                   GAUSS_DOMAIN, k0, k1)
+    u1 = (_u53(w0, w1) + np.uint64(1)).astype(np.float64) * 2.0 ** -53
+    u2 = _u53(w2, w3).astype(np.float64) * 2.0 ** -53
+    rad = np.sqrt(-2.0 * np.log(u1))
+    ang = 2.0 * math.pi * u2
+    z = np.where((r & np.uint64(1)) == 0, rad * np.cos(ang), rad * np.sin(ang))
+    return z * (1.0 / math.sqrt(d))
+
+
+class _ScalarWordStream:
+    """Word w = output word (w mod 4) of Philox4x32-10 at counter
+    (lo32(w div 4), hi32(w div 4), 0, domain)."""
+
+    def __init__(self, seed, domain):
+        self.k0, self.k1 = seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF
+        self.domain = domain
+        self.pos = 0
+        self.block = None
+
+    def next(self):
+        b, lane = divmod(self.pos, 4)
+        if lane == 0 or self.block is None:
+            self.block = [int(x) for x in philox4x32_10(b & 0xFFFFFFFF, b >> 32, 0, self.domain,
+                                                        self.k0, self.k1)]
+        self.pos += 1
+        return self.block[lane]
+
+    def uniform(self, s):
+        """Exact uniform integer in [0, s), Lemire's multiply-shift with rejection."""
+        thresh = ((1 << 32) - s) % s
+        while True:
+            prod = self.next() * s
+            if (prod & 0xFFFFFFFF) >= thresh:
+                return prod >> 32
+
+
+def srht_rows(m, d, seed):
+    """The d distinct rows of the Hadamard transform an SRHT keeps (the first
+    d of a random permutation of 0..m'-1, m' = 2^ceil(log2 m)): Floyd's
+    sampler fed by the "SRHR" word stream, in draw order."""
+    mp = 1 << max(0, (m - 1).bit_length())
+    if not 1 <= d <= mp:
+        raise ValueError("need 1 <= d <= m'")
+    st = _ScalarWordStream(seed, SRHT_ROW_DOMAIN)
+    picks, taken = [], set()
+    for t in range(d):
+        top = mp - d + t
+        r = st.uniform(top + 1)
+        if r in taken:
+            r = top
+        picks.append(r)
+        taken.add(r)
+    return np.array(picks, dtype=np.int64), mp
+
+
+def srht_signs(m, seed):
+    """Rademacher diagonal of D: bit 0 of word 0 of the block at counter
+    (lo32(j), hi32(j), 0, "SRHD"); set means -1."""
+    k0, k1 = seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF
+    j = np.arange(m, dtype=np.uint64)
+    w0 = philox4x32_10(j & _MASK32, j >> np.uint64(32), 0, SRHT_SIGN_DOMAIN, k0, k1)[0]
+    return np.where((w0 & np.uint32(1)) != 0, -1.0, 1.0)
+
+
+def srht_sketch_matrix(m, d, seed):
+    """S = sqrt(m / d) Pi[:d, :] H D (Sec. 2.3.1, SRHTs) as a dense d x m
+    matrix: H the orthonormal Sylvester-Hadamard matrix of order m'
+    (entries (-1)^popcount(p & j) / sqrt(m')), D = diag(signs) on the first
+    m rows, Pi[:d, :] keeping rows srht_rows(m, d, seed)."""
+    p, mp = srht_rows(m, d, seed)
+    sg = srht_signs(m, seed)
+    j = np.arange(m, dtype=np.int64)
+    bits = np.bitwise_and(p[:, None], j[None, :])
+    parity = np.zeros(bits.shape, dtype=np.int64)
+    x = bits.copy()
+    while np.any(x):
+        parity ^= x & 1
+        x >>= 1
+    H = np.where(parity == 1, -1.0, 1.0)
+    return H * sg[None, :] * math.sqrt(m / (d * mp))
+
+
+def cqrrpt_dense(A, d, kind, seed, tol, cond_max=10.0):
+    """CQRRPT with a dense sketching operator: kind "gaussian" or "srht"."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    if not (1 <= n <= m and n <= d <= m):
+        raise ValueError("need 1 <= n <= d <= m")
+    S = gaussian_sketch_matrix(m, d, seed) if kind == "gaussian" else srht_sketch_matrix(m, d, seed)
+    return cqrrpt_core(A, S, tol, cond_max)
+
+
+# ---------------------------------------------------------------------------
 # S2. The sketch
 # ---------------------------------------------------------------------------
 

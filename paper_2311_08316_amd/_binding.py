@@ -64,6 +64,9 @@ _SIGS = {
                                              _vp]),
     "cqrrpt_sketched_cholqr_ex": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i32, _u64,
                                                  _vp, _i64, _vp, _i64, _vp, _sz, _vp, _vp]),
+    "cqrrpt_dense_workspace_bytes": (_sz, [_i64, _i64, _i64]),
+    "cqrrpt_factor_dense_ex": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i32, _u64, _dbl,
+                                              _vp, _i64, _vp, _i64, _vp, _vp, _sz, _vp, _vp]),
     "cqrrpt_probe_copy": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
     "cqrrpt_probe_mfma": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _vp, _i64,
                                          ctypes.POINTER(_i64), _vp]),
@@ -340,6 +343,34 @@ def sketched_cholqr(A, d, nnz, seed):
     if inf.status != 0:
         _check(inf.status, "cqrrpt_sketched_cholqr_ex")
     return Q, R, inf
+
+
+SKETCH_GAUSSIAN = 1
+SKETCH_SRHT = 2
+
+
+def factor_dense(A, d, kind, seed, tol):
+    """CQRRPT with a dense sketching operator (``cqrrpt_factor_dense_ex``):
+    kind SKETCH_GAUSSIAN or SKETCH_SRHT. Returns (Q, R, J, info)."""
+    A = colmajor(A)
+    m, n = A.shape
+    Q = empty_colmajor(m, n, A.device)
+    R = empty_colmajor(n, n, A.device)
+    J = torch.empty(n, dtype=torch.int64, device=A.device)
+    wsb = lib().cqrrpt_dense_workspace_bytes(m, n, d)
+    if wsb == 0:
+        raise CqrrptError("unsupported sizes")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=A.device)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
+    rc = lib().cqrrpt_factor_dense_ex(A.data_ptr(), _ld(A), m, n, d, kind, seed, tol,
+                                      Q.data_ptr(), m, R.data_ptr(), n, J.data_ptr(),
+                                      ws.data_ptr(), wsb, _stream_handle(A.device),
+                                      info.data_ptr())
+    _check(rc, "cqrrpt_factor_dense_ex")
+    inf = CqrrptInfo.from_buffer_copy(bytes(info.cpu().numpy().tobytes()))
+    if inf.status != 0:
+        _check(inf.status, "cqrrpt_factor_dense_ex")
+    return Q, R, J, inf
 
 
 def factor_sync(A, d, nnz, seed, tol):

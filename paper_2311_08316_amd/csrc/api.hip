@@ -348,10 +348,12 @@ namespace {
 int factor_core(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, int32_t nnz,
                 uint64_t seed, double tol, double* Q, int64_t ldq, double* R, int64_t ldr,
                 int64_t* J, cqrrpt_mode_t mode, void* ws, size_t ws_bytes, void* stream,
-                cqrrpt_info_t* info, double* Rpre, int64_t ldrp, bool precursor = false) {
+                cqrrpt_info_t* info, double* Rpre, int64_t ldrp, bool precursor = false,
+                int dense_kind = 0) {
   if (n > kMaxN || d > kMaxD || !cqh::sketch_fits((int)d, nnz)) return CQRRPT_ELIMIT;
   const Layout L = make_layout(m, n, d, nnz, mode);
-  if (ws_bytes < L.total) return CQRRPT_EWORKSPACE;
+  const size_t need = L.total + (dense_kind ? cqh::dense_sketch_ws_bytes(m, n, (int)d) : 0);
+  if (ws_bytes < need) return CQRRPT_EWORKSPACE;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
@@ -372,9 +374,13 @@ int factor_core(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, i
   hipLaunchKernelGGL(info_init_kernel, dim3(1), dim3(64), 0, s, info);
   CQ_TRY(hipGetLastError());
   mk.mark(0);
-  // S1-S2: sketch.
-  CQ_TRY(cqh::launch_sketch(L.sk, A, lda, m, n, (int)d, nnz, seed, Ahat, d, base + L.off_sketch,
-                            info, s));
+  // S1-S2: sketch (the SASO; or a dense operator, formed past the layout).
+  if (dense_kind)
+    CQ_TRY(cqh::launch_dense_sketch(dense_kind, A, lda, m, n, (int)d, seed, Ahat, d,
+                                    base + L.total, info, s));
+  else
+    CQ_TRY(cqh::launch_sketch(L.sk, A, lda, m, n, (int)d, nnz, seed, Ahat, d,
+                              base + L.off_sketch, info, s));
   mk.mark(1);
   // S3: QRCP of the sketch -> J, R_sk (the precursor of Sec. 1.3: plain
   // Householder QR, J = identity, kept in the workspace).
@@ -512,6 +518,29 @@ int cqrrpt_sketched_cholqr_ex(const double* A, int64_t lda, int64_t m, int64_t n
   if (!info) return -15;
   return factor_core(A, lda, m, n, d, nnz, seed, 0.0, Q, ldq, R, ldr, nullptr, CQRRPT_FP64, ws,
                      ws_bytes, stream, info, nullptr, 0, true);
+}
+
+size_t cqrrpt_dense_workspace_bytes(int64_t m, int64_t n, int64_t d) {
+  if (m < 1 || n < 1 || n > m || d < n || d > m || n > kMaxN || d > kMaxD) return 0;
+  return make_layout(m, n, d, 1, CQRRPT_FP64).total + cqh::dense_sketch_ws_bytes(m, n, (int)d);
+}
+
+int cqrrpt_factor_dense_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d,
+                           int32_t kind, uint64_t seed, double tol, double* Q, int64_t ldq,
+                           double* R, int64_t ldr, int64_t* J, void* ws, size_t ws_bytes,
+                           void* stream, cqrrpt_info_t* info) {
+  const int c = check_common(A, lda, m, n, d, 1, tol);
+  if (c) return c;
+  if (kind != CQRRPT_SKETCH_GAUSSIAN && kind != CQRRPT_SKETCH_SRHT) return -6;
+  if (!Q) return -9;
+  if (ldq < m) return -10;
+  if (!R) return -11;
+  if (ldr < n) return -12;
+  if (!J) return -13;
+  if (!ws) return -14;
+  if (!info) return -17;
+  return factor_core(A, lda, m, n, d, 1, seed, tol, Q, ldq, R, ldr, J, CQRRPT_FP64, ws, ws_bytes,
+                     stream, info, nullptr, 0, false, kind);
 }
 
 int cqrrpt_factor_noalloc(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d,

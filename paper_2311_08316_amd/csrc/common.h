@@ -316,6 +316,13 @@ hipError_t launch_sketch(const SketchPlan& p, const double* A, int64_t lda, int6
                          int d, int nnz, uint64_t seed, double* Ahat, int64_t ldah, void* ws,
                          cqrrpt_info_t* info, hipStream_t s);
 
+// Dense sketching operators (Gaussian, SRHT): S^T formed in ws, then
+// Ahat = S A on the matrix cores. ws: dense_sketch_ws_bytes(m, n, d) bytes.
+size_t dense_sketch_ws_bytes(int64_t m, int64_t n, int d);
+hipError_t launch_dense_sketch(int kind, const double* A, int64_t lda, int64_t m, int64_t n,
+                               int d, uint64_t seed, double* Ahat, int64_t ldah, void* ws,
+                               cqrrpt_info_t* info, hipStream_t s);
+
 struct QrcpPlan {
   bool reg;       // register-resident variant
   int rpl, cpw;   // its rows per lane and columns per wave

@@ -557,3 +557,26 @@ def test_mixed_fp32_lines_cholqr2(P, kind, cond):
     assert recon <= max(1e-5, 10 * recon_o)
     assert not Qn[:, k:].any() and not Rn[k:, :].any()
     assert np.array_equal(Rn, np.triu(Rn)) and np.all(np.diag(Rn)[:k] > 0)
+
+
+# ---------------------------------------------------------------------------
+# Dense sketching operators (Gaussian, SRHT; cqrrpt_factor_dense_ex) against
+# the oracle's CQRRPT with the same operator. The Gaussian entries come from
+# the same counter-based draws on both sides but through each side's own
+# log/cos/sin, so they agree to a few ulps; pivots and ranks must be
+# identical on inputs with pivot margins, R to 1e-12, Q to the cond bound.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", ["gaussian", "srht"])
+@pytest.mark.parametrize("m,n,d,spec", [(3000, 60, 75, "log1e6"), (20003, 200, 250, "log1e8"),
+                                        (5000, 100, 125, "separated"), (8192, 64, 80, "log1e4")])
+def test_dense_sketch_factor_parity(P, kind, m, n, d, spec):
+    say(f"dense sketch {kind} m={m} n={n} d={d} {spec}")
+    if spec == "separated":
+        A = W.column_scaled_well_separated(m, n, seed=41, ratio=1.1)
+    else:
+        A = W.spectrum_matrix(m, n, W.logspaced_spectrum(n, float(spec[3:])), seed=m % 83)
+    orc = O.cqrrpt_dense(A, d, kind, seed=6, tol=1e-14)
+    code = P.SKETCH_GAUSSIAN if kind == "gaussian" else P.SKETCH_SRHT
+    gpu = P.factor_dense(to_gpu(A), d, code, 6, 1e-14)
+    compare_factor(A, gpu, orc, f"{kind} {m}x{n}")

@@ -535,3 +535,94 @@ def test_precursor_rank_deficient_inputs():
     assert abs(out["R"][12, 12]) < 1e-12 * np.abs(out["R"]).max()
     piv = O.cqrrpt(D, d=25, nnz=4, seed=1, tol=1e-14)
     assert piv["rank"] == 19
+
+
+# ---------------------------------------------------------------------------
+# Dense sketching operators (Sec. 2.3.1): Gaussian matrices and SRHTs
+# ---------------------------------------------------------------------------
+
+def test_gaussian_sketch_distribution():
+    import scipy.stats
+    m, d = 6000, 64
+    S = O.gaussian_sketch_matrix(m, d, seed=3)
+    z = S.ravel() * math.sqrt(d)          # N(0, 1) if the entries are N(0, 1/d)
+    N = z.size
+    assert abs(z.mean()) < 4.0 / math.sqrt(N)
+    assert abs(z.var() - 1.0) < 4.0 * math.sqrt(2.0 / N)
+    assert scipy.stats.kstest(z, "norm").pvalue > 1e-3
+    # The two rows drawn from one Box-Muller pair are uncorrelated.
+    c = np.corrcoef(S[0::2].ravel(), S[1::2].ravel())[0, 1]
+    assert abs(c) < 4.0 / math.sqrt(N / 2)
+    # Columns are independent streams: a different seed, a different matrix;
+    # the same seed, the same bits.
+    assert np.array_equal(S, O.gaussian_sketch_matrix(m, d, seed=3))
+    assert not np.allclose(S, O.gaussian_sketch_matrix(m, d, seed=4))
+
+
+def test_gaussian_sketch_isotropy_monte_carlo():
+    # E[S^T S] = I_m (Sec. 2.3.1), averaged over seeds.
+    m, d, reps = 40, 25, 400
+    acc = np.zeros((m, m))
+    for s in range(reps):
+        S = O.gaussian_sketch_matrix(m, d, seed=1000 + s)
+        acc += S.T @ S
+    acc /= reps
+    # Each entry averages reps * d products of unit-variance terms / d.
+    assert np.max(np.abs(acc - np.eye(m))) < 6.0 / math.sqrt(reps * d)
+
+
+def test_srht_structure():
+    # m a power of two: the kept Hadamard rows are orthogonal, so
+    # S S^T = (m / d) I exactly; every entry is +-sqrt(m / (d m')).
+    m, d = 1024, 100
+    S = O.srht_sketch_matrix(m, d, seed=5)
+    assert np.allclose(S @ S.T, (m / d) * np.eye(d), atol=1e-12)
+    assert np.allclose(np.abs(S), math.sqrt(m / (d * 1024)))
+    rows, mp = O.srht_rows(m, d, seed=5)
+    assert mp == 1024 and len(set(rows.tolist())) == d and rows.min() >= 0 and rows.max() < mp
+    # Padding: m = 1000 pads to m' = 1024, entries +-sqrt(m / (d m')).
+    S2 = O.srht_sketch_matrix(1000, 64, seed=6)
+    assert S2.shape == (64, 1000)
+    assert np.allclose(np.abs(S2), math.sqrt(1000 / (64 * 1024)))
+    sg = O.srht_signs(20000, seed=7)
+    assert abs(sg.mean()) < 4.0 / math.sqrt(20000)
+
+
+def test_srht_rows_uniform_subsets():
+    # Floyd over [0, m') fed by the SRHT word stream: with m' = 8 and d = 3,
+    # all C(8, 3) = 56 subsets appear about equally often over seeds.
+    counts = {}
+    reps = 5600
+    for s in range(reps):
+        rows, _ = O.srht_rows(8, 3, seed=s)
+        key = tuple(sorted(rows.tolist()))
+        assert len(set(key)) == 3
+        counts[key] = counts.get(key, 0) + 1
+    assert len(counts) == 56
+    exp = reps / 56
+    chi2 = sum((c - exp) ** 2 / exp for c in counts.values())
+    assert chi2 < 110  # 55 degrees of freedom: p < 1e-5 beyond this
+
+
+def test_srht_isotropy_monte_carlo():
+    m, d, reps = 64, 16, 300
+    acc = np.zeros((m, m))
+    for s in range(reps):
+        S = O.srht_sketch_matrix(m, d, seed=2000 + s)
+        acc += S.T @ S
+    acc /= reps
+    assert np.allclose(np.diag(acc), 1.0)          # exactly m/d * d/m per diagonal entry
+    assert np.max(np.abs(acc - np.eye(m))) < 0.25
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "srht"])
+def test_dense_sketch_path(kind):
+    # Separated column norms: every sketch keeps the pivot decisions of
+    # GEQP3 on A itself; the factors satisfy the correctness theorem.
+    A = W.column_scaled_well_separated(3000, 40, seed=31, ratio=2.0)
+    out = O.cqrrpt_dense(A, 50, kind, seed=9, tol=1e-14)
+    _, _, piv = scipy.linalg.qr(A, mode="economic", pivoting=True)
+    assert out["rank"] == 40 and np.array_equal(out["J"], piv)
+    Q, R, J = out["Q"], out["R"], out["J"]
+    assert np.linalg.norm(A[:, J] - Q @ R) / np.linalg.norm(A) < 1e-14
+    assert np.linalg.norm(Q.T @ Q - np.eye(40), 2) < 1e-13
