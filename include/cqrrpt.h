@@ -316,7 +316,12 @@ const char* cqrrpt_stage_name(int i);
  * Serving (derived from the serving goal; not in the paper)
  * ------------------------------------------------------------------------
  * A server admits factorization requests of any shape as they arrive and
- * runs them concurrently on the current device:
+ * runs them concurrently on the current device. Requests admitted together
+ * form a batch: each runs its sketch, its solve and Gram, and its Q and R
+ * products on its own slot stream, while the batch's QRCPs (grouped by
+ * kernel shape) and its Cholesky steps run as single cooperative launches,
+ * one gang of workgroups per request, on a server stream ordered against the
+ * slot streams by events:
  *   cqrrpt_server_create(budget, max_slots, mode): allocates one device
  *     arena of `budget` bytes (all request workspaces are carved from it)
  *     and max_slots streams; NULL on bad arguments or HIP failure.

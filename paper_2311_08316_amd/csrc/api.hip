@@ -341,6 +341,237 @@ size_t cqrrpt_workspace_bytes(int64_t m, int64_t n, int64_t d, int32_t nnz, cqrr
 
 namespace {
 
+// One factorization's arguments and workspace pointers, shared by the
+// phases below (the serving form runs them with batched small steps in
+// between).
+struct FactorCtx {
+  const double* A;
+  int64_t lda, m, n, d;
+  int32_t nnz;
+  uint64_t seed;
+  double tol;
+  double* Q;
+  int64_t ldq;
+  double* R;
+  int64_t ldr;
+  int64_t* J;
+  cqrrpt_mode_t mode;
+  cqrrpt_info_t* info;
+  double* Rpre;
+  int64_t ldrp;
+  bool precursor;
+  int dense_kind;
+  hipStream_t s;
+  Layout L;
+  char* base;
+  double *Ahat, *Rsk, *rn2, *bmax, *Gp, *tpack, *G, *Winv;
+  int64_t *kv, *ko_dev, *k_dev;
+  int ni;
+  CallMarks mk;
+};
+
+int factor_setup(FactorCtx& c, const double* A, int64_t lda, int64_t m, int64_t n, int64_t d,
+                 int32_t nnz, uint64_t seed, double tol, double* Q, int64_t ldq, double* R,
+                 int64_t ldr, int64_t* J, cqrrpt_mode_t mode, void* ws, size_t ws_bytes,
+                 void* stream, cqrrpt_info_t* info, double* Rpre, int64_t ldrp, bool precursor,
+                 int dense_kind) {
+  if (n > kMaxN || d > kMaxD || !cqh::sketch_fits((int)d, nnz)) return CQRRPT_ELIMIT;
+  c.L = make_layout(m, n, d, nnz, mode);
+  const size_t need = c.L.total + (dense_kind ? cqh::dense_sketch_ws_bytes(m, n, (int)d) : 0);
+  if (ws_bytes < need) return CQRRPT_EWORKSPACE;
+  c.A = A;
+  c.lda = lda;
+  c.m = m;
+  c.n = n;
+  c.d = d;
+  c.nnz = nnz;
+  c.seed = seed;
+  c.tol = tol;
+  c.Q = Q;
+  c.ldq = ldq;
+  c.R = R;
+  c.ldr = ldr;
+  c.mode = mode;
+  c.info = info;
+  c.Rpre = Rpre;
+  c.ldrp = ldrp;
+  c.precursor = precursor;
+  c.dense_kind = dense_kind;
+  c.s = static_cast<hipStream_t>(stream);
+  c.base = static_cast<char*>(ws);
+  const Layout& L = c.L;
+  c.Ahat = reinterpret_cast<double*>(c.base + L.off_ahat);
+  c.Rsk = reinterpret_cast<double*>(c.base + L.off_rsk);
+  c.rn2 = reinterpret_cast<double*>(c.base + L.off_rn2);
+  c.bmax = reinterpret_cast<double*>(c.base + L.off_bmax);
+  c.kv = reinterpret_cast<int64_t*>(c.base + L.off_k);
+  c.ko_dev = c.kv;
+  c.k_dev = c.kv + 1;
+  c.Gp = reinterpret_cast<double*>(c.base + L.off_syrkp);
+  c.tpack = reinterpret_cast<double*>(c.base + L.off_tpack);
+  c.G = reinterpret_cast<double*>(c.base + L.off_g);
+  c.Winv = reinterpret_cast<double*>(c.base + L.off_winv);
+  // The precursor of Sec. 1.3 keeps its (identity) pivots in the workspace.
+  c.J = precursor ? reinterpret_cast<int64_t*>(c.base + L.off_jtmp) : J;
+  c.ni = (int)n;
+  c.mk = begin_marks(c.s);
+  return CQRRPT_OK;
+}
+
+double stage2_bound(const FactorCtx& c) {
+  return c.precursor                            ? INFINITY
+         : c.mode == CQRRPT_FP64                ? kStage2CondFp64
+         : c.mode == CQRRPT_MIXED_FP32_CHOLQR2 ? kStage2CondFp32Lines
+                                                : kStage2CondMixed;
+}
+
+// S1-S2: diagnostics reset and the sketch (the SASO; or a dense operator,
+// formed past the layout).
+int phase_sketch(FactorCtx& c) {
+  hipStream_t s = c.s;
+  hipLaunchKernelGGL(info_init_kernel, dim3(1), dim3(64), 0, s, c.info);
+  CQ_TRY(hipGetLastError());
+  c.mk.mark(0);
+  if (c.dense_kind)
+    CQ_TRY(cqh::launch_dense_sketch(c.dense_kind, c.A, c.lda, c.m, c.n, (int)c.d, c.seed, c.Ahat,
+                                    c.d, c.base + c.L.total, c.info, s));
+  else
+    CQ_TRY(cqh::launch_sketch(c.L.sk, c.A, c.lda, c.m, c.n, (int)c.d, c.nnz, c.seed, c.Ahat, c.d,
+                              c.base + c.L.off_sketch, c.info, s));
+  c.mk.mark(1);
+  return CQRRPT_OK;
+}
+
+// S3: QRCP of the sketch -> J, R_sk (the precursor: plain Householder QR).
+int phase_qrcp(FactorCtx& c) {
+  CQ_TRY(cqh::launch_qrcp(c.L.qr, c.Ahat, c.d, (int)c.d, c.ni, c.J, c.Rsk, c.n,
+                          c.base + c.L.off_qrcp, c.info, c.s, c.precursor));
+  c.mk.mark(2);
+  return CQRRPT_OK;
+}
+
+cqh::QrcpBatchItem qrcp_item(const FactorCtx& c) {
+  cqh::QrcpBatchItem it;
+  it.X = c.Ahat;
+  it.ldx = c.d;
+  it.d = (int)c.d;
+  it.n = c.ni;
+  it.J = c.J;
+  it.R = c.Rsk;
+  it.ldr = c.n;
+  it.ws = c.base + c.L.off_qrcp;
+  it.info = c.info;
+  return it;
+}
+
+// S4-S6: first-stage rank, preconditioning solve, Gram.
+int phase_tall(FactorCtx& c) {
+  hipStream_t s = c.s;
+  const int64_t m = c.m, n = c.n;
+  const int ni = c.ni;
+  // The precursor assumes full rank: tolerance 0 only drops an exactly zero
+  // trailing block.
+  CQ_TRY(cqh::launch_rank_stage1(c.Rsk, n, ni, c.precursor ? 0.0 : c.tol, c.rn2, c.bmax, c.ko_dev,
+                                 c.info, s));
+  c.mk.mark(3);
+  if (c.mode == CQRRPT_FP64) {
+    // S5: M_pre = A[:, J[:k_o]] R_sk^{-1}, written into Q.
+    CQ_TRY(cqh::launch_trsm_f64(c.A, c.lda, c.J, c.Q, c.ldq, c.Rsk, n, m, c.ko_dev, ni, c.tpack,
+                                c.info, s));
+    c.mk.mark(4);
+    // S6: G = M_pre^T M_pre.
+    CQ_TRY(cqh::launch_gram_f64(c.Q, c.ldq, m, c.ko_dev, ni, c.Gp, c.G, n, c.info, s));
+  } else {
+    float* M32 = reinterpret_cast<float*>(c.base + c.L.off_mpre32);
+    CQ_TRY(cqh::launch_trsm_mixed(c.A, c.lda, c.J, M32, m, c.Rsk, n, m, c.ko_dev, ni, c.tpack,
+                                  c.info, s));
+    c.mk.mark(4);
+    if (c.mode == CQRRPT_MIXED_FP32_CHOLQR2)
+      CQ_TRY(cqh::launch_gram_f32(M32, m, m, c.ko_dev, ni, c.Gp, c.G, n, c.info, s));
+    else
+      CQ_TRY(cqh::launch_syrk<float>(M32, m, m, c.ko_dev, ni, c.Gp, c.G, n, c.info, s));
+  }
+  c.mk.mark(5);
+  return CQRRPT_OK;
+}
+
+// S7-S8: R_pre = chol(G) in place, second-stage rank k; Winv = R_pre^{-1}.
+int phase_chol(FactorCtx& c) {
+  CQ_TRY(cqh::launch_cholesky(c.G, c.n, c.ko_dev, c.ni, c.k_dev, c.Winv, c.n,
+                              c.base + c.L.off_chol, c.info, c.s, stage2_bound(c)));
+  c.mk.mark(6);
+  return CQRRPT_OK;
+}
+
+cqh::CholBatchItem chol_item(const FactorCtx& c) {
+  cqh::CholBatchItem it;
+  it.G = c.G;
+  it.ldg = c.n;
+  it.ko_dev = c.ko_dev;
+  it.kmax = c.ni;
+  it.k_dev = c.k_dev;
+  it.W = c.Winv;
+  it.ldw = c.n;
+  it.ws = c.base + c.L.off_chol;
+  it.info = c.info;
+  it.cond_max = stage2_bound(c);
+  return it;
+}
+
+// S9-S11: Q, R = R_pre R_sk, zero fill past the rank, and the CholeskyQR2
+// pass of the modes that have one.
+int phase_tail(FactorCtx& c) {
+  hipStream_t s = c.s;
+  const int64_t m = c.m, n = c.n;
+  const int ni = c.ni;
+  double* Q = c.Q;
+  const int64_t ldq = c.ldq;
+  // S9: Q = M_pre[:, :k] R_pre^{-1}, as the product with Winv[:k, :k].
+  if (c.Rpre) {
+    // Implicit Q: M_pre stays.
+  } else if (c.mode == CQRRPT_FP64) {
+    CQ_TRY(cqh::launch_qform_f64(Q, ldq, Q, ldq, c.Winv, n, m, c.k_dev, c.info, s));
+  } else if (c.mode == CQRRPT_MIXED_FP32_CHOLQR2) {
+    float* M32 = reinterpret_cast<float*>(c.base + c.L.off_mpre32);
+    CQ_TRY(cqh::launch_qform_f32(M32, m, Q, ldq, c.Winv, n, m, c.k_dev, c.info, s));
+  } else {
+    float* M32 = reinterpret_cast<float*>(c.base + c.L.off_mpre32);
+    CQ_TRY(cqh::launch_qform_f32in(M32, m, Q, ldq, c.Winv, n, m, c.k_dev, c.info, s));
+  }
+  c.mk.mark(7);
+  // S10: R = R_pre R_sk[:k, :]; zero Q past the rank.
+  CQ_TRY(cqh::launch_trmm_r(c.G, n, c.Rsk, n, c.R, c.ldr, ni, c.k_dev, c.info, s));
+  CQ_TRY(cqh::launch_zero_cols(Q, ldq, m, ni, c.k_dev, c.info, s));
+  if (c.Rpre) CQ_TRY(cqh::launch_copy_upper(c.G, n, c.Rpre, c.ldrp, ni, c.k_dev, c.info, s));
+  c.mk.mark(8);
+  if (c.mode == CQRRPT_MIXED_CHECKED || c.mode == CQRRPT_MIXED_FP32_CHOLQR2) {
+    // S11: the CholeskyQR2 pass (decided on the device in the checked mode,
+    // always in the FP32-lines mode). G2 = Q^T Q (FP64) replaces R_pre in G,
+    // R's old value goes to the R_sk buffer (both are dead after S10).
+    int* pass = reinterpret_cast<int*>(c.kv + 3);
+    int* apply = pass + 1;
+    int64_t* k2_dev = c.kv + 2;
+    CQ_TRY(cqh::launch_syrk<double>(Q, ldq, m, c.k_dev, ni, c.Gp, c.G, n, c.info, s));
+    if (c.mode == CQRRPT_MIXED_CHECKED) {
+      // The partial Gram tiles are dead once G2 is summed: scratch for the
+      // power iteration.
+      CQ_TRY(cqh::launch_orth_check(c.G, n, c.k_dev, ni, kCholQR2Threshold, pass, c.Gp, c.info,
+                                    s));
+    } else {
+      hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(64), 0, s, pass, 1);
+      CQ_TRY(hipGetLastError());
+    }
+    CQ_TRY(cqh::launch_cholesky(c.G, n, c.k_dev, ni, k2_dev, c.Winv, n, c.base + c.L.off_chol,
+                                c.info, s, INFINITY, false, pass));
+    CQ_TRY(cqh::launch_cholqr2_commit(pass, c.k_dev, k2_dev, apply, c.R, c.ldr, c.Rsk, n, ni,
+                                      c.info, s));
+    CQ_TRY(cqh::launch_qform_f64(Q, ldq, Q, ldq, c.Winv, n, m, c.k_dev, c.info, s, apply));
+    CQ_TRY(cqh::launch_trmm_r(c.G, n, c.Rsk, n, c.R, c.ldr, ni, c.k_dev, c.info, s, apply));
+  }
+  c.mk.mark(9);
+  return CQRRPT_OK;
+}
+
 // The factorization on validated arguments. With Rpre == nullptr (explicit
 // Q) the Q buffer receives Q; otherwise (FP64 only) it keeps M_pre[:, :k],
 // the Q solve is skipped and Rpre receives R_pre[:k, :k]: the implicit
@@ -350,118 +581,59 @@ int factor_core(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, i
                 int64_t* J, cqrrpt_mode_t mode, void* ws, size_t ws_bytes, void* stream,
                 cqrrpt_info_t* info, double* Rpre, int64_t ldrp, bool precursor = false,
                 int dense_kind = 0) {
-  if (n > kMaxN || d > kMaxD || !cqh::sketch_fits((int)d, nnz)) return CQRRPT_ELIMIT;
-  const Layout L = make_layout(m, n, d, nnz, mode);
-  const size_t need = L.total + (dense_kind ? cqh::dense_sketch_ws_bytes(m, n, (int)d) : 0);
-  if (ws_bytes < need) return CQRRPT_EWORKSPACE;
-
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  char* base = static_cast<char*>(ws);
-  double* Ahat = reinterpret_cast<double*>(base + L.off_ahat);
-  double* Rsk = reinterpret_cast<double*>(base + L.off_rsk);
-  double* rn2 = reinterpret_cast<double*>(base + L.off_rn2);
-  double* bmax = reinterpret_cast<double*>(base + L.off_bmax);
-  int64_t* kv = reinterpret_cast<int64_t*>(base + L.off_k);
-  int64_t* ko_dev = kv;
-  int64_t* k_dev = kv + 1;
-  double* Gp = reinterpret_cast<double*>(base + L.off_syrkp);
-  double* tpack = reinterpret_cast<double*>(base + L.off_tpack);
-  double* G = reinterpret_cast<double*>(base + L.off_g);
-  double* Winv = reinterpret_cast<double*>(base + L.off_winv);
-  const int ni = (int)n;
-
-  CallMarks mk = begin_marks(s);
-  hipLaunchKernelGGL(info_init_kernel, dim3(1), dim3(64), 0, s, info);
-  CQ_TRY(hipGetLastError());
-  mk.mark(0);
-  // S1-S2: sketch (the SASO; or a dense operator, formed past the layout).
-  if (dense_kind)
-    CQ_TRY(cqh::launch_dense_sketch(dense_kind, A, lda, m, n, (int)d, seed, Ahat, d,
-                                    base + L.total, info, s));
-  else
-    CQ_TRY(cqh::launch_sketch(L.sk, A, lda, m, n, (int)d, nnz, seed, Ahat, d,
-                              base + L.off_sketch, info, s));
-  mk.mark(1);
-  // S3: QRCP of the sketch -> J, R_sk (the precursor of Sec. 1.3: plain
-  // Householder QR, J = identity, kept in the workspace).
-  if (precursor) J = reinterpret_cast<int64_t*>(base + L.off_jtmp);
-  CQ_TRY(cqh::launch_qrcp(L.qr, Ahat, d, (int)d, ni, J, Rsk, n, base + L.off_qrcp, info, s,
-                          precursor));
-  mk.mark(2);
-  // S4: first-stage rank k_o (the precursor assumes full rank: tolerance 0
-  // only drops an exactly zero trailing block).
-  CQ_TRY(cqh::launch_rank_stage1(Rsk, n, ni, precursor ? 0.0 : tol, rn2, bmax, ko_dev, info, s));
-  mk.mark(3);
-  if (mode == CQRRPT_FP64) {
-    // S5: M_pre = A[:, J[:k_o]] R_sk^{-1}, written into Q.
-    CQ_TRY(cqh::launch_trsm_f64(A, lda, J, Q, ldq, Rsk, n, m, ko_dev, ni, tpack, info, s));
-    mk.mark(4);
-    // S6: G = M_pre^T M_pre.
-    CQ_TRY(cqh::launch_gram_f64(Q, ldq, m, ko_dev, ni, Gp, G, n, info, s));
-  } else {
-    float* M32 = reinterpret_cast<float*>(base + L.off_mpre32);
-    CQ_TRY(cqh::launch_trsm_mixed(A, lda, J, M32, m, Rsk, n, m, ko_dev, ni, tpack, info, s));
-    mk.mark(4);
-    if (mode == CQRRPT_MIXED_FP32_CHOLQR2)
-      CQ_TRY(cqh::launch_gram_f32(M32, m, m, ko_dev, ni, Gp, G, n, info, s));
-    else
-      CQ_TRY(cqh::launch_syrk<float>(M32, m, m, ko_dev, ni, Gp, G, n, info, s));
-  }
-  mk.mark(5);
-  // S7-S8: R_pre = chol(G) in place, second-stage rank k; Winv = R_pre^{-1}.
-  // The precursor has no second stage (a Cholesky failure still truncates).
-  CQ_TRY(cqh::launch_cholesky(G, n, ko_dev, ni, k_dev, Winv, n, base + L.off_chol, info, s,
-                              precursor                          ? INFINITY
-                              : mode == CQRRPT_FP64              ? kStage2CondFp64
-                              : mode == CQRRPT_MIXED_FP32_CHOLQR2 ? kStage2CondFp32Lines
-                                                                 : kStage2CondMixed));
-  mk.mark(6);
-  // S9: Q = M_pre[:, :k] R_pre^{-1}, as the product with Winv[:k, :k].
-  if (Rpre) {
-    // Implicit Q: M_pre stays.
-  } else if (mode == CQRRPT_FP64) {
-    CQ_TRY(cqh::launch_qform_f64(Q, ldq, Q, ldq, Winv, n, m, k_dev, info, s));
-  } else if (mode == CQRRPT_MIXED_FP32_CHOLQR2) {
-    float* M32 = reinterpret_cast<float*>(base + L.off_mpre32);
-    CQ_TRY(cqh::launch_qform_f32(M32, m, Q, ldq, Winv, n, m, k_dev, info, s));
-  } else {
-    float* M32 = reinterpret_cast<float*>(base + L.off_mpre32);
-    CQ_TRY(cqh::launch_qform_f32in(M32, m, Q, ldq, Winv, n, m, k_dev, info, s));
-  }
-  mk.mark(7);
-  // S10: R = R_pre R_sk[:k, :]; zero Q past the rank.
-  CQ_TRY(cqh::launch_trmm_r(G, n, Rsk, n, R, ldr, ni, k_dev, info, s));
-  CQ_TRY(cqh::launch_zero_cols(Q, ldq, m, ni, k_dev, info, s));
-  if (Rpre) CQ_TRY(cqh::launch_copy_upper(G, n, Rpre, ldrp, ni, k_dev, info, s));
-  mk.mark(8);
-  if (mode == CQRRPT_MIXED_CHECKED || mode == CQRRPT_MIXED_FP32_CHOLQR2) {
-    // S11: adaptive CholeskyQR2 pass, decided on the device. G2 = Q^T Q
-    // (FP64) replaces R_pre in G, R's old value goes to the R_sk buffer
-    // (both are dead after S10).
-    int* pass = reinterpret_cast<int*>(kv + 3);
-    int* apply = pass + 1;
-    int64_t* k2_dev = kv + 2;
-    CQ_TRY(cqh::launch_syrk<double>(Q, ldq, m, k_dev, ni, Gp, G, n, info, s));
-    if (mode == CQRRPT_MIXED_CHECKED) {
-      // The partial Gram tiles are dead once G2 is summed: scratch for the
-      // power iteration.
-      CQ_TRY(cqh::launch_orth_check(G, n, k_dev, ni, kCholQR2Threshold, pass, Gp, info, s));
-    } else {
-      // FP32 CholeskyQR lines: the second pass always runs.
-      hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(64), 0, s, pass, 1);
-      CQ_TRY(hipGetLastError());
-    }
-    CQ_TRY(cqh::launch_cholesky(G, n, k_dev, ni, k2_dev, Winv, n, base + L.off_chol, info, s,
-                                INFINITY, false, pass));
-    CQ_TRY(cqh::launch_cholqr2_commit(pass, k_dev, k2_dev, apply, R, ldr, Rsk, n, ni, info, s));
-    CQ_TRY(cqh::launch_qform_f64(Q, ldq, Q, ldq, Winv, n, m, k_dev, info, s, apply));
-    CQ_TRY(cqh::launch_trmm_r(G, n, Rsk, n, R, ldr, ni, k_dev, info, s, apply));
-  }
-  mk.mark(9);
-  return CQRRPT_OK;
+  FactorCtx c;
+  int rc = factor_setup(c, A, lda, m, n, d, nnz, seed, tol, Q, ldq, R, ldr, J, mode, ws, ws_bytes,
+                        stream, info, Rpre, ldrp, precursor, dense_kind);
+  if (rc) return rc;
+  if ((rc = phase_sketch(c))) return rc;
+  if ((rc = phase_qrcp(c))) return rc;
+  if ((rc = phase_tall(c))) return rc;
+  if ((rc = phase_chol(c))) return rc;
+  return phase_tail(c);
 }
 
 }  // namespace
+
+namespace cqh {
+
+// Phased factorization for the serving form: the same launches as
+// cqrrpt_factor_ex, split where the server inserts its batched QRCP and
+// Cholesky launches.
+struct Phased {
+  FactorCtx c;
+};
+
+Phased* phased_begin(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, int32_t nnz,
+                     uint64_t seed, double tol, double* Q, int64_t ldq, double* R, int64_t ldr,
+                     int64_t* J, cqrrpt_mode_t mode, void* ws, size_t ws_bytes, void* stream,
+                     cqrrpt_info_t* info, int* rc) {
+  *rc = check_common(A, lda, m, n, d, nnz, tol);
+  if (*rc) return nullptr;
+  if (!Q || ldq < m || !R || ldr < n || !J || !ws || !info) {
+    *rc = -2;
+    return nullptr;
+  }
+  Phased* p = new Phased();
+  *rc = factor_setup(p->c, A, lda, m, n, d, nnz, seed, tol, Q, ldq, R, ldr, J, mode, ws, ws_bytes,
+                     stream, info, nullptr, 0, false, 0);
+  if (*rc) {
+    delete p;
+    return nullptr;
+  }
+  return p;
+}
+
+int phased_sketch(Phased* p) { return phase_sketch(p->c); }
+int phased_qrcp(Phased* p) { return phase_qrcp(p->c); }
+int phased_tall(Phased* p) { return phase_tall(p->c); }
+int phased_tail(Phased* p) { return phase_tail(p->c); }
+bool phased_batchable(const Phased* p) { return p->c.L.qr.reg; }
+QrcpBatchItem phased_qrcp_item(const Phased* p) { return qrcp_item(p->c); }
+CholBatchItem phased_chol_item(const Phased* p) { return chol_item(p->c); }
+void phased_mark(Phased* p, int i) { p->c.mk.mark(i); }
+void phased_end(Phased* p) { delete p; }
+
+}  // namespace cqh
 
 extern "C" {
 

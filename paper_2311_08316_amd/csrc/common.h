@@ -335,6 +335,23 @@ struct QrcpPlan {
 };
 QrcpPlan plan_qrcp(int d, int n);
 size_t qrcp_ws_bytes(const QrcpPlan& p);
+// Batched QRCPs (serving): items of the same register shape share one
+// cooperative launch, one gang of workgroups each, with each item's own
+// workspace (ws: qrcp_ws_bytes(plan_qrcp(d, n)) bytes) and the same kernel
+// body and workgroup count as a launch of its own (so the same results).
+struct QrcpBatchItem {
+  double* X;
+  int64_t ldx;
+  int d, n;
+  int64_t* J;
+  double* R;
+  int64_t ldr;
+  void* ws;
+  cqrrpt_info_t* info;
+};
+bool qrcp_batchable(int d, int n);
+hipError_t launch_qrcp_batch(const QrcpBatchItem* items, int count, hipStream_t s);
+
 // nopivot: column i at step i (unpivoted Householder QR, J = identity).
 hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, int64_t* J,
                        double* R, int64_t ldr, void* ws, cqrrpt_info_t* info, hipStream_t s,
@@ -404,6 +421,23 @@ hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int km
                            bool record = true, const int* enable = nullptr);
 
 // Kernels from here on treat k as 0 once info->status is set.
+// Batched Cholesky steps (serving): one cooperative launch, one gang of
+// workgroups per item (the gang size launch_cholesky would use); the record
+// flag is on and no enable flag is used.
+struct CholBatchItem {
+  double* G;
+  int64_t ldg;
+  const int64_t* ko_dev;
+  int kmax;
+  int64_t* k_dev;
+  double* W;
+  int64_t ldw;
+  void* ws;  // chol_ws_bytes(kmax)
+  cqrrpt_info_t* info;
+  double cond_max;
+};
+hipError_t launch_cholesky_batch(const CholBatchItem* items, int count, hipStream_t s);
+
 hipError_t launch_trmm_r(const double* Rpre, int64_t ldp, const double* Rsk, int64_t ldk,
                          double* R, int64_t ldr, int n, const int64_t* kdev,
                          const cqrrpt_info_t* info, hipStream_t s, const int* enable = nullptr);
@@ -422,5 +456,27 @@ hipError_t launch_zero_cols(double* Q, int64_t ldq, int64_t m, int n, const int6
 // out[:k, :k] = upper triangle of G[:k, :k], zero elsewhere in the n x n out.
 hipError_t launch_copy_upper(const double* G, int64_t ldg, double* out, int64_t ldo, int n,
                              const int64_t* kdev, const cqrrpt_info_t* info, hipStream_t s);
+
+// Phased factorization (the serving form's batched small steps): the
+// launches of cqrrpt_factor_ex in order, sketch | QRCP | rank, solve and
+// Gram | Cholesky | Q, R and the CholeskyQR2 pass, with the QRCP and
+// Cholesky also available as batch items. phased_begin validates the
+// arguments (rc: cqrrpt_factor_ex's code; nullptr on failure).
+struct Phased;
+Phased* phased_begin(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, int32_t nnz,
+                     uint64_t seed, double tol, double* Q, int64_t ldq, double* R, int64_t ldr,
+                     int64_t* J, cqrrpt_mode_t mode, void* ws, size_t ws_bytes, void* stream,
+                     cqrrpt_info_t* info, int* rc);
+int phased_sketch(Phased* p);
+int phased_qrcp(Phased* p);
+int phased_tall(Phased* p);
+int phased_tail(Phased* p);
+bool phased_batchable(const Phased* p);
+QrcpBatchItem phased_qrcp_item(const Phased* p);
+CholBatchItem phased_chol_item(const Phased* p);
+// Stage-timing mark i on the factorization's stream (the batched QRCP ends
+// with mark 2, the batched Cholesky with mark 6).
+void phased_mark(Phased* p, int i);
+void phased_end(Phased* p);
 
 }  // namespace cqh

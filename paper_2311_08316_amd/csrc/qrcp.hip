@@ -31,6 +31,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "common.h"
 
@@ -332,8 +333,10 @@ CQ_INLINE double chain_sum(const double (&p)[C]) {
   else return p[0];
 }
 
+// The register-resident QRCP of one matrix on G workgroups, this one being
+// number g (a whole launch, or one gang of a batched launch).
 template <int NT, int RPL, int CPW>
-__global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
+__device__ __forceinline__ void qrcp_reg_body(const QrcpArgs& a, const int G, const int g) {
   constexpr int W = NT / cq::kWave;
   constexpr int KR = (cq::kWave * RPL + NT - 1) / NT;  // staged rows per thread
   constexpr int KS = kRegMaxG / cq::kWave;             // candidate slots per lane
@@ -346,8 +349,6 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
   __shared__ int s_p;
   __shared__ int s_bad;
 
-  const int G = gridDim.x;
-  const int g = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & (cq::kWave - 1);
   const int wave = tid / cq::kWave;
@@ -710,6 +711,30 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
   }
 }
 
+template <int NT, int RPL, int CPW>
+__global__ void __launch_bounds__(NT) qrcp_reg_kernel(QrcpArgs a) {
+  qrcp_reg_body<NT, RPL, CPW>(a, (int)gridDim.x, (int)blockIdx.x);
+}
+
+// Several QRCPs in one cooperative launch: gang r is workgroups
+// start[r] .. start[r + 1] - 1, each gang with its own matrix, outputs and
+// exchange words (the serving form batches the small steps of the requests
+// it admits together).
+constexpr int kMaxGangs = 16;
+struct QrcpGangs {
+  int ngang;
+  int start[kMaxGangs + 1];
+  QrcpArgs a[kMaxGangs];
+};
+
+template <int NT, int RPL, int CPW>
+__global__ void __launch_bounds__(NT) qrcp_reg_batch_kernel(QrcpGangs gs) {
+  int r = 0;
+  while (r + 1 < gs.ngang && (int)blockIdx.x >= gs.start[r + 1]) ++r;
+  qrcp_reg_body<NT, RPL, CPW>(gs.a[r], gs.start[r + 1] - gs.start[r],
+                              (int)blockIdx.x - gs.start[r]);
+}
+
 // Zero the exchange words (flags included) and the abort word before a
 // cooperative launch.
 __global__ void qrcp_reset_kernel(uint64_t* words, size_t nwords) {
@@ -884,22 +909,27 @@ QrcpPlan plan_qrcp(int d, int n) {
   return p;
 }
 
+template <int NT, int R, int C>
+static const void* pick_kernel(bool batch) {
+  return batch ? (const void*)qrcp_reg_batch_kernel<NT, R, C> : (const void*)qrcp_reg_kernel<NT, R, C>;
+}
+
 template <int R>
-static const void* reg_kernel_r(int threads, int cpw) {
+static const void* reg_kernel_r(int threads, int cpw, bool batch) {
   constexpr int TW = wide_threads(R);
   constexpr int CM = cpw_max(R);
-  if (threads == 256 && cpw == 1) return (const void*)qrcp_reg_kernel<256, R, 1>;
+  if (threads == 256 && cpw == 1) return pick_kernel<256, R, 1>(batch);
   if constexpr (TW == 512)
-    if (threads == 512 && cpw == 1) return (const void*)qrcp_reg_kernel<512, R, 1>;
-  if (threads == TW && cpw == 2) return (const void*)qrcp_reg_kernel<TW, R, 2>;
+    if (threads == 512 && cpw == 1) return pick_kernel<512, R, 1>(batch);
+  if (threads == TW && cpw == 2) return pick_kernel<TW, R, 2>(batch);
   if constexpr (CM > 2)
-    if (threads == TW && cpw == CM) return (const void*)qrcp_reg_kernel<TW, R, CM>;
+    if (threads == TW && cpw == CM) return pick_kernel<TW, R, CM>(batch);
   return nullptr;
 }
 
-static const void* reg_kernel(int rpl, int threads, int cpw) {
+static const void* reg_kernel(int rpl, int threads, int cpw, bool batch = false) {
 #define CQ_REG(R) \
-  if (rpl == R) return reg_kernel_r<R>(threads, cpw);
+  if (rpl == R) return reg_kernel_r<R>(threads, cpw, batch);
   CQ_REG(1) CQ_REG(2) CQ_REG(4) CQ_REG(6) CQ_REG(8) CQ_REG(10)
   CQ_REG(12) CQ_REG(16) CQ_REG(20) CQ_REG(24) CQ_REG(32) CQ_REG(40)
 #undef CQ_REG
@@ -910,14 +940,12 @@ size_t qrcp_ws_bytes(const QrcpPlan& p) {
   return p.stage_bytes + p.cand_bytes + p.beta_bytes + p.sync_bytes;
 }
 
-hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, int64_t* J,
-                       double* R, int64_t ldr, void* ws, cqrrpt_info_t* info, hipStream_t s,
-                       bool nopivot) {
-  if (!p.reg && (p.cols_per_block > kMaxCols || p.nblocks > kThreads))
-    return hipErrorInvalidValue;
+// Kernel arguments of one QRCP on the workspace ws laid out by plan p.
+static QrcpArgs qrcp_args(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, int64_t* J,
+                          double* R, int64_t ldr, void* ws, cqrrpt_info_t* info, bool nopivot) {
   const int G = p.nblocks;
   char* base = static_cast<char*>(ws);
-  QrcpArgs a;
+  QrcpArgs a{};
   a.X = X;
   a.ldx = ldx;
   a.d = d;
@@ -937,9 +965,13 @@ hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, 
   a.abort = reinterpret_cast<int*>(base + p.stage_bytes + p.cand_bytes + p.beta_bytes);
   a.info = info;
   a.nopivot = nopivot ? 1 : 0;
+  return a;
+}
 
-  // Zero the exchange words (all flagged words, or the tags) and the abort
-  // word before the cooperative launch.
+// Zero the exchange words (all flagged words, or the tags) and the abort
+// word before the cooperative launch.
+static hipError_t qrcp_reset(const QrcpPlan& p, const QrcpArgs& a, hipStream_t s) {
+  const int G = p.nblocks;
   uint64_t* zero_at = p.reg ? a.fstage : reinterpret_cast<uint64_t*>(a.tag);
   const size_t zero_words =
       p.reg ? (p.stage_bytes + p.cand_bytes) / 8 : align256((size_t)2 * G * 4) / 8;
@@ -949,9 +981,17 @@ hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(qrcp_reset_kernel, dim3(1), dim3(64), 0, s,
                      reinterpret_cast<uint64_t*>(a.abort), (size_t)1);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
 
+hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, int64_t* J,
+                       double* R, int64_t ldr, void* ws, cqrrpt_info_t* info, hipStream_t s,
+                       bool nopivot) {
+  if (!p.reg && (p.cols_per_block > kMaxCols || p.nblocks > kThreads))
+    return hipErrorInvalidValue;
+  QrcpArgs a = qrcp_args(p, X, ldx, d, n, J, R, ldr, ws, info, nopivot);
+  hipError_t e = qrcp_reset(p, a, s);
+  if (e != hipSuccess) return e;
   const void* fn;
   int threads;
   if (p.reg) {
@@ -971,6 +1011,64 @@ hipError_t launch_qrcp(const QrcpPlan& p, double* X, int64_t ldx, int d, int n, 
   void* args[] = {&a};
   return hipLaunchCooperativeKernel(fn, dim3(p.nblocks), dim3(threads), args,
                                     (unsigned)p.lds_bytes, s);
+}
+
+bool qrcp_batchable(int d, int n) { return plan_qrcp(d, n).reg; }
+
+// Items with the same register shape share one cooperative launch, one gang
+// of workgroups each (the same kernel body and workgroup count as a launch
+// of its own, so the same bits). Shapes are launched in the order they first
+// appear.
+hipError_t launch_qrcp_batch(const QrcpBatchItem* items, int count, hipStream_t s) {
+  std::vector<int> done((size_t)count, 0);
+  for (int i0 = 0; i0 < count; ++i0) {
+    if (done[i0]) continue;
+    const QrcpPlan p0 = plan_qrcp(items[i0].d, items[i0].n);
+    if (!p0.reg) return hipErrorInvalidValue;
+    const void* fn = reg_kernel(p0.rpl, p0.threads, p0.cpw, true);
+    if (!fn) return hipErrorInvalidValue;
+    // Dynamic LDS: the shape's v array plus the widest item's sign flags.
+    size_t lds = p0.lds_bytes;
+    for (int i = i0; i < count; ++i) {
+      if (done[i]) continue;
+      const QrcpPlan p = plan_qrcp(items[i].d, items[i].n);
+      if (p.reg && p.rpl == p0.rpl && p.threads == p0.threads && p.cpw == p0.cpw)
+        lds = std::max(lds, p.lds_bytes);
+    }
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, p0.threads, lds);
+    if (e != hipSuccess) return e;
+    const int capacity = per_cu * device_info().num_cu;
+    int i = i0;
+    while (i < count) {
+      QrcpGangs gs;
+      gs.ngang = 0;
+      gs.start[0] = 0;
+      int total = 0;
+      for (; i < count && gs.ngang < kMaxGangs; ++i) {
+        if (done[i]) continue;
+        const QrcpPlan p = plan_qrcp(items[i].d, items[i].n);
+        if (!(p.reg && p.rpl == p0.rpl && p.threads == p0.threads && p.cpw == p0.cpw)) continue;
+        if (p.nblocks > capacity) return hipErrorCooperativeLaunchTooLarge;
+        if (total + p.nblocks > capacity) break;
+        const QrcpBatchItem& it = items[i];
+        gs.a[gs.ngang] = qrcp_args(p, it.X, it.ldx, it.d, it.n, it.J, it.R, it.ldr, it.ws,
+                                   it.info, false);
+        e = qrcp_reset(p, gs.a[gs.ngang], s);
+        if (e != hipSuccess) return e;
+        total += p.nblocks;
+        gs.start[++gs.ngang] = total;
+        done[i] = 1;
+      }
+      if (gs.ngang == 0) break;
+      void* args[] = {&gs};
+      e = hipLaunchCooperativeKernel(fn, dim3(total), dim3(p0.threads), args, (unsigned)lds, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_rank_stage1(const double* R, int64_t ldr, int n, double tol, double* rn2,

@@ -10,8 +10,14 @@
 //   * Slots: max_slots streams (default priority) with one completion event
 //     each. A request occupies a slot from admission to completion.
 //   * A scheduler thread retires finished requests (event query), then
-//     admits the oldest pending request while it fits (no overtaking, so no
-//     request starves), launching its stream-ordered factorization.
+//     admits pending requests in arrival order while slots and memory allow
+//     (no overtaking, so no request starves). The requests admitted together
+//     form a batch: each runs its sketch, its rank stage, preconditioning
+//     solve and Gram, and its Q and R products on its own slot stream, while
+//     their QRCPs and their Cholesky steps run as one cooperative launch each
+//     (one gang of workgroups per request) on the server's small-step
+//     stream, ordered by events. Cooperative launches of separate requests
+//     would run one after another; in one launch they run side by side.
 //   * Results do not depend on the mix: every kernel of the factorization
 //     has a fixed reduction order and touches only its own request's
 //     buffers, so a request returns the same bits alone and among others.
@@ -91,6 +97,7 @@ struct Request {
   size_t ws_off = 0;
   int slot = -1;
   int state = 0;  // 0 pending, 1 running, 2 done
+  cqh::Phased* ph = nullptr;
   int rc = 0;
   double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
 };
@@ -105,7 +112,10 @@ struct cqrrpt_server {
   Arena* arena = nullptr;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> done_ev;
+  std::vector<hipEvent_t> front_ev;  // per slot: sketch done / Gram done
   std::vector<Request*> slot_req;
+  hipStream_t small = nullptr;         // batched QRCP and Cholesky launches
+  hipEvent_t small_ev = nullptr;
   // Per slot, pinned host copy of the running request's device status word
   // (info->status), copied on the slot's stream before its completion event.
   int32_t* status_host = nullptr;
@@ -123,6 +133,7 @@ struct cqrrpt_server {
   void schedule();
   bool retire_locked();
   void admit_locked();
+  void launch_batch(std::vector<Request*>& batch);
 };
 
 bool cqrrpt_server::retire_locked() {
@@ -147,42 +158,119 @@ bool cqrrpt_server::retire_locked() {
 }
 
 void cqrrpt_server::admit_locked() {
+  std::vector<Request*> batch;
+  std::vector<char> taken(slot_req.size(), 0);
   while (!pending.empty()) {
     int slot = -1;
     for (size_t s = 0; s < slot_req.size(); ++s)
-      if (!slot_req[s]) {
+      if (!slot_req[s] && !taken[s]) {
         slot = (int)s;
         break;
       }
-    if (slot < 0) return;
+    if (slot < 0) break;
     Request* r = pending.front();
     const size_t off = arena->alloc(r->ws_bytes);
-    if (off == Arena::kNone) return;  // wait for memory; no overtaking
+    if (off == Arena::kNone) break;  // wait for memory; no overtaking
     pending.pop_front();
     r->ws_off = off;
     r->slot = slot;
     r->t_admit = now_ms();
+    taken[slot] = 1;
+    batch.push_back(r);
+  }
+  if (!batch.empty()) launch_batch(batch);
+}
+
+// Enqueues a batch: per request, its phases on its slot stream; the QRCPs
+// and Cholesky steps of the batch in one launch each on the small-step
+// stream, which waits for the requests' earlier phases and which the slot
+// streams wait for in turn. A request whose setup fails finishes at once.
+void cqrrpt_server::launch_batch(std::vector<Request*>& batch) {
+  std::vector<Request*> live;
+  for (Request* r : batch) {
+    const int slot = r->slot;
     status_host[slot] = 0;
-    r->rc = cqrrpt_factor_ex(r->A, r->lda, r->m, r->n, r->d, r->nnz, r->seed, r->tol, r->Q,
-                             r->ldq, r->R, r->ldr, r->J, mode, base + off, r->ws_bytes,
-                             streams[slot], r->info);
-    if (r->rc == CQRRPT_OK &&
-        hipMemcpyAsync(&status_host[slot], &r->info->status, sizeof(int32_t),
-                       hipMemcpyDeviceToHost, streams[slot]) != hipSuccess)
-      r->rc = CQRRPT_EHIP;
-    if (r->rc == CQRRPT_OK && hipEventRecord(done_ev[slot], streams[slot]) != hipSuccess)
-      r->rc = CQRRPT_EHIP;
-    if (r->rc != CQRRPT_OK) {
+    int rc = CQRRPT_OK;
+    r->ph = cqh::phased_begin(r->A, r->lda, r->m, r->n, r->d, r->nnz, r->seed, r->tol, r->Q,
+                              r->ldq, r->R, r->ldr, r->J, mode, base + r->ws_off, r->ws_bytes,
+                              streams[slot], r->info, &rc);
+    if (r->ph && rc == CQRRPT_OK) rc = cqh::phased_sketch(r->ph);
+    if (rc == CQRRPT_OK && hipEventRecord(front_ev[slot], streams[slot]) != hipSuccess)
+      rc = CQRRPT_EHIP;
+    r->rc = rc;
+    if (rc != CQRRPT_OK) {
       // Nothing (or not everything) was enqueued: finish at once.
       (void)hipStreamSynchronize(streams[slot]);
+      if (r->ph) cqh::phased_end(r->ph);
+      r->ph = nullptr;
       r->t_done = now_ms();
       r->state = 2;
-      arena->release(off, r->ws_bytes);
+      arena->release(r->ws_off, r->ws_bytes);
       continue;
     }
     r->state = 1;
     slot_req[slot] = r;
     ++running;
+    live.push_back(r);
+  }
+  if (live.empty()) return;
+  auto fail = [&](Request* r, int rc) {
+    if (r->rc == CQRRPT_OK) r->rc = rc;
+  };
+  // QRCPs: the register-resident ones batched, the others on their own
+  // streams.
+  std::vector<cqh::QrcpBatchItem> qitems;
+  for (Request* r : live) {
+    if (!cqh::phased_batchable(r->ph)) continue;
+    if (hipStreamWaitEvent(small, front_ev[r->slot], 0) != hipSuccess) fail(r, CQRRPT_EHIP);
+    qitems.push_back(cqh::phased_qrcp_item(r->ph));
+  }
+  bool qok = true;
+  if (!qitems.empty()) {
+    qok = cqh::launch_qrcp_batch(qitems.data(), (int)qitems.size(), small) == hipSuccess &&
+          hipEventRecord(small_ev, small) == hipSuccess;
+  }
+  for (Request* r : live) {
+    hipStream_t st = streams[r->slot];
+    int rc = CQRRPT_OK;
+    if (cqh::phased_batchable(r->ph)) {
+      if (!qok || hipStreamWaitEvent(st, small_ev, 0) != hipSuccess) rc = CQRRPT_EHIP;
+      cqh::phased_mark(r->ph, 2);
+    } else {
+      rc = cqh::phased_qrcp(r->ph);
+    }
+    if (rc == CQRRPT_OK) rc = cqh::phased_tall(r->ph);
+    if (rc == CQRRPT_OK && hipEventRecord(front_ev[r->slot], st) != hipSuccess) rc = CQRRPT_EHIP;
+    if (rc != CQRRPT_OK) fail(r, rc);
+  }
+  // Cholesky steps, batched.
+  std::vector<cqh::CholBatchItem> citems;
+  for (Request* r : live) {
+    if (hipStreamWaitEvent(small, front_ev[r->slot], 0) != hipSuccess) fail(r, CQRRPT_EHIP);
+    citems.push_back(cqh::phased_chol_item(r->ph));
+  }
+  const bool cok = cqh::launch_cholesky_batch(citems.data(), (int)citems.size(), small) ==
+                       hipSuccess &&
+                   hipEventRecord(small_ev, small) == hipSuccess;
+  for (Request* r : live) {
+    const int slot = r->slot;
+    hipStream_t st = streams[slot];
+    int rc = CQRRPT_OK;
+    if (!cok || hipStreamWaitEvent(st, small_ev, 0) != hipSuccess) rc = CQRRPT_EHIP;
+    cqh::phased_mark(r->ph, 6);
+    if (rc == CQRRPT_OK) rc = cqh::phased_tail(r->ph);
+    if (rc != CQRRPT_OK) fail(r, rc);
+    if (hipMemcpyAsync(&status_host[slot], &r->info->status, sizeof(int32_t),
+                       hipMemcpyDeviceToHost, st) != hipSuccess)
+      fail(r, CQRRPT_EHIP);
+    if (hipEventRecord(done_ev[slot], st) != hipSuccess) {
+      // The request cannot be tracked on the device: wait for it here.
+      fail(r, CQRRPT_EHIP);
+      (void)hipStreamSynchronize(st);
+      (void)hipEventRecord(done_ev[slot], nullptr);
+    }
+    cqh::phased_end(r->ph);
+    r->ph = nullptr;
   }
 }
 
@@ -231,22 +319,32 @@ cqrrpt_server_t* cqrrpt_server_create(size_t hbm_budget_bytes, int32_t max_slots
     return nullptr;
   }
   sv->arena = new Arena(sv->budget);
-  sv->streams.resize(max_slots);
-  sv->done_ev.resize(max_slots);
+  sv->streams.assign(max_slots, nullptr);
+  sv->done_ev.assign(max_slots, nullptr);
+  sv->front_ev.assign(max_slots, nullptr);
   sv->slot_req.assign(max_slots, nullptr);
-  for (int s = 0; s < max_slots; ++s) {
-    if (hipStreamCreateWithFlags(&sv->streams[s], hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&sv->done_ev[s], hipEventDisableTiming) != hipSuccess) {
-      for (int t = 0; t <= s; ++t) {
-        if (sv->streams[t]) (void)hipStreamDestroy(sv->streams[t]);
-        if (sv->done_ev[t]) (void)hipEventDestroy(sv->done_ev[t]);
-      }
-      (void)hipFree(sv->base);
-      (void)hipHostFree(sv->status_host);
-      delete sv->arena;
-      delete sv;
-      return nullptr;
+  auto cleanup = [sv]() {
+    for (size_t t = 0; t < sv->streams.size(); ++t) {
+      if (sv->streams[t]) (void)hipStreamDestroy(sv->streams[t]);
+      if (sv->done_ev[t]) (void)hipEventDestroy(sv->done_ev[t]);
+      if (sv->front_ev[t]) (void)hipEventDestroy(sv->front_ev[t]);
     }
+    if (sv->small) (void)hipStreamDestroy(sv->small);
+    if (sv->small_ev) (void)hipEventDestroy(sv->small_ev);
+    (void)hipFree(sv->base);
+    (void)hipHostFree(sv->status_host);
+    delete sv->arena;
+    delete sv;
+  };
+  bool ok = hipStreamCreateWithFlags(&sv->small, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&sv->small_ev, hipEventDisableTiming) == hipSuccess;
+  for (int s = 0; ok && s < max_slots; ++s)
+    ok = hipStreamCreateWithFlags(&sv->streams[s], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&sv->done_ev[s], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&sv->front_ev[s], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    cleanup();
+    return nullptr;
   }
   sv->worker = std::thread([sv] { sv->schedule(); });
   return sv;
@@ -345,11 +443,15 @@ void cqrrpt_server_destroy(cqrrpt_server_t* sv) {
   }
   sv->cv.notify_one();
   if (sv->worker.joinable()) sv->worker.join();
+  (void)hipStreamSynchronize(sv->small);
   for (size_t s = 0; s < sv->streams.size(); ++s) {
     (void)hipStreamSynchronize(sv->streams[s]);
     (void)hipStreamDestroy(sv->streams[s]);
     (void)hipEventDestroy(sv->done_ev[s]);
+    (void)hipEventDestroy(sv->front_ev[s]);
   }
+  (void)hipStreamDestroy(sv->small);
+  (void)hipEventDestroy(sv->small_ev);
   (void)hipFree(sv->base);
   (void)hipHostFree(sv->status_host);
   for (auto& kv : sv->all) delete kv.second;

@@ -139,7 +139,9 @@ CQ_INLINE void shift_update(double (&v)[kB], const lds_cdouble* row, double s, H
   }
 }
 
-__global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
+// The Cholesky step of one Gram on G workgroups, this one being number g
+// (a whole launch, or one gang of a batched launch).
+__device__ __forceinline__ void chol_body(const CholArgs& a, const int G, const int g) {
   // D and YB carry 16 extra values: the factor's row updates read a fixed
   // number of values past the diagonal (results for rows past the block are
   // discarded).
@@ -149,8 +151,6 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
   __shared__ double IR[kB];
   __shared__ int s_fail;
 
-  const int G = gridDim.x;
-  const int g = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -604,6 +604,25 @@ __global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
   }
 }
 
+__global__ void __launch_bounds__(kThreads) chol_kernel(CholArgs a) {
+  chol_body(a, (int)gridDim.x, (int)blockIdx.x);
+}
+
+// Several Cholesky steps in one cooperative launch: gang r is workgroups
+// start[r] .. start[r + 1] - 1 (the serving form's batched small steps).
+constexpr int kMaxCholGangs = 16;
+struct CholGangs {
+  int ngang;
+  int start[kMaxCholGangs + 1];
+  CholArgs a[kMaxCholGangs];
+};
+
+__global__ void __launch_bounds__(kThreads) chol_batch_kernel(CholGangs gs) {
+  int r = 0;
+  while (r + 1 < gs.ngang && (int)blockIdx.x >= gs.start[r + 1]) ++r;
+  chol_body(gs.a[r], gs.start[r + 1] - gs.start[r], (int)blockIdx.x - gs.start[r]);
+}
+
 // Clears the barrier words and the rank output: a launch that leaves early
 // (barrier timeout) then leaves k = 0 behind, not an earlier call's value.
 __global__ void chol_reset_kernel(unsigned* w, int nw, int64_t* kout) {
@@ -882,6 +901,58 @@ hipError_t launch_cholesky(double* G, int64_t ldg, const int64_t* ko_dev, int km
   void* args[] = {&a};
   return hipLaunchCooperativeKernel((const void*)chol_kernel, dim3(nblocks), dim3(kThreads), args,
                                     0, s);
+}
+
+hipError_t launch_cholesky_batch(const CholBatchItem* items, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, (const void*)chol_batch_kernel, kThreads, 0);
+  if (e != hipSuccess) return e;
+  const int capacity = per_cu * device_info().num_cu;
+  int i = 0;
+  while (i < count) {
+    CholGangs gs;
+    gs.ngang = 0;
+    gs.start[0] = 0;
+    int total = 0;
+    while (i < count && gs.ngang < kMaxCholGangs) {
+      const CholBatchItem& it = items[i];
+      const int nb = (it.kmax + kB - 1) / kB;
+      const int first_tasks = (nb - 1) * nb / 2;
+      int G = (first_tasks + 3) / 4;
+      G = G < 16 ? 16 : G > 64 ? 64 : G;
+      if (gs.ngang > 0 && total + G > capacity) break;
+      if (G > capacity) return hipErrorCooperativeLaunchTooLarge;
+      unsigned* w = static_cast<unsigned*>(it.ws);
+      hipLaunchKernelGGL(chol_reset_kernel, dim3(1), dim3(64), 0, s, w, 8, it.k_dev);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      CholArgs& a = gs.a[gs.ngang];
+      a.G = it.G;
+      a.ldg = it.ldg;
+      a.ko = it.ko_dev;
+      a.kout = it.k_dev;
+      a.flags = reinterpret_cast<int*>(w + 4);
+      a.W = it.W;
+      a.ldw = it.ldw;
+      a.info = it.info;
+      a.bar.count = w;
+      a.bar.abort = reinterpret_cast<int*>(w + 2);
+      a.bar.nblocks = (unsigned)G;
+      a.cond_max = it.cond_max;
+      a.record = true;
+      a.enable = nullptr;
+      total += G;
+      gs.start[++gs.ngang] = total;
+      ++i;
+    }
+    void* args[] = {&gs};
+    e = hipLaunchCooperativeKernel((const void*)chol_batch_kernel, dim3(total), dim3(kThreads),
+                                   args, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_trmm_r(const double* Rpre, int64_t ldp, const double* Rsk, int64_t ldk,
