@@ -45,24 +45,24 @@ HEADLINE = "fp64_4194304x2048_rank1536"
 # Matrix-core stages: (stage, kernel, algorithmic flops per launch from
 # (m, k_o, k)).
 MFMA_STAGES = (
-    ("precondition", "trsm_rows_kernel<double, double>", lambda m, ko, k: m * ko * ko),
-    ("gram", "gram128_kernel + gram128_reduce_kernel", lambda m, ko, k: m * ko * (ko + 1)),
-    ("q_solve", "qform_kernel<double, double, double>", lambda m, ko, k: m * k * k),
+    ("precondition", "trsm_rows_kernel<128, double, double>", lambda m, ko, k: m * ko * ko),
+    ("gram", "gram_dv_kernel<16, 1> + gram128_reduce_kernel", lambda m, ko, k: m * ko * (ko + 1)),
+    ("q_solve", "qform_kernel<256, double, double, double>", lambda m, ko, k: m * k * k),
 )
 MIXED_STAGES = (
-    ("precondition", "trsm_rows_kernel<float, float>", lambda m, ko, k: m * ko * ko,
+    ("precondition", "trsm_rows_kernel<128, float, float>", lambda m, ko, k: m * ko * ko,
      PEAK_FP32_MFMA),
     ("gram", "syrk_kernel<float> + syrk_reduce_kernel", lambda m, ko, k: m * ko * (ko + 1),
      PEAK_FP64_MFMA),
-    ("q_solve", "qform_kernel<float, double, double>", lambda m, ko, k: m * k * k,
+    ("q_solve", "qform_kernel<256, float, double, double>", lambda m, ko, k: m * k * k,
      PEAK_FP64_MFMA),
 )
 FP32_LINES_STAGES = (
-    ("precondition", "trsm_rows_kernel<float, float>", lambda m, ko, k: m * ko * ko,
+    ("precondition", "trsm_rows_kernel<128, float, float>", lambda m, ko, k: m * ko * ko,
      PEAK_FP32_MFMA),
     ("gram", "gram128_kernel<float, float> + gram128_reduce_kernel",
      lambda m, ko, k: m * ko * (ko + 1), PEAK_FP32_MFMA),
-    ("q_solve", "qform_kernel<float, double, float>", lambda m, ko, k: m * k * k,
+    ("q_solve", "qform_kernel<256, float, double, float>", lambda m, ko, k: m * k * k,
      PEAK_FP32_MFMA),
 )
 
@@ -202,14 +202,18 @@ def rooflines(stages, w, ko, k, mixed=False, fp32_lines=False):
 
 
 def kernel_source_hash():
-    with open(os.path.join(HERE, "paper_2311_08316_amd", "csrc", "tall.hip"), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the sources of the three matrix-core stages (tall.hip, gram.hip)."""
+    h = hashlib.sha256()
+    for name in ("tall.hip", "gram.hip"):
+        with open(os.path.join(HERE, "paper_2311_08316_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(stage):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, if it was taken on the current kernel source; else None."""
-    name = {"precondition": "trsm", "gram": "gram128", "q_solve": "qform"}.get(stage)
+    name = {"precondition": "trsm", "gram": "gram_dv", "q_solve": "qform"}.get(stage)
     if name is None:
         return None
     path = os.path.join(HERE, "profiles", f"{name}_fp64_4194304x2048_traffic.txt")
@@ -221,7 +225,7 @@ def measured_traffic(stage):
             if "=" in line and not line.startswith("#"):
                 key, val = line.split("=", 1)
                 vals[key.strip()] = val.strip()
-    if vals.get("tall_hip_sha256_16") != kernel_source_hash():
+    if vals.get("kernel_sources_sha256_16") != kernel_source_hash():
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])

@@ -29,6 +29,9 @@ FLAGS = [
 # code that reads the sums (the Gram's compensated fold).
 EXTRA = {
     "tall.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+    # The directly loaded Gram: in accumulation registers every accumulator
+    # was copied out and back on each trip of the K loop.
+    "gram.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
     # The throughput probe's accumulators too (in accumulation registers they
     # were copied out and back around every round of the loop).
     "probe.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],

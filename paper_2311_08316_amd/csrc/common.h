@@ -393,6 +393,19 @@ int gram_splits(int64_t m, int kmax);
 hipError_t launch_gram_f64(const double* X, int64_t ldx, int64_t m, const int64_t* kdev,
                            int kmax, double* partials, double* G, int64_t ldg,
                            const cqrrpt_info_t* info, hipStream_t s);
+// The 128 x 128 FP64 Gram with operands loaded straight into registers
+// (X 16-byte aligned, ldx even: gram_dv_supported); at most gram_splits
+// splits, so its partials fit where the 128 x 128 Gram's do.
+bool gram_dv_supported(const double* X, int64_t ldx);
+int gram_dv_splits(int64_t m, int kmax);
+hipError_t launch_gram_dv_f64(const double* X, int64_t ldx, int64_t m, const int64_t* kdev,
+                              int kmax, double* partials, double* G, int64_t ldg,
+                              const cqrrpt_info_t* info, hipStream_t s);
+// Sum of the row-major 128 x 128 partial tiles over the splits, in split
+// order, into the upper triangle of G[:k, :k].
+hipError_t launch_gram128_reduce(const double* partials, int nsplit, int tiles,
+                                 const int64_t* kdev, double* G, int64_t ldg,
+                                 const cqrrpt_info_t* info, hipStream_t s);
 // The same Gram of FP32 data on FP32 matrix cores with FP32 accumulation
 // (partials and G in FP64 storage).
 hipError_t launch_gram_f32(const float* X, int64_t ldx, int64_t m, const int64_t* kdev,

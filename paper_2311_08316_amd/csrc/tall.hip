@@ -39,7 +39,7 @@ template <> CQ_INLINE int acc_row<double>(int lq, int r) { return lq + 4 * r; }
 template <> CQ_INLINE int acc_row<float>(int lq, int r) { return 4 * lq + r; }
 
 // Triangular solve X R = B (R upper, non-unit), left-looking per row block.
-// A workgroup of kTThreads owns kRT rows and walks column panels of width
+// A workgroup of 2 RT threads owns RT rows and walks column panels of width
 // kPW:
 //   acc = X[rows, :c0] R[:c0, panel]                 (MFMA)
 // then solves the panel's diagonal block 16 columns at a time:
@@ -47,33 +47,31 @@ template <> CQ_INLINE int acc_row<float>(int lq, int r) { return 4 * lq + r; }
 //   X_t = T_t inv(R_tt)                              (MFMA, inverse precomputed)
 //   acc[:, tiles > t] += X_t R[tile t, tiles > t]    (MFMA)
 // Wide panels keep the re-reads of the already solved columns (the K operand
-// of the product) at m n^2 / (2 kPW) values in total.
-constexpr int kTThreads = 256;  // 4 waves; two workgroups per CU
-constexpr int kRT = 128;        // rows per workgroup
+// of the product) at m n^2 / (2 kPW) values in total; more rows per
+// workgroup divide the reads of R (and of W in the Q product) the same way.
 constexpr int kPW = 128;        // panel width
 constexpr int kKB = 16;         // K per staging step
-constexpr int kSLd = 144;       // LDS row pitch: 128 + 16 keeps lane groups on distinct banks
+// Rows per workgroup, measured at 4194304 x 2048: the Q product 313 ms with
+// 256 rows (eight waves, one workgroup per CU) against 328 ms with 128 (four
+// waves, two per CU); the solve 316 ms with 128 against 320 ms with 256.
+constexpr int kTRT = 128;  // rows per workgroup of the solve
+constexpr int kQRT = 256;  // rows per workgroup of the Q product
 
-// LDS (units of TC): staging 2 x (X tile kKB x kRT with rows padded to kSLd,
-// R tile kPW x kKB transposed with rows padded to kWLd); during the diagonal
-// phase the same space holds the tile of B (then T_t, then X_t; 16 x kRT,
-// column-major), the R strip (transposed, kPW x 16) and the accumulator
-// tile (16 x kRT).
-constexpr int kTileSz = kKB * kSLd;
+// LDS (units of TC): staging 2 x (X tile kKB x RT with rows padded to
+// RT + 16, which keeps lane groups on distinct banks; R tile kPW x kKB
+// transposed with rows padded to kWLd); during the diagonal phase of the
+// solve the same space holds the R strips (transposed, kPW x 16) and, in
+// FP32, each wave's regroup tile.
+template <int RT> constexpr int qform_sld() { return RT + 16; }
 // Tiles of R (or W) are kept transposed, [column][K] with a pitch of kWLd:
 // the stores (K fastest across lanes, as loaded from the column-major
 // matrix) and the operand reads (K = lane / 16, column = lane % 16) then
-// spread over the banks; a [K][column] layout at a pitch of kSLd put the
+// spread over the banks; a [K][column] layout at a pitch of RT + 16 put the
 // stores on one bank in eight.
-#ifndef CQ_WLD
-#define CQ_WLD 20
-#endif
-constexpr int kWLd = CQ_WLD;
+constexpr int kWLd = 20;
 constexpr int kWTile = kPW * kWLd;
-constexpr int kQStage = kTileSz + kWTile;  // one staging buffer: B/X tile, then R tile
-constexpr int kTrsmLds = 2 * kQStage;
-// After the TC area: the panel's gathered column indices (int32).
-constexpr size_t kTrsmLdsBytes(size_t tc_bytes) { return kTrsmLds * tc_bytes + kPW * 4; }
+// One staging buffer: the X (or M) tile, then the R (or W) tile.
+template <int RT> constexpr int qform_stage() { return kKB * qform_sld<RT>() + kWTile; }
 
 // R[i, j] through a 32-bit element offset (the launcher checks that every
 // offset of the k x k block fits).
@@ -137,8 +135,8 @@ trsm_inv_kernel(const double* __restrict__ R, int64_t ldr, const int64_t* kdev, 
 // The off-diagonal K loop stages X and R tiles through double-buffered LDS
 // with one register stage of prefetch (a second stage made the compiler
 // spill inside the loop).
-template <typename TX, typename TC>
-__global__ void __launch_bounds__(kTThreads, 2)
+template <int RT, typename TX, typename TC>
+__global__ void __launch_bounds__(2 * RT, RT == 128 ? 2 : 1)
 trsm_rows_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gather, TX* X,
                  int64_t ldx, const double* __restrict__ R, int64_t ldr, int64_t m,
                  const int64_t* kdev, const double* __restrict__ inv, const cqrrpt_info_t* info,
@@ -150,7 +148,10 @@ trsm_rows_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gathe
   constexpr bool kRegroup = std::is_same<TC, float>::value;
   extern __shared__ unsigned char smem_raw[];
   TC* lds = reinterpret_cast<TC*>(smem_raw);
-  int* gcols = reinterpret_cast<int*>(lds + kTrsmLds);  // [kPW]
+  constexpr int kThr = 2 * RT;
+  constexpr int kSL = qform_sld<RT>();
+  constexpr int kStage = qform_stage<RT>();
+  int* gcols = reinterpret_cast<int*>(lds + 2 * kStage);  // [kPW]
 
   if (info->status != 0 || (enable && *enable == 0)) return;
   const int k = (int)*kdev;
@@ -160,9 +161,11 @@ trsm_rows_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gathe
   const int wave = tid >> 6;
   const int l16 = lane & 15;
   const int lq = lane >> 4;
-  const int64_t row0 = (int64_t)blockIdx.x * kRT;
-  constexpr int kLoads = kKB * kRT / kTThreads;  // 8 per operand and step
-  const int ra = tid & (kRT - 1), ca = tid >> 7;
+  const int64_t row0 = (int64_t)blockIdx.x * RT;
+  constexpr int kLoads = kKB * RT / kThr;    // 8 values of X per thread and step
+  constexpr int kRLoads = kKB * kPW / kThr;  // values of R per thread and step
+  constexpr int kRStride = kThr / 16;        // column stride of a thread's R values
+  const int ra = tid & (RT - 1), ca = tid / RT;
   const int rb = tid & 15, cb = tid >> 4;
   const int64_t rowa = row0 + ra < m ? row0 + ra : m - 1;
   const uint32_t ldr32 = (uint32_t)ldr;
@@ -183,34 +186,34 @@ trsm_rows_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gathe
 
     if (c0o > 0) {
       TX areg0[kLoads];
-      double rreg0[kLoads];
-      auto load = [&](int kk, TX (&ar)[kLoads], double (&rr)[kLoads]) {
+      double rreg0[kRLoads];
+      auto load = [&](int kk, TX (&ar)[kLoads], double (&rr)[kRLoads]) {
         const TX* xs = X + rowa + (int64_t)(kk + ca) * ldx;
 #pragma unroll
         for (int q = 0; q < kLoads; ++q) ar[q] = xs[(int64_t)(2 * q) * ldx];
 #pragma unroll
-        for (int q = 0; q < kLoads; ++q) {
-          const int col = c0o + cb + 16 * q;
+        for (int q = 0; q < kRLoads; ++q) {
+          const int col = c0o + cb + kRStride * q;
           rr[q] = r_at(R, ldr32, kk + rb, col < k ? col : k - 1);
         }
       };
-      auto store = [&](int buf, const TX (&ar)[kLoads], const double (&rr)[kLoads]) {
-        TC* At = lds + buf * kQStage;
-        TC* Rt = At + kTileSz;
+      auto store = [&](int buf, const TX (&ar)[kLoads], const double (&rr)[kRLoads]) {
+        TC* At = lds + buf * kStage;
+        TC* Rt = At + kKB * kSL;
 #pragma unroll
-        for (int q = 0; q < kLoads; ++q) At[(ca + 2 * q) * kSLd + ra] = (TC)ar[q];
+        for (int q = 0; q < kLoads; ++q) At[(ca + 2 * q) * kSL + ra] = (TC)ar[q];
 #pragma unroll
-        for (int q = 0; q < kLoads; ++q)
-          Rt[(cb + 16 * q) * kWLd + rb] = c0o + cb + 16 * q < k ? (TC)rr[q] : (TC)0;
+        for (int q = 0; q < kRLoads; ++q)
+          Rt[(cb + kRStride * q) * kWLd + rb] = c0o + cb + kRStride * q < k ? (TC)rr[q] : (TC)0;
       };
       auto multiply = [&](int buf) {
-        const TC* At = lds + buf * kQStage;
-        const TC* Rt = At + kTileSz;
+        const TC* At = lds + buf * kStage;
+        const TC* Rt = At + kKB * kSL;
 #pragma unroll
         for (int s = 0; s < kKB / 4; ++s) {
           TC xb[2], rf[8];
 #pragma unroll
-          for (int a = 0; a < 2; ++a) xb[a] = At[(4 * s + lq) * kSLd + 32 * wave + 16 * a + l16];
+          for (int a = 0; a < 2; ++a) xb[a] = At[(4 * s + lq) * kSL + 32 * wave + 16 * a + l16];
 #pragma unroll
           for (int b = 0; b < 8; ++b) rf[b] = Rt[(16 * b + l16) * kWLd + 4 * s + lq];
 #pragma unroll
@@ -249,20 +252,20 @@ trsm_rows_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gathe
       rowl[a] = row0 + 32 * wave + 16 * a + l16;
       rowc[a] = rowl[a] < m ? rowl[a] : m - 1;
     }
-    double sreg[kLoads];
+    double sreg[kRLoads];
     auto load_strip = [&](int t) {
       const int ri = c0o + 16 * t + rb;
 #pragma unroll
-      for (int q = 0; q < kLoads; ++q) {
-        const int cj = c0o + cb + 16 * q;
+      for (int q = 0; q < kRLoads; ++q) {
+        const int cj = c0o + cb + kRStride * q;
         sreg[q] = r_at(R, ldr32, ri < k ? ri : k - 1, cj < k ? cj : k - 1);
       }
     };
     auto store_strip = [&](int t, TC* Rs) {
 #pragma unroll
-      for (int q = 0; q < kLoads; ++q)
-        Rs[(cb + 16 * q) * kWLd + rb] =
-            r_entry<TC>(sreg[q], c0o + 16 * t + rb, c0o + cb + 16 * q, k);
+      for (int q = 0; q < kRLoads; ++q)
+        Rs[(cb + kRStride * q) * kWLd + rb] =
+            r_entry<TC>(sreg[q], c0o + 16 * t + rb, c0o + cb + kRStride * q, k);
     };
     double bt[2][4];
     auto load_b = [&](int t) {
@@ -356,7 +359,7 @@ hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX*
                             const double* R, int64_t ldr, int64_t m, const int64_t* kdev,
                             int kmax, double* inv, const cqrrpt_info_t* info,
                             const int* enable, hipStream_t s) {
-  const size_t lds = kTrsmLdsBytes(sizeof(TC));
+  const size_t lds = (size_t)2 * qform_stage<kTRT>() * sizeof(TC) + kPW * 4;
   // R is addressed with 32-bit element offsets.
   if (ldr <= 0 || (uint64_t)ldr * 8192u > 0xffffffffull) return hipErrorInvalidValue;
   const int ntiles = (kmax + kInvTile - 1) / kInvTile;
@@ -364,12 +367,12 @@ hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX*
                      kdev, ntiles, inv, info, enable);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t grid = (m + kRT - 1) / kRT;
-  const void* fn = (const void*)trsm_rows_kernel<TX, TC>;
+  const int64_t grid = (m + kTRT - 1) / kTRT;
+  const void* fn = (const void*)trsm_rows_kernel<kTRT, TX, TC>;
   e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((trsm_rows_kernel<TX, TC>), dim3((unsigned)grid), dim3(kTThreads), lds, s,
-                     B, ldb, gather, X, ldx, R, ldr, m, kdev, inv, info, enable);
+  hipLaunchKernelGGL((trsm_rows_kernel<kTRT, TX, TC>), dim3((unsigned)grid), dim3(2 * kTRT), lds,
+                     s, B, ldb, gather, X, ldx, R, ldr, m, kdev, inv, info, enable);
   return hipGetLastError();
 }
 
@@ -379,7 +382,7 @@ hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX*
 // as a product with the inverse, which is accurate because R_pre is well
 // conditioned (it inherits the conditioning of M_pre, the preconditioned
 // matrix of Sec. 3). No substitution remains, so every block is a plain
-// matrix-core product. A workgroup owns kRT rows and walks the 128-column
+// matrix-core product. A workgroup owns RT rows and walks the 128-column
 // panels from the last to the first, so M may alias Q: panel c reads the
 // columns below c + 128 only, which later (lower) panels have not written.
 // The K loop stages M and W tiles through double-buffered LDS with two
@@ -388,10 +391,8 @@ hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX*
 // hold the transposed tile (rows on the N index), so the stores of 16
 // consecutive lanes cover 16 consecutive rows.
 // ---------------------------------------------------------------------------
-constexpr int kQformLds = kTrsmLds;
-
-template <typename TM, typename TQ, typename TC>
-__global__ void __launch_bounds__(kTThreads, 2)
+template <int RT, typename TM, typename TQ, typename TC>
+__global__ void __launch_bounds__(2 * RT, RT == 128 ? 2 : 1)
 qform_kernel(const TM* M, int64_t ldm, TQ* Q, int64_t ldq, const double* __restrict__ W,
              int64_t ldw, int64_t m, const int64_t* kdev, const cqrrpt_info_t* info,
              const int* enable) {
@@ -402,16 +403,22 @@ qform_kernel(const TM* M, int64_t ldm, TQ* Q, int64_t ldq, const double* __restr
   if (info->status != 0 || (enable && *enable == 0)) return;
   const int k = (int)*kdev;
   if (k <= 0) return;
+  constexpr int kThr = 2 * RT;
+  constexpr int kSL = qform_sld<RT>();
+  constexpr int kStage = qform_stage<RT>();
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = wave & 1;
-  const int wc = __builtin_amdgcn_readfirstlane(wave >> 1);
+  // Waves of 64 x 64: RT / 64 row groups by two column halves.
+  const int wr = wave & (RT / 64 - 1);
+  const int wc = __builtin_amdgcn_readfirstlane(wave / (RT / 64));
   const int l16 = lane & 15;
   const int lq = lane >> 4;
-  const int64_t row0 = (int64_t)blockIdx.x * kRT;
-  constexpr int kLoads = kKB * kRT / kTThreads;  // 8 per operand and step
-  const int ra = tid & (kRT - 1), ca = tid >> 7;
+  const int64_t row0 = (int64_t)blockIdx.x * RT;
+  constexpr int kLoads = kKB * RT / kThr;    // 8 values of M per thread and step
+  constexpr int kWLoads = kKB * kPW / kThr;  // values of W per thread and step
+  constexpr int kWStride = kThr / 16;        // column stride of a thread's W values
+  const int ra = tid & (RT - 1), ca = tid / RT;
   const int rb = tid & 15, cb = tid >> 4;
   // Rows past m read row m-1 (in bounds); their results are never stored.
   const int64_t rowa = row0 + ra < m ? row0 + ra : m - 1;
@@ -429,10 +436,10 @@ qform_kernel(const TM* M, int64_t ldm, TQ* Q, int64_t ldq, const double* __restr
       for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
     TM areg0[kLoads], areg1[kLoads];
-    double wreg0[kLoads], wreg1[kLoads];
+    double wreg0[kWLoads], wreg1[kWLoads];
     // Columns of M past k read column k-1 and rows of W past k read row
     // k-1 (in bounds); the W values are masked to zero when stored.
-    auto load = [&](int kk, TM (&ar)[kLoads], double (&wv)[kLoads]) {
+    auto load = [&](int kk, TM (&ar)[kLoads], double (&wv)[kWLoads]) {
 #pragma unroll
       for (int q = 0; q < kLoads; ++q) {
         const int col = kk + ca + 2 * q;
@@ -440,22 +447,22 @@ qform_kernel(const TM* M, int64_t ldm, TQ* Q, int64_t ldq, const double* __restr
       }
       const int wrow = kk + rb < k ? kk + rb : k - 1;
 #pragma unroll
-      for (int q = 0; q < kLoads; ++q) {
-        const int col = c0o + cb + 16 * q;
+      for (int q = 0; q < kWLoads; ++q) {
+        const int col = c0o + cb + kWStride * q;
         wv[q] = W[(uint32_t)wrow + (uint32_t)(col < k ? col : k - 1) * ldw32];
       }
     };
     // The W tile is kept transposed, [column][K] (pitch kWLd).
-    auto store = [&](int buf, int kk, const TM (&ar)[kLoads], const double (&wv)[kLoads]) {
-      TC* At = lds + buf * kQStage;
-      TC* Wt = At + kTileSz;
+    auto store = [&](int buf, int kk, const TM (&ar)[kLoads], const double (&wv)[kWLoads]) {
+      TC* At = lds + buf * kStage;
+      TC* Wt = At + kKB * kSL;
 #pragma unroll
-      for (int q = 0; q < kLoads; ++q) At[(ca + 2 * q) * kSLd + ra] = (TC)ar[q];
+      for (int q = 0; q < kLoads; ++q) At[(ca + 2 * q) * kSL + ra] = (TC)ar[q];
       const int wrow = kk + rb;
 #pragma unroll
-      for (int q = 0; q < kLoads; ++q) {
-        const int col = c0o + cb + 16 * q;
-        Wt[(cb + 16 * q) * kWLd + rb] = (wrow <= col && col < k) ? (TC)wv[q] : (TC)0;
+      for (int q = 0; q < kWLoads; ++q) {
+        const int col = c0o + cb + kWStride * q;
+        Wt[(cb + kWStride * q) * kWLd + rb] = (wrow <= col && col < k) ? (TC)wv[q] : (TC)0;
       }
     };
     // K step kk is above this wave's columns' diagonal block only while kk
@@ -463,13 +470,13 @@ qform_kernel(const TM* M, int64_t ldm, TQ* Q, int64_t ldq, const double* __restr
     const int kwave = c0o + 64 * (wc + 1);
     auto multiply = [&](int buf, int kk) {
       if (kk >= kwave) return;
-      const TC* At = lds + buf * kQStage;
-      const TC* Wt = At + kTileSz;
+      const TC* At = lds + buf * kStage;
+      const TC* Wt = At + kKB * kSL;
 #pragma unroll
       for (int s = 0; s < kKB / 4; ++s) {
         TC af[4], bf[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) af[a] = At[(4 * s + lq) * kSLd + 64 * wr + 16 * a + l16];
+        for (int a = 0; a < 4; ++a) af[a] = At[(4 * s + lq) * kSL + 64 * wr + 16 * a + l16];
 #pragma unroll
         for (int b = 0; b < 4; ++b) bf[b] = Wt[(64 * wc + 16 * b + l16) * kWLd + 4 * s + lq];
 #pragma unroll
@@ -519,15 +526,15 @@ template <typename TM, typename TQ, typename TC>
 hipError_t launch_qform_impl(const TM* M, int64_t ldm, TQ* Q, int64_t ldq, const double* W,
                              int64_t ldw, int64_t m, const int64_t* kdev,
                              const cqrrpt_info_t* info, const int* enable, hipStream_t s) {
-  const size_t lds = (size_t)kQformLds * sizeof(TC);
+  const size_t lds = (size_t)2 * qform_stage<kQRT>() * sizeof(TC);
   // W is addressed with 32-bit element offsets.
   if (ldw <= 0 || (uint64_t)ldw * 8192u > 0xffffffffull) return hipErrorInvalidValue;
-  const void* fn = (const void*)qform_kernel<TM, TQ, TC>;
+  const void* fn = (const void*)qform_kernel<kQRT, TM, TQ, TC>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const int64_t grid = (m + kRT - 1) / kRT;
-  hipLaunchKernelGGL((qform_kernel<TM, TQ, TC>), dim3((unsigned)grid), dim3(kTThreads), lds, s,
-                     M, ldm, Q, ldq, W, ldw, m, kdev, info, enable);
+  const int64_t grid = (m + kQRT - 1) / kQRT;
+  hipLaunchKernelGGL((qform_kernel<kQRT, TM, TQ, TC>), dim3((unsigned)grid), dim3(2 * kQRT), lds,
+                     s, M, ldm, Q, ldq, W, ldw, m, kdev, info, enable);
   return hipGetLastError();
 }
 
@@ -742,18 +749,10 @@ gram128_kernel(const TX* __restrict__ X, int64_t ldx, int64_t m, const int64_t* 
   TC* gsm = reinterpret_cast<TC*>(gsm_raw);
   if (info->status != 0) return;
   const int64_t k = *kdev;
-#ifndef CQ_GRAM_ORDER
-#define CQ_GRAM_ORDER 0
-#endif
-#if CQ_GRAM_ORDER == 0
   const int xcd = blockIdx.x % kXcds;
   const int slot = blockIdx.x / kXcds;
   const int split = (slot / tiles) * kXcds + xcd;
   const int t = slot % tiles;
-#else
-  const int split = blockIdx.x / tiles;
-  const int t = blockIdx.x % tiles;
-#endif
   int J = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((J + 1) * (J + 2) / 2 <= t) ++J;
   while (J * (J + 1) / 2 > t) --J;
@@ -1015,7 +1014,21 @@ hipError_t launch_gram_impl(const TX* X, int64_t ldx, int64_t m, const int64_t* 
 hipError_t launch_gram_f64(const double* X, int64_t ldx, int64_t m, const int64_t* kdev,
                            int kmax, double* partials, double* G, int64_t ldg,
                            const cqrrpt_info_t* info, hipStream_t s) {
+  // Operands loaded straight into registers where 16-byte loads line up and
+  // the columns are not a multiple of 4 KiB apart (there the direct loads,
+  // twice as many requests as through LDS, met cache-channel conflicts:
+  // 469 against 365 ms at 4194304 x 2048).
+  if (gram_dv_supported(X, ldx) && (ldx * 8) % 4096 != 0)
+    return launch_gram_dv_f64(X, ldx, m, kdev, kmax, partials, G, ldg, info, s);
   return launch_gram_impl<double, double>(X, ldx, m, kdev, kmax, partials, G, ldg, info, s);
+}
+
+hipError_t launch_gram128_reduce(const double* partials, int nsplit, int tiles,
+                                 const int64_t* kdev, double* G, int64_t ldg,
+                                 const cqrrpt_info_t* info, hipStream_t s) {
+  hipLaunchKernelGGL(gram128_reduce_kernel, dim3(kGT * kGT / kThreads, (unsigned)tiles),
+                     dim3(kThreads), 0, s, partials, nsplit, tiles, kdev, G, ldg, info);
+  return hipGetLastError();
 }
 
 hipError_t launch_gram_f32(const float* X, int64_t ldx, int64_t m, const int64_t* kdev,
