@@ -161,6 +161,11 @@ int cqrrpt_qrcp(double* X, int64_t ldx, int64_t d, int64_t n,
  *       good default in FP64. The second stage keeps the largest leading
  *       block whose diagonal condition estimate is <= sqrt(100) = 10.
  * Q:    m x n output (ldq >= m): Q[:, :rank] orthonormal, Q[:, rank:] = 0.
+ *       In the FP64 mode Q also holds M_pre until the Q step overwrites it;
+ *       an ldq whose 8 ldq bytes are a multiple of 4 KiB (for example a
+ *       power of two) puts the rows the Gram reads together on colliding
+ *       cache sets and channels and takes the slower LDS-staged Gram
+ *       (365 against 299 ms at 4194304 x 2048): prefer ldq = m + 16 there.
  * R:    n x n output (ldr >= n): R[:rank, :] upper trapezoidal with a
  *       non-negative diagonal, R[rank:, :] = 0.
  * J:    int64[n] output, 0-based pivots, always the full permutation.

@@ -301,6 +301,7 @@ hipError_t launch_saso_sample(int64_t m, int d, int nnz, uint64_t seed, int32_t*
 
 struct SketchPlan {
   int reg_t;    // targets per thread of the register variant (0: LDS variant)
+  int thr;      // threads per workgroup of the register variant
   int ts;       // source rows per sub-chunk
   int nsub;     // number of sub-chunks
   int nc;       // columns per workgroup

@@ -212,14 +212,15 @@ saso_partial_kernel(const double* __restrict__ A, int64_t lda, int64_t m, int64_
 }
 
 // ---------------------------------------------------------------------------
-// Register-accumulator variant of the partial sketch. Thread t owns targets
-// r = t + 256 i (i < T) for all NC columns of the block, held in registers.
+// Register-accumulator variant of the partial sketch. With THR threads,
+// thread t owns targets r = t + THR i (i < T) for all NC columns of the
+// block, held in registers.
 // Per sub-chunk it walks its T segments in lock step, reading whole staged
 // rows of A (NC contiguous doubles) from LDS. Within a target the order of
 // the additions is ascending source row, sub-chunk after sub-chunk.
 // ---------------------------------------------------------------------------
-template <int T, int NC, int LL>
-__global__ void __launch_bounds__(kThreads)
+template <int T, int NC, int LL, int THR>
+__global__ void __launch_bounds__(THR)
 saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, int64_t n, int d,
                         int nnz, int ts, int subs_per_chunk, int nsub,
                         const int32_t* __restrict__ seg, const uint16_t* __restrict__ list,
@@ -250,7 +251,7 @@ saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, in
   // back), then stored to LDS after the previous walk. Fixed per-thread load
   // counts: the tile holds ts * NC <= 4096 values, the segment table
   // d + 1 <= 256 T + 1 offsets, the list ts * nnz <= 512 LL entries.
-  constexpr int kTileLoads = 4096 / kThreads;
+  constexpr int kTileLoads = (4096 + THR - 1) / THR;
   constexpr int kSegLoads = T + 1;
   constexpr int kListLoads = LL;  // 32-bit words, two entries each
   const int ts_shift = 31 - __clz(ts);       // ts is a power of two
@@ -264,7 +265,7 @@ saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, in
     rows_next = rows_here;
 #pragma unroll
     for (int i = 0; i < kTileLoads; ++i) {
-      const int e = tid + kThreads * i;
+      const int e = tid + THR * i;
       const int c = e >> ts_shift;
       const int jl = e & (ts - 1);
       tv[i] = (e < ts * NC && jl < rows_here && c < ncols) ? A[(j0 + jl) + (c0 + c) * lda] : 0.0;
@@ -272,14 +273,14 @@ saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, in
     const int32_t* segb = seg + (int64_t)sb * (d + 1);
 #pragma unroll
     for (int i = 0; i < kSegLoads; ++i) {
-      const int r = tid + kThreads * i;
+      const int r = tid + THR * i;
       sv[i] = r <= d ? segb[r] : 0;
     }
     const uint32_t* lb = reinterpret_cast<const uint32_t*>(list + (int64_t)sb * ts * nnz);
     const int nw = (rows_here * nnz + 1) >> 1;
 #pragma unroll
     for (int i = 0; i < kListLoads; ++i) {
-      const int w = tid + kThreads * i;
+      const int w = tid + THR * i;
       lv[i] = w < nw ? lb[w] : 0u;
     }
   };
@@ -292,12 +293,12 @@ saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, in
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kTileLoads; ++i) {
-      const int e = tid + kThreads * i;
+      const int e = tid + THR * i;
       if (e < ts * NC) tile[(e & (ts - 1)) * kRowPitch + (e >> ts_shift)] = tv[i];
     }
 #pragma unroll
     for (int i = 0; i < kSegLoads; ++i) {
-      const int r = tid + kThreads * i;
+      const int r = tid + THR * i;
       if (r <= d) sseg[r] = sv[i];
     }
     {
@@ -305,7 +306,7 @@ saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, in
       const int nw = (rows_here * nnz + 1) >> 1;
 #pragma unroll
       for (int i = 0; i < kListLoads; ++i) {
-        const int w = tid + kThreads * i;
+        const int w = tid + THR * i;
         if (w < nw) sl32[w] = lv[i];
       }
     }
@@ -324,7 +325,7 @@ saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, in
     pre[0] = 0;
 #pragma unroll
     for (int i = 0; i < T; ++i) {
-      const int r = tid + kThreads * i;
+      const int r = tid + THR * i;
       base[i] = r < d ? sseg[r] : 0;
       pre[i + 1] = pre[i] + (r < d ? sseg[r + 1] - base[i] : 0);
     }
@@ -354,7 +355,7 @@ saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, in
   }
 #pragma unroll
   for (int i = 0; i < T; ++i) {
-    const int r = tid + kThreads * i;
+    const int r = tid + THR * i;
     if (r >= d) continue;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -399,23 +400,36 @@ size_t partial_reg_lds_bytes(int d, int nnz, int ts, int nc) {
   return (size_t)ts * (nc + 2) * 8 + (size_t)((d + 1 + 3) & ~3) * 4 + (size_t)ts * nnz * 2;
 }
 
-// Targets per thread (rounded up to an instantiated value) for d rows.
-int reg_targets(int d) {
-  static const int kT[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
-  const int need = (d + kThreads - 1) / kThreads;
-  for (int t : kT)
-    if (t >= need) return t;
-  return 0;
+// Threads per workgroup of the register variant and targets per thread
+// (d rows over the threads, rounded up to an instantiated count; 0: none,
+// the LDS variant runs). More threads mean fewer targets per thread (less
+// of the walk's weighted work) and more waves to cover its dependent LDS
+// reads. Measured sketch times, 256 / 512 / 1024 threads: 4194304 x 2048
+// with d = 2560: 103.9 / 63.3 / 53.6 ms; 131072 x 1024, d = 1280: 0.904 /
+// 0.889 / 0.851 ms; 1048576 x 512, d = 640: 2.92 / 2.84 / 3.18 ms.
+int reg_threads(int d) { return d > 1024 && d <= 3072 ? 1024 : 512; }
+
+int reg_targets(int d, int thr) {
+  const int need = (d + thr - 1) / thr;
+  if (thr == 1024) return need <= 2 ? 2 : need <= 3 ? 3 : 0;
+  return need <= 1 ? 1 : need <= 2 ? 2 : need <= 8 ? 8 : 0;
 }
 
-// LL: 32-bit list words per thread, ts * nnz / 512 rounded up to 8 or 16.
-const void* reg_partial_kernel(int T, int NC, int LL) {
-#define CQ_SK(TT, CC)                                                                   \
-  if (T == TT && NC == CC)                                                              \
-    return LL <= 8 ? (const void*)saso_partial_reg_kernel<TT, CC, 8>                    \
-                   : (const void*)saso_partial_reg_kernel<TT, CC, 16>;
-  CQ_SK(1, 8) CQ_SK(2, 8) CQ_SK(3, 8) CQ_SK(4, 8) CQ_SK(5, 8) CQ_SK(6, 8) CQ_SK(8, 8)
-  CQ_SK(10, 8) CQ_SK(12, 4) CQ_SK(16, 4)
+// LL: 32-bit list words per thread, ts * nnz / (2 thr) rounded up to 2, 4,
+// 8 or 16.
+int reg_list_words(int ts, int nnz, int thr) {
+  const int w = (ts * nnz / 2 + thr - 1) / thr;
+  return w <= 2 ? 2 : w <= 4 ? 4 : w <= 8 ? 8 : 16;
+}
+
+const void* reg_partial_kernel(int T, int NC, int LL, int THR) {
+#define CQ_SK(TT, CC, HH)                                                               \
+  if (T == TT && NC == CC && THR == HH)                                                 \
+    return LL <= 2 ? (const void*)saso_partial_reg_kernel<TT, CC, 2, HH>                \
+         : LL <= 4 ? (const void*)saso_partial_reg_kernel<TT, CC, 4, HH>                \
+         : LL <= 8 ? (const void*)saso_partial_reg_kernel<TT, CC, 8, HH>                \
+                   : (const void*)saso_partial_reg_kernel<TT, CC, 16, HH>;
+  CQ_SK(1, 8, 512) CQ_SK(2, 8, 512) CQ_SK(8, 8, 512) CQ_SK(2, 8, 1024) CQ_SK(3, 8, 1024)
 #undef CQ_SK
   return nullptr;
 }
@@ -443,10 +457,11 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int d, int nnz) {
   p.ts = sub_rows(nnz);
   p.nsub = (int)((m + p.ts - 1) / p.ts);
   const size_t budget = dev.lds_per_block;
-  p.reg_t = reg_targets(d);
+  p.thr = reg_threads(d);
+  p.reg_t = reg_targets(d, p.thr);
   int nc;
   if (p.reg_t > 0) {
-    nc = p.reg_t <= 10 ? 8 : 4;
+    nc = 8;
     p.lds_bytes = partial_reg_lds_bytes(d, nnz, p.ts, nc);
   } else {
     nc = 16;
@@ -463,9 +478,9 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int d, int nnz) {
   // partial sums stay small next to A.
   int per_cu = 2;
   if (p.reg_t > 0) {
-    const void* fn = reg_partial_kernel(p.reg_t, nc, (p.ts * nnz + 511) / 512);
+    const void* fn = reg_partial_kernel(p.reg_t, nc, reg_list_words(p.ts, nnz, p.thr), p.thr);
     int occ = 0;
-    if (fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kThreads, p.lds_bytes) ==
+    if (fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, p.thr, p.lds_bytes) ==
                   hipSuccess &&
         occ > 0)
       per_cu = occ;
@@ -524,7 +539,7 @@ hipError_t launch_sketch(const SketchPlan& p, const double* A, int64_t lda, int6
   const int64_t ncb = (n + p.nc - 1) / p.nc;
   const int direct = p.nchunk == 1;
   if (p.reg_t > 0) {
-    const void* fn = reg_partial_kernel(p.reg_t, p.nc, (p.ts * nnz + 511) / 512);
+    const void* fn = reg_partial_kernel(p.reg_t, p.nc, reg_list_words(p.ts, nnz, p.thr), p.thr);
     if (!fn) return hipErrorInvalidValue;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
     if (e != hipSuccess) return e;
@@ -533,7 +548,7 @@ hipError_t launch_sketch(const SketchPlan& p, const double* A, int64_t lda, int6
                     (void*)&p.ts, (void*)&p.subs_per_chunk, (void*)&p.nsub, (void*)&seg,
                     (void*)&list, (void*)&part, (void*)&part_ld, (void*)&part_stride,
                     (void*)&scale, (void*)&Ahat, (void*)&ldah, (void*)&direct, (void*)&info};
-    e = hipLaunchKernel(fn, dim3((unsigned)ncb, p.nchunk), dim3(kThreads), args, p.lds_bytes, s);
+    e = hipLaunchKernel(fn, dim3((unsigned)ncb, p.nchunk), dim3(p.thr), args, p.lds_bytes, s);
   } else {
     e = hipFuncSetAttribute((const void*)saso_partial_kernel,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);

@@ -122,9 +122,10 @@ def test_sketch_parity(P, m, n, d, nnz):
     assert np.all(np.abs(S1 - So) <= bound + 1e-300)
 
 
-# Sketch shapes reaching every kernel variant: register walks with 8, 10, 12
-# and 16 target rows per thread (d up to 2048, 2560, 3072, 4096) and the LDS
-# variant past 4096 rows.
+# Sketch shapes reaching every kernel variant (with the small shapes above,
+# which take 512 threads with one or two target rows per thread): 1024
+# threads with two and three target rows (d = 1800; 2560 and 3000), 512
+# threads with eight (d = 4096), and the LDS variant past 4096 rows.
 @pytest.mark.parametrize("m,n,d,nnz", [(30000, 40, 1800, 8), (30000, 37, 2560, 8),
                                        (20000, 33, 3000, 8), (40000, 20, 4096, 8),
                                        (30000, 24, 5000, 8), (25000, 9, 9000, 4)])
