@@ -226,3 +226,64 @@ def test_fullsize_share_524288x2048(P):
     orth, recon = device_quality(A, f.Q, f.R, f.J, n)
     say(f"  orth {orth:.2e} recon {recon:.2e}")
     assert orth <= 1e-12 and recon <= 1e-12
+
+
+def test_fullsize_4194304x2048(P):
+    """The 4,194,304 x 2,048 planted-rank workload itself, in the launch
+    configuration bench.py times (a Factorization with its padded Q). The
+    whole oracle does not finish here in minutes (its QRCP of the 2560 x 2048
+    sketch alone takes minutes), so the oracle checks sampled outputs it can
+    compute one at a time, and the rest is checked by properties that hold
+    at any size:
+      * the sketch at this shape (the same plan and kernel variant as inside
+        the factorization) against the oracle's sketch of sampled columns,
+        entry by entry within the rounding bound of the sketch parity test;
+      * ranks of both stages (the planted rank sits at the sketch's noise
+        floor: both are n at tol 1e-14), J a permutation, R upper triangular
+        with a positive diagonal, ||Q^T Q - I||_2 <= 1e-12,
+        ||A[:,J] - Q R||_F / ||A||_F <= 1e-12, and R^T R equal to the Gram of
+        A[:, J] to 1e-12 relative (the QR factors of A[:, J] are unique)."""
+    say("full 4194304 x 2048")
+    A, w = W.make_workload_gpu("fp64_4194304x2048_rank1536", seed=0)
+    m, n, d, nnz, tol = w["m"], w["n"], w["d"], w["nnz"], w["tol"]
+    seed = 0
+    S = P.sketch(A, d, nnz, seed).cpu().numpy()
+    rows, signs = O.saso_sample(m, d, nnz, seed)
+    p = np.bincount(rows.ravel(), minlength=d).max()
+    cols = [0, 1, 777, 1535, 2047]
+    a = A[:, cols].cpu().numpy()
+    So = O.sketch(a, rows, signs, d)
+    absS = O.sketch(np.abs(a), rows, np.ones_like(signs), d)
+    bound = (2 * p + 4) * U64 * absS
+    for i, c in enumerate(cols):
+        assert np.all(np.abs(S[:, c] - So[:, i]) <= bound[:, i] + 1e-300), f"sketch column {c}"
+    del S, rows, signs, a, So, absS
+    f = P.Factorization(m, n, d, nnz, P.CQRRPT_FP64)
+    f.run(A, seed, tol)
+    info = f.info()
+    say(f"  rank {info.rank} (stage 1 {info.rank_stage1})")
+    assert info.status == 0 and info.rank == n and info.rank_stage1 == n
+    Jn = f.J.cpu().numpy()
+    assert np.array_equal(np.sort(Jn), np.arange(n))
+    Rn = f.R.cpu().numpy()
+    assert np.array_equal(Rn, np.triu(Rn)) and np.all(np.diag(Rn) > 0)
+    # Blocked device checks (A, Q and a gathered copy do not fit together).
+    G = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    GA = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    e2 = torch.zeros((), dtype=torch.float64, device="cuda")
+    a2 = torch.zeros((), dtype=torch.float64, device="cuda")
+    for r0 in range(0, m, 1 << 18):
+        r1 = min(m, r0 + (1 << 18))
+        Qb = f.Q[r0:r1]
+        Ab = A[r0:r1][:, f.J]
+        G += Qb.t() @ Qb
+        GA += Ab.t() @ Ab
+        e2 += torch.linalg.norm(Ab - Qb @ f.R) ** 2
+        a2 += torch.linalg.norm(Ab) ** 2
+    G -= torch.eye(n, dtype=torch.float64, device="cuda")
+    orth = float(np.max(np.abs(np.linalg.eigvalsh(G.cpu().numpy()))))
+    recon = float(torch.sqrt(e2 / a2))
+    RtR = f.R.t() @ f.R
+    gram_err = float(torch.linalg.norm(RtR - GA) / torch.linalg.norm(GA))
+    say(f"  orth {orth:.2e} recon {recon:.2e} R^T R vs Gram {gram_err:.2e}")
+    assert orth <= 1e-12 and recon <= 1e-12 and gram_err <= 1e-12
