@@ -30,7 +30,10 @@ What is computed, step by step, in the paper's order (Algorithm 2,
   S10 R = R_pre[:k, :k] R_sk[:k, :]                                (Alg. 2, undo preconditioning)
 
 Also here: the unpivoted precursor of Sec. 1.3 (``sketched_cholqr``): sketch,
-unpivoted QR of the sketch, precondition, CholeskyQR, for full-rank inputs.
+unpivoted QR of the sketch, precondition, CholeskyQR, for full-rank inputs;
+the dense Gaussian and SRHT operators of Sec. 2.3.1 (``cqrrpt_dense``); and
+HQRRP, the randomized block-pivoted QR of Sec. 5.2.2, in place of GEQP3 on
+the sketch (``hqrrp``, ``cqrrpt_hqrrp``).
 
 Readings where the paper is silent (each is listed in the design doc as well):
   * random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the seed,
@@ -207,6 +210,7 @@ def saso_matrix(m, d, nnz, seed):
 # ---------------------------------------------------------------------------
 
 GAUSS_DOMAIN = 0x47415553       # "GAUS"
+HQRRP_DOMAIN = 0x48515250       # "HQRP": the sampling matrix of ``hqrrp``
 SRHT_SIGN_DOMAIN = 0x53524844   # "SRHD"
 SRHT_ROW_DOMAIN = 0x53524852    # "SRHR"
 
@@ -218,7 +222,7 @@ def _u53(hi_word, lo_word):
         (np.asarray(lo_word, dtype=np.uint64) >> np.uint64(6))
 
 
-def gaussian_sketch_matrix(m, d, seed):
+def gaussian_sketch_matrix(m, d, seed, domain=GAUSS_DOMAIN):
     """S (d x m) with iid N(0, 1/d) entries (Sec. 2.3.1, Gaussian matrices).
     Entries (2q, j) and (2q + 1, j) come from one Philox4x32-10 block with
     counter (lo32(j), hi32(j), q, "GAUS"): u1 = (U(w0, w1) + 1) 2^-53 in
@@ -229,7 +233,7 @@ def gaussian_sketch_matrix(m, d, seed):
     j = np.arange(m, dtype=np.uint64)[None, :]
     r = np.arange(d, dtype=np.uint64)[:, None]
     w0, w1, w2, w3 = philox4x32_10(j & _MASK32, j >> np.uint64(32), r >> np.uint64(1),
-                                   GAUSS_DOMAIN, k0, k1)
+                                   domain, k0, k1)
     u1 = (_u53(w0, w1) + np.uint64(1)).astype(np.float64) * 2.0 ** -53
     u2 = _u53(w2, w3).astype(np.float64) * 2.0 ** -53
     rad = np.sqrt(-2.0 * np.log(u1))
@@ -401,6 +405,114 @@ def qrcp_q_factor(refl, flip, d):
     return Q
 
 
+def _householder(x):
+    """LAPACK-convention reflector of x: (v, tau, beta) with v[0] = 1,
+    (I - tau v v^T) x = beta e_1; tau = beta = 0 when ||x|| = 0."""
+    normx = math.sqrt(float(np.sum(x * x)))
+    if normx == 0.0:
+        return np.zeros_like(x), 0.0, 0.0
+    alpha = x[0]
+    beta = -normx if alpha >= 0.0 else normx
+    v = x / (alpha - beta)
+    v[0] = 1.0
+    return v, (beta - alpha) / beta, beta
+
+
+def hqrrp(X, b, s, seed, Omega=None):
+    """Householder QR with randomized block pivoting (HQRRP) of a d x n
+    matrix, as the paper substitutes it for GEQP3 on the sketch (Sec. 5.2.2),
+    following the loop of the randomized QRCP methods it outlines in Sec. 1
+    (sample Y = Omega X with b + s rows; per block: pivots from Y, QR of the
+    chosen columns, update of X and Y) with the sample update
+    Y2 <- Y2 - Y1 R11^{-1} R12 of the cited HQRRP work.
+
+    Per block of bb = min(b, n - i) columns starting at position i:
+      1. the first bb pivots of max-norm QRCP (exact norms, ties to the
+         smallest original column index) of a copy of Y[:, i:]; the chosen
+         columns move to positions i.., in pivot order, and the others keep
+         their relative order (in X, Y and J);
+      2. unpivoted Householder QR of X[i:, i:i+bb], each reflector applied to
+         all later columns (LAPACK convention, as ``qrcp``);
+      3. Y[:, i+bb:] -= Y[:, i:i+bb] Z with R11 Z = R12, R11 = X[i:i+bb,
+         i:i+bb] (upper) and R12 = X[i:i+bb, i+bb:], by back substitution; a
+         zero diagonal entry of R11 gives a zero row of Z.
+    Omega defaults to the Gaussian (b + s) x d matrix of
+    ``gaussian_sketch_matrix`` with the "HQRP" counter domain.
+    Returns (J, R) as ``qrcp``: R upper triangular with a non-negative
+    diagonal and X[:, J] = Q R."""
+    X = np.array(X, dtype=np.float64, copy=True)
+    d, n = X.shape
+    if d < n:
+        raise ValueError("hqrrp expects at least as many rows as columns")
+    if b < 1 or s < 0:
+        raise ValueError("need b >= 1 and s >= 0")
+    if Omega is None:
+        Omega = gaussian_sketch_matrix(d, b + s, seed, HQRRP_DOMAIN)
+    Y = np.asarray(Omega, dtype=np.float64) @ X
+    p = Y.shape[0]
+    J = np.arange(n)
+    i = 0
+    while i < n:
+        bb = min(b, n - i)
+        # 1. pivots of the block from a reflected copy of Y's remaining columns
+        Yc = Y[:, i:].copy()
+        alive = list(range(n - i))
+        sel = []
+        for t in range(bb):
+            if t < p:
+                nu = np.sqrt(np.sum(Yc[t:, alive] ** 2, axis=0))
+            else:
+                nu = np.zeros(len(alive))
+            top = nu.max()
+            cand = [alive[c] for c in np.flatnonzero(nu == top)]
+            c = min(cand, key=lambda q: J[i + q])
+            sel.append(c)
+            alive.remove(c)
+            if t < p and alive:
+                v, tau, _ = _householder(Yc[t:, c].copy())
+                if tau != 0.0:
+                    w = v @ Yc[t:, alive]
+                    Yc[t:, alive] -= tau * np.outer(v, w)
+        perm = np.array(sel + alive, dtype=np.int64)
+        X[:, i:] = X[:, i:][:, perm]
+        Y[:, i:] = Y[:, i:][:, perm]
+        J[i:] = J[i:][perm]
+        # 2. unpivoted Householder QR of the chosen columns, applied to the rest
+        for j in range(i, i + bb):
+            v, tau, beta = _householder(X[j:, j].copy())
+            if tau != 0.0 and j + 1 < n:
+                w = v @ X[j:, j + 1:]
+                X[j:, j + 1:] -= tau * np.outer(v, w)
+            X[j, j] = beta
+            X[j + 1:, j] = 0.0
+        # 3. sample update of the remaining columns
+        if i + bb < n:
+            R11 = X[i:i + bb, i:i + bb]
+            R12 = X[i:i + bb, i + bb:]
+            Z = np.zeros_like(R12)
+            for r in range(bb - 1, -1, -1):
+                if R11[r, r] != 0.0:
+                    Z[r] = (R12[r] - R11[r, r + 1:] @ Z[r + 1:]) / R11[r, r]
+            Y[:, i + bb:] -= Y[:, i:i + bb] @ Z
+        i += bb
+    R = np.triu(X[:n, :n])
+    flip = np.diag(R) < 0.0
+    R[flip, :] = -R[flip, :]
+    return J, R
+
+
+def cqrrpt_hqrrp(A, d, nnz, seed, tol, b, s, hseed, cond_max=10.0):
+    """CQRRPT whose QRCP of the sketch is ``hqrrp`` (Sec. 5.2.2)."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    if not (1 <= n <= m and n <= d <= m):
+        raise ValueError("need 1 <= n <= d <= m")
+    rows, signs = saso_sample(m, d, nnz, seed)
+    Ahat = sketch(A, rows, signs, d)
+    return _core_from_sketch(A, Ahat, tol, cond_max,
+                             qrcp_fn=lambda X: hqrrp(X, b, s, hseed))
+
+
 # ---------------------------------------------------------------------------
 # S4 / S8. Numerical rank (Sec. 3.3)
 # ---------------------------------------------------------------------------
@@ -488,14 +600,14 @@ def cqrrpt_core(A, S, tol, cond_max=10.0):
     return _core_from_sketch(A, Ahat, tol, cond_max)
 
 
-def _core_from_sketch(A, Ahat, tol, cond_max):
+def _core_from_sketch(A, Ahat, tol, cond_max, qrcp_fn=None):
     m, n = A.shape
     out = dict(Q=np.zeros((m, n)), R=np.zeros((n, n)), J=np.arange(n), rank=0,
                rank_stage1=0, chol_fail_col=-1, status=STATUS_OK, Ahat=Ahat, Rsk=None)
     if not np.all(np.isfinite(Ahat)):
         out["status"] = STATUS_NONFINITE
         return out
-    J, Rsk = qrcp(Ahat)
+    J, Rsk = qrcp(Ahat) if qrcp_fn is None else qrcp_fn(Ahat)
     out["J"], out["Rsk"] = J, Rsk
     k_o = rank_stage1(Rsk, tol)
     out["rank_stage1"] = k_o

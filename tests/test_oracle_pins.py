@@ -626,3 +626,85 @@ def test_dense_sketch_path(kind):
     Q, R, J = out["Q"], out["R"], out["J"]
     assert np.linalg.norm(A[:, J] - Q @ R) / np.linalg.norm(A) < 1e-14
     assert np.linalg.norm(Q.T @ Q - np.eye(40), 2) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# HQRRP on the sketch (Sec. 5.2.2)
+# ---------------------------------------------------------------------------
+
+def _positive_r(M):
+    R = np.linalg.qr(M, mode="r")
+    R = np.triu(R[:M.shape[1], :M.shape[1]])
+    sg = np.where(np.diag(R) < 0, -1.0, 1.0)
+    return sg[:, None] * R
+
+
+@pytest.mark.parametrize("d,n,b", [(120, 60, 1), (120, 60, 8), (90, 90, 7), (200, 33, 16)])
+def test_hqrrp_identity_sampler_is_geqp3(d, n, b):
+    # With Omega = I (b + s = d) the sample is X itself, and the sample
+    # update Y2 - Y1 R11^{-1} R12 = Q2 R22 keeps the trailing column norms,
+    # so every block takes GEQP3's next pivots (LAPACK, through scipy).
+    X = W.column_scaled_well_separated(d, n, seed=d + n + b, ratio=1.2)
+    J, R = O.hqrrp(X, b, d - b, seed=0, Omega=np.eye(d))
+    _, Rl, piv = scipy.linalg.qr(X, mode="economic", pivoting=True)
+    assert np.array_equal(J, piv)
+    sg = np.where(np.diag(Rl) < 0, -1.0, 1.0)
+    assert np.linalg.norm(R - sg[:, None] * Rl) <= 1e-13 * np.linalg.norm(Rl)
+
+
+@pytest.mark.parametrize("b,s", [(1, 0), (4, 4), (16, 8), (64, 8)])
+def test_hqrrp_factor_is_the_qr_of_the_permuted_matrix(b, s):
+    # Whatever the pivots, R is the unique positive-diagonal R of X[:, J].
+    X = W.spectrum_matrix(300, 70, W.logspaced_spectrum(70, 1e8), seed=5)
+    J, R = O.hqrrp(X, b, s, seed=9)
+    assert np.array_equal(np.sort(J), np.arange(70))
+    assert np.array_equal(R, np.triu(R)) and np.all(np.diag(R) >= 0)
+    Rr = _positive_r(X[:, J])
+    assert np.linalg.norm(R - Rr) <= 1e-13 * np.linalg.norm(Rr)
+
+
+def test_hqrrp_single_block_takes_the_samples_pivots():
+    # b >= n: one block, whose pivots are those of GEQP3 on the sample
+    # Omega X (formed here with its own product).
+    d, n, b, s = 150, 40, 40, 6
+    X = W.column_scaled_well_separated(d, n, seed=44, ratio=1.15)
+    Om = O.gaussian_sketch_matrix(d, b + s, 3, O.HQRRP_DOMAIN)
+    Y = np.einsum("ij,jk->ik", Om, X)
+    _, _, piv = scipy.linalg.qr(Y, mode="economic", pivoting=True)
+    J, R = O.hqrrp(X, b, s, seed=3)
+    assert np.array_equal(J, piv)
+
+
+def test_hqrrp_reveals_a_planted_rank():
+    # Rank 30 plus noise at 1e-13: after the first 30 pivots the trailing
+    # block of R is at the noise level, far below the smallest leading
+    # diagonal entry (the rank-revealing property block pivoting keeps).
+    s = np.concatenate([np.geomspace(1.0, 1e-4, 30), np.zeros(30)])
+    X = W.spectrum_matrix(400, 60, s, seed=6) + 1e-13 * W.gaussian_matrix(400, 60, seed=7)
+    J, R = O.hqrrp(X, 8, 8, seed=2)
+    lead = np.abs(np.diag(R))[:30].min()
+    tail = np.linalg.norm(R[30:, 30:])
+    assert tail < 1e-10 * np.abs(R).max() and lead > 1e3 * tail
+
+
+def test_hqrrp_zero_column():
+    # An exactly zero column is chosen last (norm 0) and leaves a zero
+    # diagonal entry; the zero-diagonal rule of the sample update keeps
+    # everything finite.
+    X = W.gaussian_matrix(50, 12, seed=8)
+    X[:, 4] = 0.0
+    J, R = O.hqrrp(X, 4, 4, seed=1)
+    assert J[-1] == 4 and R[-1, -1] == 0.0 and np.all(np.isfinite(R))
+    Rr = _positive_r(X[:, J[:-1]])
+    assert np.linalg.norm(R[:-1, :-1] - Rr) <= 1e-13 * np.linalg.norm(Rr)
+
+
+def test_cqrrpt_with_hqrrp_meets_the_correctness_theorem():
+    A = _c1_small(m=5000, n=80, cond=1e8, seed=12)
+    out = O.cqrrpt_hqrrp(A, d=100, nnz=4, seed=3, tol=1e-14, b=16, s=8, hseed=5)
+    Q, R, J = out["Q"], out["R"], out["J"]
+    assert out["rank"] == 80
+    assert np.linalg.norm(A[:, J] - Q @ R) / np.linalg.norm(A) < 1e-14
+    assert np.linalg.norm(Q.T @ Q - np.eye(80), 2) < 1e-13
+    Qd, Rd = O.factor_given_pivots(A, J, 80)
+    assert np.linalg.norm(R - Rd) / np.linalg.norm(Rd) < 1e-12
