@@ -425,6 +425,56 @@ def gamma_sweep(P, torch, seed):
     return out
 
 
+def hqrrp_study(P, torch, W, seed, reps=5):
+    """Sec. 5.2.2: HQRRP (block 16, oversampling 8) against the GEQP3-order
+    QRCP on sketch shapes (Gaussian d x n), and CQRRPT with HQRRP on the
+    131,072 x 1,024 planted-rank input: time per call (device events around
+    ``reps`` calls, each allocating through torch's cache), trailing-norm
+    ratio max_l ||R_h[l:, l:]||_F / ||R_q[l:, l:]||_F (pivot quality against
+    the QRCP's), rank and quality."""
+    out = {}
+    for d, n in ((1280, 1024), (2560, 2048)):
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed + d)
+        X = torch.randn((n, d), dtype=torch.float64, device="cuda", generator=gen).t()
+        row = {}
+        for name, fn in (("qrcp", lambda: P.qrcp(X)), ("hqrrp", lambda: P.hqrrp(X, 16, 8, seed))):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                r = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            row[name + "_ms"] = e0.elapsed_time(e1) / reps
+            row[name + "_R"] = r[1]
+        tq = torch.sqrt(torch.flip(torch.cumsum(torch.flip((torch.triu(row.pop("qrcp_R")) ** 2).sum(1), [0]), 0), [0]))
+        th = torch.sqrt(torch.flip(torch.cumsum(torch.flip((torch.triu(row.pop("hqrrp_R")) ** 2).sum(1), [0]), 0), [0]))
+        ratio = (th / torch.clamp(tq, min=1e-300)).cpu().numpy()
+        row["trailing_hqrrp_over_qrcp_max"] = float(ratio.max())
+        row["trailing_hqrrp_over_qrcp_median"] = float(np.median(ratio))
+        out[f"sketch_{d}x{n}"] = row
+        del X
+    A, w = W.make_workload_gpu("fp64_131072x1024_rank512", seed=seed)
+    for tol in (1e-14, 1e-9):
+        P.factor_hqrrp(A, w["d"], w["nnz"], seed, tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            Q, R, J, info = P.factor_hqrrp(A, w["d"], w["nnz"], seed, tol)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        orth, recon = quality(torch, A, Q, R, J, int(info.rank))
+        out[f"factor_131072x1024_tol{tol:g}"] = {"ms_per_call": ms, "rank": int(info.rank),
+                                                 "orth": orth, "recon": recon}
+        del Q, R, J
+    del A
+    torch.cuda.empty_cache()
+    log(f"hqrrp: {json.dumps(out)}")
+    return out
+
+
 def high_coherence_study(P, torch, W, seed, m=32_768, n=500):
     """Sec. 4.2 on a smaller instance of the same construction (stacked
     identities, n rows scaled by 1e10, rotated by a random orthogonal
@@ -585,6 +635,7 @@ def main():
         extra["dense_sketch_131072x1024"] = dense_sketch_run(P, torch, W, args.seed)
         extra["gamma_sweep"] = gamma_sweep(P, torch, args.seed)
         extra["high_coherence_32768x500"] = high_coherence_study(P, torch, W, args.seed)
+        extra["hqrrp_vs_qrcp"] = hqrrp_study(P, torch, W, args.seed)
         if args.serving_requests > 0:
             srv = {}
             for name, mode in (("fp64", P.CQRRPT_FP64), ("mixed", P.CQRRPT_MIXED)):

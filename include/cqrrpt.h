@@ -275,6 +275,57 @@ int cqrrpt_factor_dense_ex(const double* A, int64_t lda, int64_t m, int64_t n, i
                            double* Q, int64_t ldq, double* R, int64_t ldr, int64_t* J,
                            void* ws, size_t ws_bytes, void* stream, cqrrpt_info_t* info);
 
+/* HQRRP on the sketch (Sec. 5.2.2): Householder QR with randomized block
+ * pivoting of a d x n matrix X, the substitute the paper tries for GEQP3 on
+ * the sketch, following the randomized QRCP loop it outlines in Sec. 1.
+ * A Gaussian Omega (p = block + oversample rows; entries (2q, j) and
+ * (2q + 1, j) by Box-Muller from one Philox4x32-10 block at counter
+ * (lo32(j), hi32(j), q, "HQRP") under key (lo32(seed), hi32(seed)), scaled
+ * by 1/sqrt(p)) gives the sample Y = Omega X; then per block of
+ * bb = min(block, n - i) columns at position i:
+ *   1. the first bb pivots of max-norm QRCP of Y's remaining columns (exact
+ *      norms, ties to the smallest original column index); the chosen
+ *      columns take positions i.. in pivot order, the others keep their
+ *      relative order;
+ *   2. unpivoted Householder QR of the chosen columns (LAPACK sign
+ *      convention), applied to the remaining columns (compact WY form);
+ *   3. the sample update Y2 <- Y2 - Y1 Z with R11 Z = R12 (a zero diagonal
+ *      entry of R11 gives a zero row of Z).
+ * Outputs as cqrrpt_qrcp: J (device int64[n]) the 0-based pivot order, R
+ * (n x n, ldr >= n) upper triangular with rows negated to a non-negative
+ * diagonal, X[:, J] = Q R. X is overwritten (Householder vectors).
+ * Limits: 1 <= block <= 16, oversample >= 0, block + oversample <= 24,
+ * n <= 2048, n <= d <= 3072 (else CQRRPT_ELIMIT). ws: device workspace of
+ * cqrrpt_hqrrp_workspace_bytes() bytes (0: out of range); info: DEVICE
+ * pointer to one cqrrpt_info_t, reset here; a non-finite X raises its status
+ * to CQRRPT_ENONFINITE and the rest is skipped. Stream-ordered.
+ * Argument order: X ldx d n block oversample seed J R ldr ws ws_bytes
+ * stream info. Errors: -1 X NULL, -2 ldx < d, -3 d < 1, -4 n < 1 or n > d,
+ * -5 block < 1, -6 oversample < 0, -8 J NULL, -9 R NULL, -10 ldr < n,
+ * -11 ws NULL, -14 info NULL, CQRRPT_ELIMIT, CQRRPT_EWORKSPACE,
+ * CQRRPT_EHIP. */
+size_t cqrrpt_hqrrp_workspace_bytes(int64_t d, int64_t n, int32_t block, int32_t oversample);
+int cqrrpt_hqrrp(double* X, int64_t ldx, int64_t d, int64_t n, int32_t block,
+                 int32_t oversample, uint64_t seed, int64_t* J, double* R, int64_t ldr,
+                 void* ws, size_t ws_bytes, void* stream, cqrrpt_info_t* info);
+
+/* CQRRPT whose QRCP of the sketch is cqrrpt_hqrrp (Sec. 5.2.2) with
+ * (block, oversample, hseed); everything else as cqrrpt_factor_ex in
+ * CQRRPT_FP64 mode (the same SASO from seed, both rank stages, Q and R).
+ * ws: cqrrpt_factor_hqrrp_workspace_bytes() bytes (0: out of range).
+ * Argument order: A lda m n d nnz seed tol block oversample hseed Q ldq R
+ * ldr J ws ws_bytes stream info. Errors: -1..-8 as cqrrpt_factor_ex,
+ * -9 block < 1, -10 oversample < 0, -12 Q NULL, -13 ldq < m, -14 R NULL,
+ * -15 ldr < n, -16 J NULL, -17 ws NULL, -20 info NULL, CQRRPT_ELIMIT (also
+ * beyond cqrrpt_hqrrp's limits), CQRRPT_EWORKSPACE, CQRRPT_EHIP. */
+size_t cqrrpt_factor_hqrrp_workspace_bytes(int64_t m, int64_t n, int64_t d, int32_t nnz,
+                                           int32_t block, int32_t oversample);
+int cqrrpt_factor_hqrrp_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d,
+                           int32_t nnz, uint64_t seed, double tol, int32_t block,
+                           int32_t oversample, uint64_t hseed, double* Q, int64_t ldq,
+                           double* R, int64_t ldr, int64_t* J, void* ws, size_t ws_bytes,
+                           void* stream, cqrrpt_info_t* info);
+
 /* Allocation-free form of cqrrpt_factor_ex, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, hosts
  * that forbid hipMalloc). Same arguments and results as cqrrpt_factor_ex

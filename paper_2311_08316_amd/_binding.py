@@ -65,6 +65,13 @@ _SIGS = {
     "cqrrpt_sketched_cholqr_ex": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i32, _u64,
                                                  _vp, _i64, _vp, _i64, _vp, _sz, _vp, _vp]),
     "cqrrpt_dense_workspace_bytes": (_sz, [_i64, _i64, _i64]),
+    "cqrrpt_hqrrp_workspace_bytes": (_sz, [_i64, _i64, _i32, _i32]),
+    "cqrrpt_hqrrp": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i32, _i32, _u64, _vp, _vp, _i64,
+                                    _vp, _sz, _vp, _vp]),
+    "cqrrpt_factor_hqrrp_workspace_bytes": (_sz, [_i64, _i64, _i64, _i32, _i32, _i32]),
+    "cqrrpt_factor_hqrrp_ex": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i32, _u64, _dbl,
+                                              _i32, _i32, _u64, _vp, _i64, _vp, _i64, _vp, _vp,
+                                              _sz, _vp, _vp]),
     "cqrrpt_factor_dense_ex": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i32, _u64, _dbl,
                                               _vp, _i64, _vp, _i64, _vp, _vp, _sz, _vp, _vp]),
     "cqrrpt_probe_copy": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
@@ -385,6 +392,52 @@ def factor_dense(A, d, kind, seed, tol):
     inf = CqrrptInfo.from_buffer_copy(bytes(info.cpu().numpy().tobytes()))
     if inf.status != 0:
         _check(inf.status, "cqrrpt_factor_dense_ex")
+    return Q, R, J, inf
+
+
+def hqrrp(X, block, oversample, seed):
+    """HQRRP of a d x n GPU matrix (``cqrrpt_hqrrp``; X is copied, not
+    overwritten). Returns (J, R, info)."""
+    src = colmajor(X)
+    d, n = src.shape
+    X = empty_colmajor(d, n, src.device)
+    X.copy_(src)
+    J = torch.empty(n, dtype=torch.int64, device=X.device)
+    R = empty_colmajor(n, n, X.device)
+    wsb = lib().cqrrpt_hqrrp_workspace_bytes(d, n, block, oversample)
+    if wsb == 0:
+        raise CqrrptError("unsupported sizes")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=X.device)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=X.device)
+    rc = lib().cqrrpt_hqrrp(X.data_ptr(), d, d, n, block, oversample, seed, J.data_ptr(),
+                            R.data_ptr(), n, ws.data_ptr(), wsb, _stream_handle(X.device),
+                            info.data_ptr())
+    _check(rc, "cqrrpt_hqrrp")
+    inf = CqrrptInfo.from_buffer_copy(bytes(info.cpu().numpy().tobytes()))
+    return J, R, inf
+
+
+def factor_hqrrp(A, d, nnz, seed, tol, block=16, oversample=8, hseed=0):
+    """CQRRPT with HQRRP on the sketch (``cqrrpt_factor_hqrrp_ex``).
+    Returns (Q, R, J, info)."""
+    A = colmajor(A)
+    m, n = A.shape
+    Q = empty_colmajor_ld(m, n, padded_ld(m), A.device)
+    R = empty_colmajor(n, n, A.device)
+    J = torch.empty(n, dtype=torch.int64, device=A.device)
+    wsb = lib().cqrrpt_factor_hqrrp_workspace_bytes(m, n, d, nnz, block, oversample)
+    if wsb == 0:
+        raise CqrrptError("unsupported sizes")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=A.device)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
+    rc = lib().cqrrpt_factor_hqrrp_ex(A.data_ptr(), _ld(A), m, n, d, nnz, seed, tol, block,
+                                      oversample, hseed, Q.data_ptr(), _ld(Q), R.data_ptr(), n,
+                                      J.data_ptr(), ws.data_ptr(), wsb,
+                                      _stream_handle(A.device), info.data_ptr())
+    _check(rc, "cqrrpt_factor_hqrrp_ex")
+    inf = CqrrptInfo.from_buffer_copy(bytes(info.cpu().numpy().tobytes()))
+    if inf.status != 0:
+        _check(inf.status, "cqrrpt_factor_hqrrp_ex")
     return Q, R, J, inf
 
 

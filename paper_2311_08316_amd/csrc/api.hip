@@ -337,6 +337,34 @@ size_t cqrrpt_workspace_bytes(int64_t m, int64_t n, int64_t d, int32_t nnz, cqrr
   return make_layout(m, n, d, nnz, mode).total;
 }
 
+size_t cqrrpt_hqrrp_workspace_bytes(int64_t d, int64_t n, int32_t block, int32_t oversample) {
+  if (!cqh::hqrrp_supported(d, n, block, oversample)) return 0;
+  return cqh::hqrrp_ws_bytes(d, n, block, oversample);
+}
+
+int cqrrpt_hqrrp(double* X, int64_t ldx, int64_t d, int64_t n, int32_t block,
+                 int32_t oversample, uint64_t seed, int64_t* J, double* R, int64_t ldr, void* ws,
+                 size_t ws_bytes, void* stream, cqrrpt_info_t* info) {
+  if (!X) return -1;
+  if (d < 1) return -3;
+  if (ldx < d) return -2;
+  if (n < 1 || n > d) return -4;
+  if (block < 1) return -5;
+  if (oversample < 0) return -6;
+  if (!J) return -8;
+  if (!R) return -9;
+  if (ldr < n) return -10;
+  if (!ws) return -11;
+  if (!info) return -14;
+  if (!cqh::hqrrp_supported(d, n, block, oversample)) return CQRRPT_ELIMIT;
+  if (ws_bytes < cqh::hqrrp_ws_bytes(d, n, block, oversample)) return CQRRPT_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(info_init_kernel, dim3(1), dim3(64), 0, s, info);
+  CQ_TRY(hipGetLastError());
+  return to_status(
+      cqh::launch_hqrrp(X, ldx, d, n, block, oversample, seed, J, R, ldr, ws, info, s));
+}
+
 }  // extern "C"
 
 namespace {
@@ -361,6 +389,8 @@ struct FactorCtx {
   int64_t ldrp;
   bool precursor;
   int dense_kind;
+  int hq_b, hq_s;  // HQRRP block and oversampling (hq_b = 0: GEQP3-order QRCP)
+  uint64_t hq_seed;
   hipStream_t s;
   Layout L;
   char* base;
@@ -374,10 +404,12 @@ int factor_setup(FactorCtx& c, const double* A, int64_t lda, int64_t m, int64_t 
                  int32_t nnz, uint64_t seed, double tol, double* Q, int64_t ldq, double* R,
                  int64_t ldr, int64_t* J, cqrrpt_mode_t mode, void* ws, size_t ws_bytes,
                  void* stream, cqrrpt_info_t* info, double* Rpre, int64_t ldrp, bool precursor,
-                 int dense_kind) {
+                 int dense_kind, int hq_b = 0, int hq_s = 0, uint64_t hq_seed = 0) {
   if (n > kMaxN || d > kMaxD || !cqh::sketch_fits((int)d, nnz)) return CQRRPT_ELIMIT;
+  if (hq_b && !cqh::hqrrp_supported(d, n, hq_b, hq_s)) return CQRRPT_ELIMIT;
   c.L = make_layout(m, n, d, nnz, mode);
-  const size_t need = c.L.total + (dense_kind ? cqh::dense_sketch_ws_bytes(m, n, (int)d) : 0);
+  const size_t need = c.L.total + (dense_kind ? cqh::dense_sketch_ws_bytes(m, n, (int)d) : 0) +
+                      (hq_b ? cqh::hqrrp_ws_bytes(d, n, hq_b, hq_s) : 0);
   if (ws_bytes < need) return CQRRPT_EWORKSPACE;
   c.A = A;
   c.lda = lda;
@@ -397,6 +429,9 @@ int factor_setup(FactorCtx& c, const double* A, int64_t lda, int64_t m, int64_t 
   c.ldrp = ldrp;
   c.precursor = precursor;
   c.dense_kind = dense_kind;
+  c.hq_b = hq_b;
+  c.hq_s = hq_s;
+  c.hq_seed = hq_seed;
   c.s = static_cast<hipStream_t>(stream);
   c.base = static_cast<char*>(ws);
   const Layout& L = c.L;
@@ -444,8 +479,12 @@ int phase_sketch(FactorCtx& c) {
 
 // S3: QRCP of the sketch -> J, R_sk (the precursor: plain Householder QR).
 int phase_qrcp(FactorCtx& c) {
-  CQ_TRY(cqh::launch_qrcp(c.L.qr, c.Ahat, c.d, (int)c.d, c.ni, c.J, c.Rsk, c.n,
-                          c.base + c.L.off_qrcp, c.info, c.s, c.precursor));
+  if (c.hq_b)  // HQRRP (Sec. 5.2.2) on the sketch, which it overwrites
+    CQ_TRY(cqh::launch_hqrrp(c.Ahat, c.d, c.d, c.n, c.hq_b, c.hq_s, c.hq_seed, c.J, c.Rsk, c.n,
+                             c.base + c.L.total, c.info, c.s));
+  else
+    CQ_TRY(cqh::launch_qrcp(c.L.qr, c.Ahat, c.d, (int)c.d, c.ni, c.J, c.Rsk, c.n,
+                            c.base + c.L.off_qrcp, c.info, c.s, c.precursor));
   c.mk.mark(2);
   return CQRRPT_OK;
 }
@@ -580,10 +619,10 @@ int factor_core(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d, i
                 uint64_t seed, double tol, double* Q, int64_t ldq, double* R, int64_t ldr,
                 int64_t* J, cqrrpt_mode_t mode, void* ws, size_t ws_bytes, void* stream,
                 cqrrpt_info_t* info, double* Rpre, int64_t ldrp, bool precursor = false,
-                int dense_kind = 0) {
+                int dense_kind = 0, int hq_b = 0, int hq_s = 0, uint64_t hq_seed = 0) {
   FactorCtx c;
   int rc = factor_setup(c, A, lda, m, n, d, nnz, seed, tol, Q, ldq, R, ldr, J, mode, ws, ws_bytes,
-                        stream, info, Rpre, ldrp, precursor, dense_kind);
+                        stream, info, Rpre, ldrp, precursor, dense_kind, hq_b, hq_s, hq_seed);
   if (rc) return rc;
   if ((rc = phase_sketch(c))) return rc;
   if ((rc = phase_qrcp(c))) return rc;
@@ -713,6 +752,33 @@ int cqrrpt_factor_dense_ex(const double* A, int64_t lda, int64_t m, int64_t n, i
   if (!info) return -17;
   return factor_core(A, lda, m, n, d, 1, seed, tol, Q, ldq, R, ldr, J, CQRRPT_FP64, ws, ws_bytes,
                      stream, info, nullptr, 0, false, kind);
+}
+
+size_t cqrrpt_factor_hqrrp_workspace_bytes(int64_t m, int64_t n, int64_t d, int32_t nnz,
+                                           int32_t block, int32_t oversample) {
+  const size_t base = cqrrpt_workspace_bytes(m, n, d, nnz, CQRRPT_FP64);
+  if (!base || !cqh::hqrrp_supported(d, n, block, oversample)) return 0;
+  return base + cqh::hqrrp_ws_bytes(d, n, block, oversample);
+}
+
+int cqrrpt_factor_hqrrp_ex(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d,
+                           int32_t nnz, uint64_t seed, double tol, int32_t block,
+                           int32_t oversample, uint64_t hseed, double* Q, int64_t ldq, double* R,
+                           int64_t ldr, int64_t* J, void* ws, size_t ws_bytes, void* stream,
+                           cqrrpt_info_t* info) {
+  const int c = check_common(A, lda, m, n, d, nnz, tol);
+  if (c) return c;
+  if (block < 1) return -9;
+  if (oversample < 0) return -10;
+  if (!Q) return -12;
+  if (ldq < m) return -13;
+  if (!R) return -14;
+  if (ldr < n) return -15;
+  if (!J) return -16;
+  if (!ws) return -17;
+  if (!info) return -20;
+  return factor_core(A, lda, m, n, d, nnz, seed, tol, Q, ldq, R, ldr, J, CQRRPT_FP64, ws,
+                     ws_bytes, stream, info, nullptr, 0, false, 0, block, oversample, hseed);
 }
 
 int cqrrpt_factor_noalloc(const double* A, int64_t lda, int64_t m, int64_t n, int64_t d,

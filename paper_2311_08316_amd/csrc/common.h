@@ -317,6 +317,25 @@ hipError_t launch_sketch(const SketchPlan& p, const double* A, int64_t lda, int6
                          int d, int nnz, uint64_t seed, double* Ahat, int64_t ldah, void* ws,
                          cqrrpt_info_t* info, hipStream_t s);
 
+// C = X1^T X2 (X1 m x d1, X2 m x d2, C d1 x d2 with ldc) on FP64 matrix
+// cores: 128 x 128 tiles split over m, partials (tn_product_ws_bytes) summed
+// in split order; non-finite results raise the status in info.
+size_t tn_product_ws_bytes(int64_t m, int d1, int d2);
+hipError_t launch_tn_product(const double* X1, int64_t ld1, int d1, const double* X2,
+                             int64_t ld2, int d2, int64_t m, double* part, double* C,
+                             int64_t ldc, cqrrpt_info_t* info, hipStream_t s);
+
+// HQRRP of a d x n matrix X in place (Sec. 5.2.2): block b <= 16,
+// oversampling s with b + s <= 24, n <= 2048, n <= d <= 3072
+// (hqrrp_supported). J (int64[n]) and R (n x n, ldr) as launch_qrcp; ws of
+// hqrrp_ws_bytes. info (device) carries the status: kernels skip work once
+// it is nonzero, and a non-finite sample raises it.
+bool hqrrp_supported(int64_t d, int64_t n, int b, int s);
+size_t hqrrp_ws_bytes(int64_t d, int64_t n, int b, int s);
+hipError_t launch_hqrrp(double* X, int64_t ldx, int64_t d, int64_t n, int b, int s,
+                        uint64_t seed, int64_t* J, double* R, int64_t ldr, void* ws,
+                        cqrrpt_info_t* info, hipStream_t st);
+
 // Dense sketching operators (Gaussian, SRHT): S^T formed in ws, then
 // Ahat = S A on the matrix cores. ws: dense_sketch_ws_bytes(m, n, d) bytes.
 size_t dense_sketch_ws_bytes(int64_t m, int64_t n, int d);

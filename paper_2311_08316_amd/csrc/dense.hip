@@ -307,21 +307,32 @@ hipError_t launch_dense_sketch(int kind, const double* A, int64_t lda, int64_t m
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int ti = (d + kT - 1) / kT, tj = (int)((n + kT - 1) / kT);
+  return launch_tn_product(St, m, d, A, lda, (int)n, m, part, Ahat, ldah, info, s);
+}
+
+size_t tn_product_ws_bytes(int64_t m, int d1, int d2) {
+  const int tiles = ((d1 + kT - 1) / kT) * ((d2 + kT - 1) / kT);
+  return (size_t)tn_splits(m, tiles) * tiles * kT * kT * 8;
+}
+
+hipError_t launch_tn_product(const double* X1, int64_t ld1, int d1, const double* X2,
+                             int64_t ld2, int d2, int64_t m, double* part, double* C,
+                             int64_t ldc, cqrrpt_info_t* info, hipStream_t s) {
+  const int ti = (d1 + kT - 1) / kT, tj = (d2 + kT - 1) / kT;
   const int tiles = ti * tj;
   const int nsplit = tn_splits(m, tiles);
   int64_t rps = (m + nsplit - 1) / nsplit;
   rps = (rps + kK - 1) / kK * kK;
   const size_t lds = (size_t)4 * kStage * 8;
-  e = hipFuncSetAttribute((const void*)tn_product_kernel,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = hipFuncSetAttribute((const void*)tn_product_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(tn_product_kernel, dim3((unsigned)(tiles * nsplit)), dim3(kThreads), lds, s,
-                     St, m, d, A, lda, (int)n, m, rps, ti, tiles, part, info);
+                     X1, ld1, d1, X2, ld2, d2, m, rps, ti, tiles, part, info);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(tn_reduce_kernel, dim3(kT * kT / kThreads, (unsigned)tiles), dim3(kThreads),
-                     0, s, part, nsplit, ti, tiles, d, (int)n, Ahat, ldah, info);
+                     0, s, part, nsplit, ti, tiles, d1, d2, C, ldc, info);
   return hipGetLastError();
 }
 

@@ -581,3 +581,65 @@ def test_dense_sketch_factor_parity(P, kind, m, n, d, spec):
     code = P.SKETCH_GAUSSIAN if kind == "gaussian" else P.SKETCH_SRHT
     gpu = P.factor_dense(to_gpu(A), d, code, 6, 1e-14)
     compare_factor(A, gpu, orc, f"{kind} {m}x{n}")
+
+
+# ---------------------------------------------------------------------------
+# HQRRP on the sketch (Sec. 5.2.2; cqrrpt_hqrrp, cqrrpt_factor_hqrrp_ex)
+# against the oracle's hqrrp. The sample Omega X is one product on each side
+# (sums in different orders), so pivots must be identical wherever the
+# sample's norms are not within rounding of each other (random inputs), R to
+# 1e-13 relative; the GEQP3 order is not expected.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,n,b,s,spec", [(60, 40, 4, 4, "gauss"), (50, 50, 16, 8, "log1e6"),
+                                          (300, 257, 16, 8, "log1e10"), (700, 333, 7, 3, "gauss"),
+                                          (1280, 1024, 16, 8, "log1e8")])
+def test_hqrrp_parity(P, d, n, b, s, spec):
+    say(f"hqrrp d={d} n={n} b={b} s={s} {spec}")
+    if spec == "gauss":
+        X = W.gaussian_matrix(d, n, seed=d + n)
+    else:
+        X = W.spectrum_matrix(d, n, W.logspaced_spectrum(n, float(spec[3:])), seed=d % 97)
+    Jo, Ro = O.hqrrp(X, b, s, seed=5)
+    Jg, Rg, info = P.hqrrp(to_gpu(X), b, s, 5)
+    assert info.status == 0
+    Jg, Rg = to_np(Jg), to_np(Rg)
+    assert np.array_equal(Jg, Jo)
+    dR = np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro)
+    assert dR <= 1e-13, f"dR {dR:.2e}"
+    assert np.array_equal(Rg, np.triu(Rg)) and np.all(np.diag(Rg) >= 0)
+    say(f"  dR {dR:.2e}")
+
+
+def test_hqrrp_zero_columns_and_limits(P):
+    # Exactly zero columns are chosen last and leave zero diagonal entries
+    # (the zero-diagonal rule of the sample update keeps the rest finite);
+    # shapes past the register-resident limits are refused.
+    X = W.gaussian_matrix(80, 30, seed=3)
+    X[:, [4, 17]] = 0.0
+    Jo, Ro = O.hqrrp(X, 8, 4, seed=2)
+    Jg, Rg, info = P.hqrrp(to_gpu(X), 8, 4, 2)
+    Jg, Rg = to_np(Jg), to_np(Rg)
+    assert np.array_equal(Jg, Jo) and set(Jg[-2:].tolist()) == {4, 17}
+    assert np.all(np.isfinite(Rg)) and Rg[-1, -1] == 0.0 and Rg[-2, -2] == 0.0
+    assert np.linalg.norm(Rg - Ro) <= 1e-13 * np.linalg.norm(Ro)
+    for d, n, b, s in ((4000, 100, 16, 8), (2600, 2100, 16, 8), (100, 50, 17, 0),
+                       (100, 50, 16, 9)):
+        assert P.lib().cqrrpt_hqrrp_workspace_bytes(d, n, b, s) == 0
+
+
+@pytest.mark.parametrize("m,n,d,nnz,spec", [(20003, 200, 250, 8, "log1e8"),
+                                            (8192, 100, 125, 4, "cliff"),
+                                            (30000, 512, 640, 8, "log1e12")])
+def test_factor_hqrrp_parity(P, m, n, d, nnz, spec):
+    say(f"factor hqrrp m={m} n={n} d={d} {spec}")
+    if spec == "cliff":
+        # A drop of 100x after 60 columns, then a graded tail well above the
+        # rounding level (pivot decisions there stay defined).
+        s = np.concatenate([np.geomspace(1.0, 1e-6, 60), np.geomspace(1e-8, 1e-10, n - 60)])
+        A = W.spectrum_matrix(m, n, s, seed=3)
+    else:
+        A = W.spectrum_matrix(m, n, W.logspaced_spectrum(n, float(spec[3:])), seed=m % 89)
+    orc = O.cqrrpt_hqrrp(A, d, nnz, seed=7, tol=1e-14, b=16, s=8, hseed=11)
+    gpu = P.factor_hqrrp(to_gpu(A), d, nnz, 7, 1e-14, block=16, oversample=8, hseed=11)
+    compare_factor(A, gpu, orc, f"hqrrp {m}x{n}")
