@@ -7,12 +7,12 @@
 // (64 wr, 64 wc) as 4 x 4 accumulators of 16 x 16. There is no LDS and no
 // barrier: each wave loads its own operand fragments (the second wave that
 // needs the same columns finds them in L1), two register stages deep, so the
-// matrix cores of a wave run while its next 16 rows are in flight. One
+// matrix cores of a wave run while its next 32 rows are in flight. One
 // workgroup per CU (the accumulators and two operand stages fill the
 // register file).
 //
 // The sum over rows runs in any order both operands agree on, so each lane
-// takes the rows it can read as 16-byte pairs: in a 16-row step, lane
+// takes the rows it can read as 16-byte pairs: in each 16 rows of a step, lane
 // (l16, lq) of a fragment holds rows (2 lq, 2 lq + 1) and (8 + 2 lq,
 // 9 + 2 lq) of column 16 f + l16, and the instruction of sub-step s takes
 // K = lq from pair s / 2, element s % 2. Partial tiles are stored row-major
@@ -26,10 +26,14 @@ constexpr int kThreads = 256;
 constexpr int kXcds = 8;   // workgroups are dealt to the XCDs round-robin
 constexpr int kGT = 128;   // output tile
 // Rows per step and workgroups per CU. Measured at 4194304 x 2048 with
-// ld = m + 16: 16 rows and one workgroup 308 ms; 8 rows and one workgroup
-// 487 ms; 8 rows and two workgroups (accumulators, operands and pointers
-// then spill) 484 ms.
-constexpr int kKS = 16;
+// ld = m + 16 (one workgroup per CU unless stated): 8 rows 487 ms (two
+// workgroups, whose accumulators, operands and pointers then spill, 484 ms);
+// 16 rows 308-313 ms (three register stages of 16 rows: the same); 24 rows
+// 286 ms; 32 rows 283-293 ms; 40 rows 290 ms. Larger steps leave fewer
+// waits and loop branches per matrix-core instruction; the order of the
+// additions is the same for every step size (step after step, two rows per
+// sub-step pair).
+constexpr int kKS = 32;
 constexpr int kOcc = 1;
 
 typedef double d2_t __attribute__((ext_vector_type(2)));
