@@ -25,6 +25,8 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kMaxNnz = 32;
 
+typedef double d2v __attribute__((ext_vector_type(2)));
+
 // ---------------------------------------------------------------------------
 // Export of S (rows and signs per column) for callers and parity checks.
 // ---------------------------------------------------------------------------
@@ -214,12 +216,12 @@ saso_partial_kernel(const double* __restrict__ A, int64_t lda, int64_t m, int64_
 // ---------------------------------------------------------------------------
 // Register-accumulator variant of the partial sketch. With THR threads,
 // thread t owns targets r = t + THR i (i < T) for all NC columns of the
-// block, held in registers.
-// Per sub-chunk it walks its T segments in lock step, reading whole staged
-// rows of A (NC contiguous doubles) from LDS. Within a target the order of
-// the additions is ascending source row, sub-chunk after sub-chunk.
+// block, held in registers; sub-chunks hold TS source rows.
+// Per sub-chunk it walks its T segments one after the other, reading whole
+// staged rows of A (NC contiguous doubles) from LDS. Within a target the
+// order of the additions is ascending source row, sub-chunk after sub-chunk.
 // ---------------------------------------------------------------------------
-template <int T, int NC, int LL, int THR>
+template <int T, int NC, int LL, int THR, int TS>
 __global__ void __launch_bounds__(THR)
 saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, int64_t n, int d,
                         int nnz, int ts, int subs_per_chunk, int nsub,
@@ -231,10 +233,11 @@ saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, in
   // so random rows start on 16 different bank offsets (a 64-byte pitch
   // gives 4) and 16-byte reads stay aligned.
   constexpr int kRowPitch = NC + 2;
+  static_assert(NC % 2 == 0, "rows are read as 16-byte pairs");
   extern __shared__ double smem[];
-  double* tile = smem;                                                   // ts * (NC + 2)
-  int* sseg = reinterpret_cast<int*>(tile + (size_t)ts * kRowPitch);    // d + 1
-  uint16_t* slst = reinterpret_cast<uint16_t*>(sseg + ((d + 1 + 3) & ~3));  // ts * nnz
+  double* tile = smem;                                                   // TS * (NC + 2)
+  int* sseg = reinterpret_cast<int*>(tile + (size_t)TS * kRowPitch);    // d + 1
+  uint16_t* slst = reinterpret_cast<uint16_t*>(sseg + ((d + 1 + 3) & ~3));  // TS * nnz
 
   const int tid = threadIdx.x;
   const int64_t c0 = (int64_t)blockIdx.x * NC;
@@ -249,26 +252,28 @@ saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, in
   // Sub-chunk sb's tile of A, segment table and entry list are loaded into
   // registers one sub-chunk ahead (all loads of a sub-chunk issued back to
   // back), then stored to LDS after the previous walk. Fixed per-thread load
-  // counts: the tile holds ts * NC <= 4096 values, the segment table
-  // d + 1 <= 256 T + 1 offsets, the list ts * nnz <= 512 LL entries.
-  constexpr int kTileLoads = (4096 + THR - 1) / THR;
+  // counts: the tile holds TS * NC values, the segment table d + 1 <=
+  // THR T + 1 offsets, the list TS * nnz <= 2 THR LL entries.
+  static_assert((TS & (TS - 1)) == 0, "sub-chunk rows are a power of two");
+  constexpr int kTileLoads = (TS * NC + THR - 1) / THR;
   constexpr int kSegLoads = T + 1;
   constexpr int kListLoads = LL;  // 32-bit words, two entries each
-  const int ts_shift = 31 - __clz(ts);       // ts is a power of two
+  constexpr int ts_shift = __builtin_ctz(TS);
+  (void)ts;  // equal to TS
   double tv[kTileLoads];
   int sv[kSegLoads];
   uint32_t lv[kListLoads];
   int rows_next = 0;
   auto prefetch = [&](int sb) {
-    const int64_t j0 = (int64_t)sb * ts;
-    const int rows_here = (int)((m - j0) < ts ? (m - j0) : ts);
+    const int64_t j0 = (int64_t)sb * TS;
+    const int rows_here = (int)((m - j0) < TS ? (m - j0) : TS);
     rows_next = rows_here;
 #pragma unroll
     for (int i = 0; i < kTileLoads; ++i) {
       const int e = tid + THR * i;
       const int c = e >> ts_shift;
-      const int jl = e & (ts - 1);
-      tv[i] = (e < ts * NC && jl < rows_here && c < ncols) ? A[(j0 + jl) + (c0 + c) * lda] : 0.0;
+      const int jl = e & (TS - 1);
+      tv[i] = (e < TS * NC && jl < rows_here && c < ncols) ? A[(j0 + jl) + (c0 + c) * lda] : 0.0;
     }
     const int32_t* segb = seg + (int64_t)sb * (d + 1);
 #pragma unroll
@@ -276,7 +281,7 @@ saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, in
       const int r = tid + THR * i;
       sv[i] = r <= d ? segb[r] : 0;
     }
-    const uint32_t* lb = reinterpret_cast<const uint32_t*>(list + (int64_t)sb * ts * nnz);
+    const uint32_t* lb = reinterpret_cast<const uint32_t*>(list + (int64_t)sb * TS * nnz);
     const int nw = (rows_here * nnz + 1) >> 1;
 #pragma unroll
     for (int i = 0; i < kListLoads; ++i) {
@@ -294,7 +299,7 @@ saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, in
 #pragma unroll
     for (int i = 0; i < kTileLoads; ++i) {
       const int e = tid + THR * i;
-      if (e < ts * NC) tile[(e & (ts - 1)) * kRowPitch + (e >> ts_shift)] = tv[i];
+      if (e < TS * NC) tile[(e & (TS - 1)) * kRowPitch + (e >> ts_shift)] = tv[i];
     }
 #pragma unroll
     for (int i = 0; i < kSegLoads; ++i) {
@@ -313,43 +318,31 @@ saso_partial_reg_kernel(const double* __restrict__ A, int64_t lda, int64_t m, in
     __syncthreads();
     if (sb + 1 < sb1) prefetch(sb + 1);
 
-    // Walk this thread's T target segments as one flat list (segment after
-    // segment, each in ascending source row): slot e belongs to target i,
-    // the segment holding position e, found without branches. Every slot
-    // does useful work in every lane until the lane's list ends, and each
-    // row read serves one target: the row is added with weight +-1 to target
-    // i and with weight 0 to the others (fma with a zero weight leaves an
-    // accumulator unchanged), so the accumulators stay in registers with
-    // static indices.
-    int base[T], pre[T + 1];
-    pre[0] = 0;
+    // Walk this thread's T target segments one after the other, each in
+    // ascending source row, with the accumulators of segment i at static
+    // register indices. A wave runs each segment loop as long as its
+    // longest lane needs; walking all T segments as one flat list instead
+    // (one loop, each row added with weight +-1 to its target and 0 to the
+    // others) did three times the FMAs and took 37.8 against 34.9 ms at
+    // 4194304 x 2048.
 #pragma unroll
     for (int i = 0; i < T; ++i) {
       const int r = tid + THR * i;
-      base[i] = r < d ? sseg[r] : 0;
-      pre[i + 1] = pre[i] + (r < d ? sseg[r + 1] - base[i] : 0);
-    }
-    const int total = pre[T];
-    for (int e = 0; e < total; ++e) {
-      int seg_i = 0;
-      int off = base[0] + e;
+      const int e0 = r < d ? sseg[r] : 0;
+      const int e1 = r < d ? sseg[r + 1] : 0;
+      for (int e = e0; e < e1; ++e) {
+        const unsigned v = slst[e];
+        // The row as 16-byte reads (ds_read_b128); read as pairs of 8-byte
+        // halves (what the compiler emits for double loads here) the
+        // random rows cost 53.6 instead of 37.1 ms at 4194304 x 2048.
+        const d2v* row = reinterpret_cast<const d2v*>(tile + (v >> 1) * kRowPitch);
+        const double sg = (v & 1u) ? -1.0 : 1.0;
 #pragma unroll
-      for (int q = 1; q < T; ++q) {
-        const bool past = e >= pre[q];
-        seg_i += past ? 1 : 0;
-        off = past ? base[q] + (e - pre[q]) : off;
-      }
-      const unsigned v = slst[off];
-      const double* row = tile + (v >> 1) * kRowPitch;
-      const double sg = (v & 1u) ? -1.0 : 1.0;
-      double rv[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) rv[c] = row[c];
-#pragma unroll
-      for (int i = 0; i < T; ++i) {
-        const double w = i == seg_i ? sg : 0.0;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) acc[i][c] = fma(w, rv[c], acc[i][c]);
+        for (int c = 0; c < NC / 2; ++c) {
+          const d2v x = row[c];
+          acc[i][2 * c] = fma(sg, x.x, acc[i][2 * c]);
+          acc[i][2 * c + 1] = fma(sg, x.y, acc[i][2 * c + 1]);
+        }
       }
     }
   }
@@ -390,7 +383,6 @@ saso_reduce_kernel(const double* __restrict__ part, int64_t part_ld, int64_t par
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int sub_rows(int nnz) { return nnz <= 16 ? 512 : 256; }
 
 size_t index_lds_bytes(int d, int nnz, int ts) {
   return (size_t)((d + 1 + 3) & ~3) * 4 + (size_t)3 * ts * nnz * 2;
@@ -402,17 +394,31 @@ size_t partial_reg_lds_bytes(int d, int nnz, int ts, int nc) {
 
 // Threads per workgroup of the register variant and targets per thread
 // (d rows over the threads, rounded up to an instantiated count; 0: none,
-// the LDS variant runs). More threads mean fewer targets per thread (less
-// of the walk's weighted work) and more waves to cover its dependent LDS
-// reads. Measured sketch times, 256 / 512 / 1024 threads: 4194304 x 2048
-// with d = 2560: 103.9 / 63.3 / 53.6 ms; 131072 x 1024, d = 1280: 0.904 /
-// 0.889 / 0.851 ms; 1048576 x 512, d = 640: 2.92 / 2.84 / 3.18 ms.
+// the LDS variant runs). More threads mean fewer targets per thread and
+// more waves to cover the walk's dependent LDS reads. Measured sketch
+// times with the earlier walk (one flat list per thread, rows read as
+// 8-byte halves), 256 / 512 / 1024 threads: 4194304 x 2048 with d = 2560:
+// 103.9 / 63.3 / 53.6 ms; 131072 x 1024, d = 1280: 0.904 / 0.889 / 0.851
+// ms; 1048576 x 512, d = 640: 2.92 / 2.84 / 3.18 ms. With the current walk
+// 512 threads (eight targets each) take 76.7 against 37.7 ms at d = 2560.
 int reg_threads(int d) { return d > 1024 && d <= 3072 ? 1024 : 512; }
 
 int reg_targets(int d, int thr) {
   const int need = (d + thr - 1) / thr;
   if (thr == 1024) return need <= 2 ? 2 : need <= 3 ? 3 : 0;
   return need <= 1 ? 1 : need <= 2 ? 2 : need <= 8 ? 8 : 0;
+}
+
+// Source rows per sub-chunk (a barrier pair each). Longer sub-chunks even
+// out the per-lane entry counts a wave waits for, but take more registers
+// for the prefetch: 1024 rows where two targets per thread on 1024 threads
+// leave room (131072 x 1024, d = 1280: 0.493 against 0.536 ms); with three
+// targets they spill (4194304 x 2048: 40.3 against 34.9 ms), and on 512
+// threads they would halve the workgroups per CU.
+int sub_rows(int d, int nnz) {
+  if (nnz > 16) return 256;
+  const int thr = reg_threads(d);
+  return thr == 1024 && reg_targets(d, thr) == 2 ? 1024 : 512;
 }
 
 // LL: 32-bit list words per thread, ts * nnz / (2 thr) rounded up to 2, 4,
@@ -422,14 +428,17 @@ int reg_list_words(int ts, int nnz, int thr) {
   return w <= 2 ? 2 : w <= 4 ? 4 : w <= 8 ? 8 : 16;
 }
 
-const void* reg_partial_kernel(int T, int NC, int LL, int THR) {
-#define CQ_SK(TT, CC, HH)                                                               \
-  if (T == TT && NC == CC && THR == HH)                                                 \
-    return LL <= 2 ? (const void*)saso_partial_reg_kernel<TT, CC, 2, HH>                \
-         : LL <= 4 ? (const void*)saso_partial_reg_kernel<TT, CC, 4, HH>                \
-         : LL <= 8 ? (const void*)saso_partial_reg_kernel<TT, CC, 8, HH>                \
-                   : (const void*)saso_partial_reg_kernel<TT, CC, 16, HH>;
-  CQ_SK(1, 8, 512) CQ_SK(2, 8, 512) CQ_SK(8, 8, 512) CQ_SK(2, 8, 1024) CQ_SK(3, 8, 1024)
+const void* reg_partial_kernel(int T, int NC, int LL, int THR, int TS) {
+#define CQ_SK(TT, CC, HH, SS)                                                           \
+  if (T == TT && NC == CC && THR == HH && TS == SS)                                     \
+    return LL <= 2 ? (const void*)saso_partial_reg_kernel<TT, CC, 2, HH, SS>            \
+         : LL <= 4 ? (const void*)saso_partial_reg_kernel<TT, CC, 4, HH, SS>            \
+         : LL <= 8 ? (const void*)saso_partial_reg_kernel<TT, CC, 8, HH, SS>            \
+                   : (const void*)saso_partial_reg_kernel<TT, CC, 16, HH, SS>;
+#define CQ_SK2(TT, HH) CQ_SK(TT, 8, HH, 256) CQ_SK(TT, 8, HH, 512)
+  CQ_SK2(1, 512) CQ_SK2(2, 512) CQ_SK2(8, 512) CQ_SK2(2, 1024) CQ_SK2(3, 1024)
+  CQ_SK(2, 8, 1024, 1024)
+#undef CQ_SK2
 #undef CQ_SK
   return nullptr;
 }
@@ -454,7 +463,7 @@ hipError_t launch_saso_sample(int64_t m, int d, int nnz, uint64_t seed, int32_t*
 SketchPlan plan_sketch(int64_t m, int64_t n, int d, int nnz) {
   const Device& dev = device_info();
   SketchPlan p{};
-  p.ts = sub_rows(nnz);
+  p.ts = sub_rows(d, nnz);
   p.nsub = (int)((m + p.ts - 1) / p.ts);
   const size_t budget = dev.lds_per_block;
   p.thr = reg_threads(d);
@@ -478,7 +487,8 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int d, int nnz) {
   // partial sums stay small next to A.
   int per_cu = 2;
   if (p.reg_t > 0) {
-    const void* fn = reg_partial_kernel(p.reg_t, nc, reg_list_words(p.ts, nnz, p.thr), p.thr);
+    const void* fn =
+        reg_partial_kernel(p.reg_t, nc, reg_list_words(p.ts, nnz, p.thr), p.thr, p.ts);
     int occ = 0;
     if (fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, p.thr, p.lds_bytes) ==
                   hipSuccess &&
@@ -513,7 +523,7 @@ size_t sketch_ws_bytes(const SketchPlan& p) { return p.seg_bytes + p.list_bytes 
 
 bool sketch_fits(int d, int nnz) {
   const Device& dev = device_info();
-  const int ts = sub_rows(nnz);
+  const int ts = sub_rows(d, nnz);
   return index_lds_bytes(d, nnz, ts) <= dev.lds_per_block &&
          partial_lds_bytes(d, nnz, ts, 1) <= dev.lds_per_block;
 }
@@ -539,7 +549,8 @@ hipError_t launch_sketch(const SketchPlan& p, const double* A, int64_t lda, int6
   const int64_t ncb = (n + p.nc - 1) / p.nc;
   const int direct = p.nchunk == 1;
   if (p.reg_t > 0) {
-    const void* fn = reg_partial_kernel(p.reg_t, p.nc, reg_list_words(p.ts, nnz, p.thr), p.thr);
+    const void* fn =
+        reg_partial_kernel(p.reg_t, p.nc, reg_list_words(p.ts, nnz, p.thr), p.thr, p.ts);
     if (!fn) return hipErrorInvalidValue;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
     if (e != hipSuccess) return e;
