@@ -411,14 +411,16 @@ int reg_targets(int d, int thr) {
 
 // Source rows per sub-chunk (a barrier pair each). Longer sub-chunks even
 // out the per-lane entry counts a wave waits for, but take more registers
-// for the prefetch: 1024 rows where two targets per thread on 1024 threads
-// leave room (131072 x 1024, d = 1280: 0.493 against 0.536 ms); with three
-// targets they spill (4194304 x 2048: 40.3 against 34.9 ms), and on 512
-// threads they would halve the workgroups per CU.
+// for the prefetch: 1024 rows on 1024 threads with two targets per thread
+// (131072 x 1024, d = 1280: 0.493 against 0.536 ms), or three and at most 8
+// nonzeros per column (4194304 x 2048, d = 2560: 26.3 against 30.4 ms; with
+// more nonzeros the list words spill). On 512 threads they would halve the
+// workgroups per CU.
 int sub_rows(int d, int nnz) {
   if (nnz > 16) return 256;
   const int thr = reg_threads(d);
-  return thr == 1024 && reg_targets(d, thr) == 2 ? 1024 : 512;
+  const int t = reg_targets(d, thr);
+  return thr == 1024 && (t == 2 || (t == 3 && nnz <= 8)) ? 1024 : 512;
 }
 
 // LL: 32-bit list words per thread, ts * nnz / (2 thr) rounded up to 2, 4,
@@ -437,7 +439,7 @@ const void* reg_partial_kernel(int T, int NC, int LL, int THR, int TS) {
                    : (const void*)saso_partial_reg_kernel<TT, CC, 16, HH, SS>;
 #define CQ_SK2(TT, HH) CQ_SK(TT, 8, HH, 256) CQ_SK(TT, 8, HH, 512)
   CQ_SK2(1, 512) CQ_SK2(2, 512) CQ_SK2(8, 512) CQ_SK2(2, 1024) CQ_SK2(3, 1024)
-  CQ_SK(2, 8, 1024, 1024)
+  CQ_SK(2, 8, 1024, 1024) CQ_SK(3, 8, 1024, 1024)
 #undef CQ_SK2
 #undef CQ_SK
   return nullptr;

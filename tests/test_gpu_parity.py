@@ -126,12 +126,14 @@ def test_sketch_parity(P, m, n, d, nnz):
 # which take 512 threads with one or two target rows per thread and 512- or
 # 256-row sub-chunks): 1024 threads with two target rows on 1024-row
 # sub-chunks (d = 1800 and 1500, the latter with nnz = 16 and with fewer
-# rows than one sub-chunk), with three on 512-row sub-chunks (d = 2560 and
-# 3000), 512 threads with eight (d = 4096), and the LDS variant past 4096.
+# rows than one sub-chunk), with three on 1024-row sub-chunks (d = 2560 and
+# 3000) and, past 8 nonzeros per column, on 512-row ones (d = 2600), 512
+# threads with eight (d = 4096), and the LDS variant past 4096.
 @pytest.mark.parametrize("m,n,d,nnz", [(30000, 40, 1800, 8), (30000, 21, 1500, 16),
                                        (700, 12, 1500, 8), (30000, 37, 2560, 8),
-                                       (20000, 33, 3000, 8), (40000, 20, 4096, 8),
-                                       (30000, 24, 5000, 8), (25000, 9, 9000, 4)])
+                                       (20000, 33, 3000, 8), (20000, 15, 2600, 12),
+                                       (40000, 20, 4096, 8), (30000, 24, 5000, 8),
+                                       (25000, 9, 9000, 4)])
 def test_sketch_parity_wide(P, m, n, d, nnz):
     test_sketch_parity(P, m, n, d, nnz)
 
