@@ -46,7 +46,7 @@ HEADLINE = "fp64_4194304x2048_rank1536"
 # (m, k_o, k)).
 MFMA_STAGES = (
     ("precondition", "trsm_rows_kernel<128, double, double>", lambda m, ko, k: m * ko * ko),
-    ("gram", "gram_dv_kernel<16, 1> + gram128_reduce_kernel", lambda m, ko, k: m * ko * (ko + 1)),
+    ("gram", "gram_dv_kernel<32, 1> + gram128_reduce_kernel", lambda m, ko, k: m * ko * (ko + 1)),
     ("q_solve", "qform_kernel<256, double, double, double>", lambda m, ko, k: m * k * k),
 )
 MIXED_STAGES = (
