@@ -78,8 +78,11 @@ gram_dv_kernel(const double* __restrict__ X, int64_t ldx, int64_t m, const int64
   const int lq = lane >> 4;
   const int wr = wave >> 1;
   const int wc = wave & 1;
-  // On a diagonal tile the (1, 0) block lies below the diagonal: never read.
+  // On a diagonal tile the (1, 0) block lies below the diagonal, and a
+  // block whose rows or columns start at k or past it lies outside the
+  // leading k x k block: never read.
   if (I == J && wr > wc) return;
+  if (i0 + 64 * wr >= k || j0 + 64 * wc >= k) return;
   const int64_t r0 = (int64_t)split * rows_per_split;
   const int64_t r1 = (r0 + rows_per_split) < m ? (r0 + rows_per_split) : m;
   const int64_t nrows = r1 > r0 ? r1 - r0 : 0;
@@ -199,7 +202,7 @@ gram_dv_kernel(const double* __restrict__ X, int64_t ldx, int64_t m, const int64
 namespace cqh {
 
 // Splits: a multiple of the XCD count, at most the 128 x 128 Gram's count
-// (whose partials the workspace holds), at least 1024 rows each; one
+// (whose partials the workspace holds), at least 512 rows each; one
 // workgroup per CU, so the grid runs in rounds of the CU count and the time
 // goes as ceil(rounds) / splits.
 int gram_dv_splits(int64_t m, int kmax) {
@@ -210,7 +213,7 @@ int gram_dv_splits(int64_t m, int kmax) {
   int best = kXcds;
   double best_cost = 0.0;
   for (int ns = kXcds; ns <= cap; ns += kXcds) {
-    if (ns > kXcds && (m + ns - 1) / ns < 1024) break;
+    if (ns > kXcds && (m + ns - 1) / ns < 512) break;
     const double cost = (double)((tiles * ns + slots - 1) / slots) / ns;
     if (ns == kXcds || cost < best_cost * 0.999) {
       best = ns;
