@@ -47,7 +47,7 @@ HEADLINE = "fp64_4194304x2048_rank1536"
 MFMA_STAGES = (
     ("precondition", "trsm_rows_kernel<128, double, double>", lambda m, ko, k: m * ko * ko),
     ("gram", "gram_dv_kernel<32, 1> + gram128_reduce_kernel", lambda m, ko, k: m * ko * (ko + 1)),
-    ("q_solve", "qform_kernel<256, double, double, double>", lambda m, ko, k: m * k * k),
+    ("q_solve", "qform_pack_kernel + qform_dv_kernel", lambda m, ko, k: m * k * k),
 )
 MIXED_STAGES = (
     ("precondition", "trsm_rows_kernel<128, float, float>", lambda m, ko, k: m * ko * ko,
@@ -202,9 +202,10 @@ def rooflines(stages, w, ko, k, mixed=False, fp32_lines=False):
 
 
 def kernel_source_hash():
-    """Hash of the sources of the three matrix-core stages (tall.hip, gram.hip)."""
+    """Hash of the sources of the three matrix-core stages (tall.hip, gram.hip,
+    qform_dv.hip)."""
     h = hashlib.sha256()
-    for name in ("tall.hip", "gram.hip"):
+    for name in ("tall.hip", "gram.hip", "qform_dv.hip"):
         with open(os.path.join(HERE, "paper_2311_08316_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -32,6 +32,8 @@ EXTRA = {
     # The directly loaded Gram: in accumulation registers every accumulator
     # was copied out and back on each trip of the K loop.
     "gram.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+    # The directly loaded Q product, for the same reason.
+    "qform_dv.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
     # The throughput probe's accumulators too (in accumulation registers they
     # were copied out and back around every round of the loop).
     "probe.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],

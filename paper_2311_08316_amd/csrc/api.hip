@@ -569,7 +569,9 @@ int phase_tail(FactorCtx& c) {
   if (c.Rpre) {
     // Implicit Q: M_pre stays.
   } else if (c.mode == CQRRPT_FP64) {
-    CQ_TRY(cqh::launch_qform_f64(Q, ldq, Q, ldq, c.Winv, n, m, c.k_dev, c.info, s));
+    // W packed into the Gram's partial tiles (dead once G is summed).
+    CQ_TRY(cqh::launch_qform_dv_f64(Q, ldq, Q, ldq, c.Winv, n, m, c.k_dev, ni, c.Gp,
+                                    c.L.off_g - c.L.off_syrkp, c.info, s));
   } else if (c.mode == CQRRPT_MIXED_FP32_CHOLQR2) {
     float* M32 = reinterpret_cast<float*>(c.base + c.L.off_mpre32);
     CQ_TRY(cqh::launch_qform_f32(M32, m, Q, ldq, c.Winv, n, m, c.k_dev, c.info, s));
@@ -604,7 +606,8 @@ int phase_tail(FactorCtx& c) {
                                 c.info, s, INFINITY, false, pass));
     CQ_TRY(cqh::launch_cholqr2_commit(pass, c.k_dev, k2_dev, apply, c.R, c.ldr, c.Rsk, n, ni,
                                       c.info, s));
-    CQ_TRY(cqh::launch_qform_f64(Q, ldq, Q, ldq, c.Winv, n, m, c.k_dev, c.info, s, apply));
+    CQ_TRY(cqh::launch_qform_dv_f64(Q, ldq, Q, ldq, c.Winv, n, m, c.k_dev, ni, c.Gp,
+                                    c.L.off_g - c.L.off_syrkp, c.info, s, apply));
     CQ_TRY(cqh::launch_trmm_r(c.G, n, c.Rsk, n, c.R, c.ldr, ni, c.k_dev, c.info, s, apply));
   }
   c.mk.mark(9);

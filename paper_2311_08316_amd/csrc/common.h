@@ -395,16 +395,23 @@ hipError_t launch_trsm_mixed(const double* B, int64_t ldb, const int64_t* gather
                              const int64_t* kdev, int kmax, double* pack,
                              const cqrrpt_info_t* info, hipStream_t s);
 
-// Q[:, :k] = M[:, :k] W[:k, :k], W upper triangular (read above the
-// diagonal and on it only), 32-bit element offsets (ldw * 8192 < 2^32).
-// M may alias Q (same ld). enable as for the solve.
-hipError_t launch_qform_f64(const double* M, int64_t ldm, double* Q, int64_t ldq,
-                            const double* W, int64_t ldw, int64_t m, const int64_t* kdev,
-                            const cqrrpt_info_t* info, hipStream_t s,
-                            const int* enable = nullptr);
+// Q[:, :k] = M[:, :k] W[:k, :k] for FP32-stored M (FP64 products), W upper
+// triangular (read above the diagonal and on it only), 32-bit element
+// offsets (ldw * 8192 < 2^32); LDS-staged tiles.
 hipError_t launch_qform_f32in(const float* M, int64_t ldm, double* Q, int64_t ldq,
                               const double* W, int64_t ldw, int64_t m, const int64_t* kdev,
                               const cqrrpt_info_t* info, hipStream_t s);
+// The FP64 product with both operands loaded straight into matrix-core
+// registers (qform_dv.hip): W is first packed in operand order into `pack`
+// (at least qform_dv_pack_bytes(kmax) bytes, dead after the call), then
+// Q[:, :k] = M[:, :k] W[:k, :k] with the order of additions of the
+// LDS-staged product. M may alias Q (same ld). enable as for the solve.
+size_t qform_dv_pack_bytes(int kmax);
+hipError_t launch_qform_dv_f64(const double* M, int64_t ldm, double* Q, int64_t ldq,
+                               const double* W, int64_t ldw, int64_t m, const int64_t* kdev,
+                               int kmax, double* pack, size_t pack_bytes,
+                               const cqrrpt_info_t* info, hipStream_t s,
+                               const int* enable = nullptr);
 
 int syrk_splits(int64_t m, int kmax);
 int gram_splits(int64_t m, int kmax);

@@ -249,7 +249,9 @@ tn_reduce_kernel(const double* __restrict__ P, int nsplit, int ti, int tiles, in
 }
 
 int tn_splits(int64_t m, int tiles) {
-  const int64_t slots = 2 * (int64_t)cqh::device_info().num_cu / kXcds;
+  // At least one slot, also where no device is visible (placeholder CU count).
+  int64_t slots = 2 * (int64_t)cqh::device_info().num_cu / kXcds;
+  if (slots < 1) slots = 1;
   int best = kXcds;
   double best_cost = 0.0;
   for (int ns = kXcds; ns <= 64; ns += kXcds) {

@@ -51,9 +51,10 @@ template <> CQ_INLINE int acc_row<float>(int lq, int r) { return 4 * lq + r; }
 // workgroup divide the reads of R (and of W in the Q product) the same way.
 constexpr int kPW = 128;        // panel width
 constexpr int kKB = 16;         // K per staging step
-// Rows per workgroup, measured at 4194304 x 2048: the Q product 313 ms with
-// 256 rows (eight waves, one workgroup per CU) against 328 ms with 128 (four
-// waves, two per CU); the solve 316 ms with 128 against 320 ms with 256.
+// Rows per workgroup, measured at 4194304 x 2048 in FP64 (which now runs
+// the Q product of qform_dv.hip, 300 ms): the Q product 313 ms with 256 rows
+// (eight waves, one workgroup per CU) against 328 ms with 128 (four waves,
+// two per CU); the solve 316 ms with 128 against 320 ms with 256.
 constexpr int kTRT = 128;  // rows per workgroup of the solve
 constexpr int kQRT = 256;  // rows per workgroup of the Q product
 
@@ -386,8 +387,9 @@ hipError_t launch_trsm_impl(const TB* B, int64_t ldb, const int64_t* gather, TX*
 // panels from the last to the first, so M may alias Q: panel c reads the
 // columns below c + 128 only, which later (lower) panels have not written.
 // The K loop stages M and W tiles through double-buffered LDS with two
-// register stages of prefetch;
-// a wave skips the K steps below its columns' diagonal. The accumulators
+// register stages of prefetch; a wave skips the K steps below its columns'
+// diagonal. This kernel serves FP32-stored M (the mixed modes); the FP64
+// product loads its operands straight into registers (qform_dv.hip). The accumulators
 // hold the transposed tile (rows on the N index), so the stores of 16
 // consecutive lanes cover 16 consecutive rows.
 // ---------------------------------------------------------------------------
@@ -921,13 +923,6 @@ hipError_t launch_trsm_mixed(const double* B, int64_t ldb, const int64_t* gather
                                                 pack, info, nullptr, s);
 }
 
-hipError_t launch_qform_f64(const double* M, int64_t ldm, double* Q, int64_t ldq,
-                            const double* W, int64_t ldw, int64_t m, const int64_t* kdev,
-                            const cqrrpt_info_t* info, hipStream_t s, const int* enable) {
-  return launch_qform_impl<double, double, double>(M, ldm, Q, ldq, W, ldw, m, kdev, info, enable,
-                                                   s);
-}
-
 hipError_t launch_qform_f32in(const float* M, int64_t ldm, double* Q, int64_t ldq,
                               const double* W, int64_t ldw, int64_t m, const int64_t* kdev,
                               const cqrrpt_info_t* info, hipStream_t s) {
@@ -935,25 +930,34 @@ hipError_t launch_qform_f32in(const float* M, int64_t ldm, double* Q, int64_t ld
                                                   nullptr, s);
 }
 
-// Splits: a multiple of the XCD count, at most 64, at least 1024 rows each,
-// partial tiles within 512 MB. Each XCD runs tiles x splits / 8 workgroups
-// in rounds of (two per CU) x (its CUs); the time goes as the number of
-// rounds times the rows per split, so take the count that minimises
-// ceil(rounds) / splits (a partly filled last round costs a whole round).
 // Row splits of the Gram kernels: at least kMinSplitRows rows each, and at
 // most 64 or, for few output tiles, about one (tile, split) pair per CU, so
 // that a Gram of one or a few tiles (k <= 384) still fills the device: at
 // 500,000 x 64 the Gram took 0.97 ms on 64 splits of 7,813 rows.
 constexpr int64_t kMinSplitRows = 512;
+// Workgroup slots per XCD at two workgroups per CU (at least one, also where
+// no device is visible and the count is a placeholder).
+int64_t max_slots() {
+  const int64_t v = 2 * (int64_t)device_info().num_cu / kXcds;
+  return v > 0 ? v : 1;
+}
+
 int max_splits(int64_t tiles) {
+  if (tiles < 1) return 64;
   const int64_t per_cu = (int64_t)device_info().num_cu / tiles / kXcds * kXcds;
   return (int)(per_cu > 64 ? per_cu : 64);
 }
 
+// Splits: a multiple of the XCD count, at most max_splits(tiles), at least
+// kMinSplitRows rows each,
+// partial tiles within 512 MB. Each XCD runs tiles x splits / 8 workgroups
+// in rounds of (two per CU) x (its CUs); the time goes as the number of
+// rounds times the rows per split, so take the count that minimises
+// ceil(rounds) / splits (a partly filled last round costs a whole round).
 int syrk_splits(int64_t m, int kmax) {
   const int nt = (kmax + kST - 1) / kST;
   const int64_t tiles = (int64_t)nt * (nt + 1) / 2;
-  const int64_t slots = 2 * (int64_t)device_info().num_cu / kXcds;
+  const int64_t slots = max_slots();
   const int64_t tile_bytes = (int64_t)kST * kST * 8;
   int best = kXcds;
   double best_cost = 0.0;
@@ -975,7 +979,7 @@ int syrk_splits(int64_t m, int kmax) {
 int gram_splits(int64_t m, int kmax) {
   const int nt = (kmax + kGT - 1) / kGT;
   const int64_t tiles = (int64_t)nt * (nt + 1) / 2;
-  const int64_t slots = 2 * (int64_t)device_info().num_cu / kXcds;
+  const int64_t slots = max_slots();
   const int64_t tile_bytes = (int64_t)kGT * kGT * 8;
   int best = kXcds;
   double best_cost = 0.0;
