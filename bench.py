@@ -45,7 +45,8 @@ HEADLINE = "fp64_4194304x2048_rank1536"
 # Matrix-core stages: (stage, kernel, algorithmic flops per launch from
 # (m, k_o, k)).
 MFMA_STAGES = (
-    ("precondition", "trsm_rows_kernel<128, double, double>", lambda m, ko, k: m * ko * ko),
+    ("precondition", "trsm_inv_kernel + trsm_rpack_kernel + trsm_dv_kernel",
+     lambda m, ko, k: m * ko * ko),
     ("gram", "gram_dv_kernel<32, 1> + gram128_reduce_kernel", lambda m, ko, k: m * ko * (ko + 1)),
     ("q_solve", "qform_pack_kernel + qform_dv_kernel", lambda m, ko, k: m * k * k),
 )

@@ -515,8 +515,9 @@ int phase_tall(FactorCtx& c) {
   c.mk.mark(3);
   if (c.mode == CQRRPT_FP64) {
     // S5: M_pre = A[:, J[:k_o]] R_sk^{-1}, written into Q.
-    CQ_TRY(cqh::launch_trsm_f64(c.A, c.lda, c.J, c.Q, c.ldq, c.Rsk, n, m, c.ko_dev, ni, c.tpack,
-                                c.info, s));
+    // R packed into the Gram's partial tiles (the Gram runs after the solve).
+    CQ_TRY(cqh::launch_trsm_dv_f64(c.A, c.lda, c.J, c.Q, c.ldq, c.Rsk, n, m, c.ko_dev, ni,
+                                   c.tpack, c.Gp, c.L.off_g - c.L.off_syrkp, c.info, s));
     c.mk.mark(4);
     // S6: G = M_pre^T M_pre.
     CQ_TRY(cqh::launch_gram_f64(c.Q, c.ldq, m, c.ko_dev, ni, c.Gp, c.G, n, c.info, s));

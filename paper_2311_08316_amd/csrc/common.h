@@ -381,15 +381,20 @@ hipError_t launch_rank_stage1(const double* R, int64_t ldr, int n, double tol, d
                               double* bmax, int64_t* kdev, cqrrpt_info_t* info, hipStream_t s);
 
 // X[:, :k] = B[:, gather[:k]] * R[:k, :k]^{-1}  (right, upper, non-unit).
-// pack: device scratch of trsm_pack_bytes(kmax) bytes (inverted 16 x 16
+// inv: device scratch of trsm_pack_bytes(kmax) bytes (inverted 16 x 16
 // diagonal blocks of R, rewritten by every launch).
 // enable (device int, optional): the launch does nothing when *enable == 0.
+// FP64, with both operands loaded straight into matrix-core registers (no
+// LDS, no barrier): R is also packed in operand order into `rpack` (at
+// least trsm_dv_pack_bytes(kmax) bytes, dead after the call); X holds the
+// bits of the LDS-staged solve (the mixed modes' FP32 solve below).
 size_t trsm_pack_bytes(int kmax);
-hipError_t launch_trsm_f64(const double* B, int64_t ldb, const int64_t* gather, double* X,
-                           int64_t ldx, const double* R, int64_t ldr, int64_t m,
-                           const int64_t* kdev, int kmax, double* pack,
-                           const cqrrpt_info_t* info, hipStream_t s,
-                           const int* enable = nullptr);
+size_t trsm_dv_pack_bytes(int kmax);
+hipError_t launch_trsm_dv_f64(const double* B, int64_t ldb, const int64_t* gather, double* X,
+                              int64_t ldx, const double* R, int64_t ldr, int64_t m,
+                              const int64_t* kdev, int kmax, double* inv, double* rpack,
+                              size_t rpack_bytes, const cqrrpt_info_t* info, hipStream_t s,
+                              const int* enable = nullptr);
 hipError_t launch_trsm_mixed(const double* B, int64_t ldb, const int64_t* gather, float* X,
                              int64_t ldx, const double* R, int64_t ldr, int64_t m,
                              const int64_t* kdev, int kmax, double* pack,

@@ -123,7 +123,9 @@ trsm_inv_kernel(const double* __restrict__ R, int64_t ldr, const int64_t* kdev, 
   for (int kk = 0; kk < kInvTile; ++kk) dst[(kk >> 2) * 64 + (kk & 3) * 16 + j] = x[kk];
 }
 
-// Triangular solve (FP64; FP32 in the mixed mode) with each wave owning 32 whole rows of the workgroup's 128 x 128
+// Triangular solve (the FP32 solve of the mixed modes; the FP64 solve is
+// trsm_dv_kernel below, the same scheme without LDS) with each wave owning
+// 32 whole rows of the workgroup's 128 x 128
 // panel (row tiles a = 0, 1; column tiles b = 0..7). The accumulators hold
 // the transposed tile: register r of lane (l16, lq) in acc[b][a] is element
 // (row 32 w + 16 a + l16, column 16 b + lq + 4 r). For the FP64 16x16x4
@@ -352,6 +354,228 @@ trsm_rows_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gathe
         __syncthreads();
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 triangular solve with the operands loaded straight into matrix-core
+// registers and no LDS or barrier. The same row ownership as above (a wave
+// owns 32 whole rows of each 128-column panel) makes the waves independent:
+// the K loop reads the wave's own solved columns of X and a packed copy of R
+// (32-deep steps, two register stages), and the diagonal phase reads its
+// strips R[tile t, panel] from the same packed copy, so nothing is shared
+// through LDS. The order of every accumulation is the one of the LDS-staged
+// kernel, so the results are the same bits.
+//
+// Packed R: panel p holds K rows 0 .. 128 p + 127 in steps t of kTKS rows;
+// per step, load j (8 kTKS / 8) and lane, two values: value (j, lane, e) is
+// R[kTKS t + 4 s + lq, 128 p + 16 b + l16] with b = j / (kTKS / 8) and s =
+// 2 (j % (kTKS / 8)) + e, stored when row <= column < k, else zero.
+// ---------------------------------------------------------------------------
+typedef double d2_t __attribute__((ext_vector_type(2)));
+// Step depth 16: at 32 the two register stages spilled.
+constexpr int kTKS = 16;                      // K per step
+constexpr int kTPairs = kTKS / 8;             // value pairs per column tile and step
+constexpr int kTSteps = kPW / kTKS;           // steps per 128 K rows
+constexpr int kTStepVals = 8 * kTPairs * 64 * 2;  // packed values per step
+
+__host__ __device__ inline int64_t trsm_panel_offset(int p) {
+  return (int64_t)kTStepVals * kTSteps * ((int64_t)p * (p + 1) / 2);
+}
+
+__global__ void __launch_bounds__(kThreads)
+trsm_rpack_kernel(const double* __restrict__ R, int64_t ldr, const int64_t* kdev, int npmax,
+                  double* __restrict__ Rp, const cqrrpt_info_t* info, const int* enable) {
+  if (info->status != 0 || (enable && *enable == 0)) return;
+  const int k = (int)*kdev;
+  if (k <= 0) return;
+  int g = blockIdx.y, p = 0;
+  while (p < npmax && g >= kTSteps * (p + 1)) g -= kTSteps * (p++ + 1);
+  if (p >= npmax || kPW * p >= k) return;
+  const int t = g;
+  const int v = blockIdx.x * kThreads + threadIdx.x;  // 0 .. kTStepVals - 1
+  const int e = v & 1;
+  const int lane = (v >> 1) & 63;
+  const int j = v >> 7;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int b = j / kTPairs, sub = 2 * (j % kTPairs) + e;
+  const int row = kTKS * t + 4 * sub + lq;
+  const int col = kPW * p + 16 * b + l16;
+  const double w = (row <= col && col < k) ? R[(int64_t)row + (int64_t)col * ldr] : 0.0;
+  Rp[trsm_panel_offset(p) + (int64_t)t * kTStepVals + v] = w;
+}
+
+__global__ void __launch_bounds__(kThreads, 1)
+trsm_dv_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gather, double* X,
+               int64_t ldx, const double* __restrict__ Rp, int64_t m, const int64_t* kdev,
+               const double* __restrict__ inv, const cqrrpt_info_t* info, const int* enable) {
+  if (info->status != 0 || (enable && *enable == 0)) return;
+  const int k = (int)*kdev;
+  if (k <= 0) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int l16 = lane & 15;
+  const int lq = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * kTRT;
+  // This lane's two rows (row tiles a = 0, 1), clamped for loads.
+  int64_t rowl[2], rowc[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    rowl[a] = row0 + 32 * wave + 16 * a + l16;
+    rowc[a] = rowl[a] < m ? rowl[a] : m - 1;
+  }
+  struct Stage {
+    double xv[2][kTKS / 4];  // X[rowc[a], 32 t + 4 s + lq]
+    d2_t rv[8 * kTPairs];    // packed R of the step
+  };
+  for (int c0 = 0; c0 < k; c0 += kPW) {
+    const int p = __builtin_amdgcn_readfirstlane(c0 / kPW);
+    const int nt = ((k - c0 < kPW ? k - c0 : kPW) + 15) / 16;
+    const double* rp = Rp + trsm_panel_offset(p) + 2 * lane;
+    d4_t acc[8][2];
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) acc[b][a] = d4_t{0, 0, 0, 0};
+
+    // acc = X[rows, :c0] R[:c0, panel] (c0 is a multiple of kTKS).
+    const int nst = c0 / kTKS;
+    auto load = [&](int t, Stage& st) {
+#pragma unroll
+      for (int sq = 0; sq < kTKS / 4; ++sq) {
+        const double* xc = X + (int64_t)(kTKS * t + 4 * sq + lq) * ldx;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) st.xv[a][sq] = xc[rowc[a]];
+      }
+      const double* r = rp + (int64_t)t * kTStepVals;
+#pragma unroll
+      for (int j = 0; j < 8 * kTPairs; ++j) st.rv[j] = *reinterpret_cast<const d2_t*>(r + 128 * j);
+    };
+    auto multiply = [&](const Stage& st) {
+#pragma unroll
+      for (int sq = 0; sq < kTKS / 4; ++sq) {
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const d2_t rj = st.rv[kTPairs * b + (sq >> 1)];
+          const double rf = (sq & 1) ? rj.y : rj.x;
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+            acc[b][a] = __builtin_amdgcn_mfma_f64_16x16x4f64(rf, st.xv[a][sq], acc[b][a], 0, 0, 0);
+        }
+      }
+    };
+    {
+      Stage s0, s1;
+      if (nst > 0) load(0, s0);
+      int t = 0;
+      for (; t + 2 < nst; t += 2) {
+        load(t + 1, s1);
+        __builtin_amdgcn_sched_barrier(0);
+        multiply(s0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(t + 2, s0);
+        __builtin_amdgcn_sched_barrier(0);
+        multiply(s1);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (t + 1 < nst) {
+        load(t + 1, s1);
+        multiply(s0);
+        multiply(s1);
+      } else if (t < nst) {
+        multiply(s0);
+      }
+    }
+
+    // Diagonal block, 16 columns at a time. Strip t (R[tile t, tile b] for
+    // the later tiles b, K index 4 sq + lq of the tile in slot sq) and B_t
+    // are loaded one tile ahead.
+    d2_t sr[2][8][2];  // [buffer][b][sq / 2]
+    double bt[2][2][4];
+    auto load_strip = [&](int t, d2_t (&dst)[8][2]) {
+      // K rows c0 + 16 t + 4 sq + lq: step 128 p / kTKS + 16 t / kTKS,
+      // sub-steps (16 t % kTKS) / 4 + sq.
+      const double* r = rp + (int64_t)(kTSteps * p + (16 * t) / kTKS) * kTStepVals;
+      const int base = ((16 * t) % kTKS) / 8;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        if (b > t) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            dst[b][h] = *reinterpret_cast<const d2_t*>(r + 128 * (kTPairs * b + base + h));
+        }
+      }
+    };
+    auto load_b = [&](int t, double (&dst)[2][4]) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int col = c0 + 16 * t + lq + 4 * r;
+        col = col < k ? col : k - 1;
+        const int64_t g = gather ? gather[col] : col;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) dst[a][r] = B[rowc[a] + g * ldb];
+      }
+    };
+    load_strip(0, sr[0]);
+    load_b(0, bt[0]);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if (t < nt) {
+        const int cur = t & 1;
+        // T_t = B_t - acc[t] (columns past k: B is taken as zero); register
+        // r holds column lq + 4 r, the K index of the next products' slot r.
+        double tv[2][4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            tv[a][r] = (c0 + 16 * t + lq + 4 * r < k ? bt[cur][a][r] : 0.0) - acc[t][a][r];
+        if (t + 1 < 8 && t + 1 < nt) {
+          load_strip(t + 1, sr[cur ^ 1]);
+          load_b(t + 1, bt[cur ^ 1]);
+        }
+        // X_t^T = inv(R_tt)^T T_t^T.
+        const double* pi = inv + (size_t)((c0 >> 4) + t) * kInvPack;
+        d4_t xt[2] = {d4_t{0, 0, 0, 0}, d4_t{0, 0, 0, 0}};
+#pragma unroll
+        for (int sq = 0; sq < 4; ++sq) {
+          const double vf = pi[sq * 64 + lane];
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+            xt[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(vf, tv[a][sq], xt[a], 0, 0, 0);
+        }
+        // X_t to memory: element (row 32 w + 16 a + l16, column 16 t + lq + 4 r).
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          if (rowl[a] < m) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int col = c0 + 16 * t + lq + 4 * r;
+              if (col < k) X[rowl[a] + (int64_t)col * ldx] = xt[a][r];
+            }
+          }
+        }
+        // acc[b][a] += R[tile t, tile b]^T X_t^T for the later tiles b.
+#pragma unroll
+        for (int b = t + 1; b < 8; ++b) {
+          if (b < nt) {
+#pragma unroll
+            for (int sq = 0; sq < 4; ++sq) {
+              const d2_t rj = sr[cur][b][sq >> 1];
+              const double rf = (sq & 1) ? rj.y : rj.x;
+#pragma unroll
+              for (int a = 0; a < 2; ++a)
+                acc[b][a] = __builtin_amdgcn_mfma_f64_16x16x4f64(rf, xt[a][sq], acc[b][a], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+    // The next panels read these columns back through other lanes of this
+    // wave: the stores reach memory before those loads.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -907,12 +1131,32 @@ size_t trsm_pack_bytes(int kmax) {
   return (size_t)((kmax + kInvTile - 1) / kInvTile) * kInvPack * 8;
 }
 
-hipError_t launch_trsm_f64(const double* B, int64_t ldb, const int64_t* gather, double* X,
-                           int64_t ldx, const double* R, int64_t ldr, int64_t m,
-                           const int64_t* kdev, int kmax, double* pack,
-                           const cqrrpt_info_t* info, hipStream_t s, const int* enable) {
-  return launch_trsm_impl<double, double, double>(B, ldb, gather, X, ldx, R, ldr, m, kdev, kmax,
-                                                  pack, info, enable, s);
+size_t trsm_dv_pack_bytes(int kmax) {
+  const int np = (kmax + kPW - 1) / kPW;
+  return (size_t)trsm_panel_offset(np) * 8;
+}
+
+hipError_t launch_trsm_dv_f64(const double* B, int64_t ldb, const int64_t* gather, double* X,
+                              int64_t ldx, const double* R, int64_t ldr, int64_t m,
+                              const int64_t* kdev, int kmax, double* inv, double* rpack,
+                              size_t rpack_bytes, const cqrrpt_info_t* info, hipStream_t s,
+                              const int* enable) {
+  if (kmax < 1 || rpack_bytes < trsm_dv_pack_bytes(kmax)) return hipErrorInvalidValue;
+  const int ntiles = (kmax + kInvTile - 1) / kInvTile;
+  hipLaunchKernelGGL(trsm_inv_kernel, dim3((unsigned)((ntiles + 3) / 4)), dim3(64), 0, s, R, ldr,
+                     kdev, ntiles, inv, info, enable);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int np = (kmax + kPW - 1) / kPW;
+  hipLaunchKernelGGL(trsm_rpack_kernel,
+                     dim3(kTStepVals / kThreads, (unsigned)(kTSteps * np * (np + 1) / 2)),
+                     dim3(kThreads), 0, s, R, ldr, kdev, np, rpack, info, enable);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t grid = (m + kTRT - 1) / kTRT;
+  hipLaunchKernelGGL(trsm_dv_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, B, ldb, gather, X,
+                     ldx, rpack, m, kdev, inv, info, enable);
+  return hipGetLastError();
 }
 
 hipError_t launch_trsm_mixed(const double* B, int64_t ldb, const int64_t* gather, float* X,
