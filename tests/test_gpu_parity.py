@@ -199,6 +199,11 @@ CASES = [
     ("nnz1-gamma1", 4000, 64, 64, 1, "log", 1e3, 1e-14),
     ("wide-16-blocks", 20000, 1024, 1280, 8, "log", 1e8, 1e-14),
     ("wide-ragged", 12001, 700, 875, 4, "log", 1e6, 1e-14),
+    # Edges of the direct-load solve and Q product: a last panel of one
+    # column (k = 129), fewer rows than one 128-row workgroup, m just above d.
+    ("one-column-panel", 3000, 129, 162, 4, "log", 1e5, 1e-14),
+    ("rows-below-tile", 90, 40, 50, 4, "log", 1e3, 1e-14),
+    ("m-just-above-d", 170, 128, 160, 4, "log", 1e4, 1e-14),
 ]
 
 
