@@ -547,9 +547,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the factorization would shard by row blocks with two all-reduces, "
-              "as DESIGN.md describes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the factorization would shard by row blocks, with one all-reduce "
+              "of the sketch and one of the Gram).", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2311_08316_amd as P

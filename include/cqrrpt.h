@@ -42,7 +42,7 @@ extern "C" {
 #define CQRRPT_EHIP          3  /* a HIP runtime call failed                                 */
 #define CQRRPT_EWORKSPACE    4  /* workspace smaller than cqrrpt_workspace_bytes()           */
 #define CQRRPT_EBARRIER      5  /* a persistent kernel's grid barrier timed out              */
-#define CQRRPT_ELIMIT        6  /* size beyond what this build supports (see limits below)   */
+#define CQRRPT_ELIMIT        6  /* size beyond what the library supports (see limits below) */
 
 /* Precision modes (Sec. 3, Theorem "simple stability": the preconditioning
  * solve may run at a larger unit roundoff than the other steps).
@@ -96,7 +96,7 @@ typedef struct {
                                 G2 = Q^T Q in FP64); 0 when no estimate was formed         */
 } cqrrpt_info_t;
 
-/* Limits of this build: n <= 8192, d <= 16384, 1 <= nnz <= 32. */
+/* Limits of the library: n <= 8192, d <= 16384, 1 <= nnz <= 32. */
 
 /* ------------------------------------------------------------------------
  * Sketching operator (Sec. 2.3.1, SASO)

@@ -35,7 +35,7 @@ the dense Gaussian and SRHT operators of Sec. 2.3.1 (``cqrrpt_dense``); and
 HQRRP, the randomized block-pivoted QR of Sec. 5.2.2, in place of GEQP3 on
 the sketch (``hqrrp``, ``cqrrpt_hqrrp``).
 
-Readings where the paper is silent (each is listed in the design doc as well):
+Readings where the paper is silent:
   * random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the seed,
     one counter stream per column of S; Floyd's subset sampler (Bentley and
     Floyd, CACM 1987) for the distinct rows; Lemire's multiply-shift with

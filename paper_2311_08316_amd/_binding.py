@@ -26,7 +26,7 @@ CQRRPT_MIXED_FP32_CHOLQR2 = 3
 STATUS = {
     0: "ok", 1: "non-finite input", 2: "device-memory budget exceeded",
     3: "HIP runtime error", 4: "workspace too small", 5: "grid barrier timed out",
-    6: "size beyond this build's limits",
+    6: "size beyond the library's limits",
 }
 
 

@@ -217,7 +217,7 @@ const char* cqrrpt_status_string(int code) {
     case CQRRPT_EHIP: return "HIP runtime error";
     case CQRRPT_EWORKSPACE: return "workspace too small";
     case CQRRPT_EBARRIER: return "grid barrier timed out";
-    case CQRRPT_ELIMIT: return "size beyond this build's limits";
+    case CQRRPT_ELIMIT: return "size beyond the library's limits";
     default: return code < 0 ? "invalid argument" : "unknown status";
   }
 }
