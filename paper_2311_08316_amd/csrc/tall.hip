@@ -362,13 +362,13 @@ trsm_rows_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gathe
 // registers and no LDS or barrier. The same row ownership as above (a wave
 // owns 32 whole rows of each 128-column panel) makes the waves independent:
 // the K loop reads the wave's own solved columns of X and a packed copy of R
-// (32-deep steps, two register stages), and the diagonal phase reads its
+// (kTKS-deep steps, two register stages), and the diagonal phase reads its
 // strips R[tile t, panel] from the same packed copy, so nothing is shared
 // through LDS. The order of every accumulation is the one of the LDS-staged
 // kernel, so the results are the same bits.
 //
 // Packed R: panel p holds K rows 0 .. 128 p + 127 in steps t of kTKS rows;
-// per step, load j (8 kTKS / 8) and lane, two values: value (j, lane, e) is
+// per step, load j (kTKS of them) and lane, two values: value (j, lane, e) is
 // R[kTKS t + 4 s + lq, 128 p + 16 b + l16] with b = j / (kTKS / 8) and s =
 // 2 (j % (kTKS / 8)) + e, stored when row <= column < k, else zero.
 // ---------------------------------------------------------------------------
@@ -425,7 +425,7 @@ trsm_dv_kernel(const double* B, int64_t ldb, const int64_t* __restrict__ gather,
     rowc[a] = rowl[a] < m ? rowl[a] : m - 1;
   }
   struct Stage {
-    double xv[2][kTKS / 4];  // X[rowc[a], 32 t + 4 s + lq]
+    double xv[2][kTKS / 4];  // X[rowc[a], kTKS t + 4 s + lq]
     d2_t rv[8 * kTPairs];    // packed R of the step
   };
   for (int c0 = 0; c0 < k; c0 += kPW) {
