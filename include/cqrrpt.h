@@ -335,7 +335,7 @@ int cqrrpt_factor_hqrrp_ex(const double* A, int64_t lda, int64_t m, int64_t n, i
  * CQRRPT_EWORKSPACE, launching nothing, when cqrrpt_workspace_bytes(m, n, d,
  * nnz, mode) exceeds that size (the workspace is dominated by the Gram's
  * split partial sums, about 8 n^2 bytes per split: 30000 x 384 in FP64
- * needs about 34 MiB, 131072 x 1024 about 355 MiB; the mixed modes add
+ * needs about 34 MiB, 131072 x 1024 about 334 MiB; the mixed modes add
  * 4 m n bytes for the FP32 M_pre). Every call on
  * one device shares that device's array: calls that overlap on one device
  * (different streams or threads without ordering between them) race and
